@@ -1,0 +1,151 @@
+"""Parameter initialisation for LDBP (Sec. IV-C): step sizes, half-step merging,
+least-squares filter taps and per-step Kerr coefficients.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Log step sizes.  The paper uses the logarithmic heuristic of its reference
+[Zhang2013c, Eq. (2)] with adjusting factor 0.4 but does not print the formula.
+Reading: every step carries the same integral of exp(-alpha' z), alpha' = 0.4
+alpha, so that short steps sit where the power is high (span start):
+    z_j = -ln(1 - (j/N)(1 - e^{-alpha' L_sp})) / alpha',   j = 0..N,
+    delta_j = z_j - z_{j-1}  (propagation order).
+This reproduces Example 1 (100 km, 2 steps: 29.6 / 70.4 km).
+
+Half-step merging (Sec. IV-C, symmetric SSM): delta'_1 = delta_1/2,
+delta'_i = (delta_{i-1} + delta_i)/2, delta'_{M+1} = delta_M/2, with the deltas
+listed in the order backpropagation visits them.
+
+Least-squares taps (Sec. IV-C): minimise ||B h - d||^2 with d_i = e^{j xi w_i^2},
+xi = -beta2 delta' f_s^2 / 2, w_i = 2 pi i / N for i = -N/2..N/2 and B the
+(N+1) x T DFT matrix B_{i,k} = e^{-j k w_i} (centred DTFT of the taps).  The
+constrained in-band variant the paper cites [Sheikh2016] is not reproduced
+(its definition is not in the paper); the full-band fit is used, which on the
+N-point grid is exactly the truncated inverse DFT of the response.
+
+Kerr coefficients: a DBP step that undoes forward step delta starting at span
+position z_a uses c = -kerr_scale * gamma * L_eff(delta) * e^{-alpha z_a}: the
+LDBP filters have unit gain, so the signal keeps the launch-power level and the
+span's power profile is carried by c instead.
+
+Pins (tests/test_oracle_design.py): Example 1 step sizes and merged lengths and
+the identical filters h^(2..4); least squares on the N-point grid equals the
+truncated inverse DFT (Parseval); symmetric taps for the even response; the
+initialised LDBP with T = n taps reproduces FFT-DBP; T_cd arithmetic (Sec. V-B, V-F).
+"""
+from __future__ import annotations
+
+import math
+from typing import Sequence
+
+import numpy as np
+
+from . import units
+
+
+def log_steps(span_len: float, nstep: int, alpha: float, factor: float = 0.4) -> list[float]:
+    """Logarithmic step sizes of one span, propagation order (reading of Sec. IV-C)."""
+    a = factor * alpha
+    if a == 0.0 or nstep == 1:
+        return [span_len / nstep] * nstep
+    z = [-math.log(1.0 - (j / nstep) * (1.0 - math.exp(-a * span_len))) / a for j in range(nstep + 1)]
+    z[-1] = span_len
+    return [z[j + 1] - z[j] for j in range(nstep)]
+
+
+def merge_half_steps(deltas: Sequence[float]) -> list[float]:
+    """Combine adjacent half-steps of the symmetric SSM (Sec. IV-C): M steps -> M+1 lengths."""
+    d = list(deltas)
+    out = [d[0] / 2.0]
+    for i in range(1, len(d)):
+        out.append((d[i - 1] + d[i]) / 2.0)
+    out.append(d[-1] / 2.0)
+    return out
+
+
+def xi_of(delta: float, beta2: float, fs: float) -> float:
+    """xi = -beta2 delta f_s^2 / 2 (Sec. IV-C, Table I)."""
+    return -beta2 * delta * fs * fs / 2.0
+
+
+def ls_taps(xi: float, T: int, N: int = 4096) -> np.ndarray:
+    """Least-squares fit of sum_k h_k e^{-j k w} to e^{j xi w^2} on the paper's (N+1)-point grid."""
+    assert T % 2 == 1
+    K = (T - 1) // 2
+    i = np.arange(-N // 2, N // 2 + 1)
+    w = 2.0 * np.pi * i / N
+    k = np.arange(-K, K + 1)
+    B = np.exp(-1j * np.outer(w, k))
+    d = np.exp(1j * xi * w * w)
+    h, *_ = np.linalg.lstsq(B, d, rcond=None)
+    return h
+
+
+def truncated_idft_taps(xi: float, T: int, N: int = 4096) -> np.ndarray:
+    """h_k = (1/N) sum_m e^{j xi w_m^2} e^{j k w_m}, w_m = 2 pi m / N, m = -N/2..N/2-1, k = -K..K."""
+    K = (T - 1) // 2
+    m = np.arange(-N // 2, N // 2)
+    w = 2.0 * np.pi * m / N
+    d = np.exp(1j * xi * w * w)
+    k = np.arange(-K, K + 1)
+    return (np.exp(1j * np.outer(k, w)) @ d) / N
+
+
+def dbp_step_plan(span_len: float, nspan: int, steps_per_span: Sequence[float]):
+    """Backpropagation order of (delta, z_start) pairs: spans last to first, steps last to first.
+
+    ``steps_per_span`` lists one span's step lengths in propagation order; z_start
+    is the position within the span where that forward step begins.
+    """
+    starts = np.concatenate([[0.0], np.cumsum(steps_per_span)[:-1]])
+    plan = []
+    for _ in range(nspan):
+        for j in reversed(range(len(steps_per_span))):
+            plan.append((float(steps_per_span[j]), float(starts[j])))
+    return plan
+
+
+def kerr_coef(delta: float, z_start: float, alpha: float, gamma: float, kerr_scale: float = 1.0) -> float:
+    """c = -kerr_scale gamma L_eff(delta) e^{-alpha z_start} (DBP step for a unit-gain model)."""
+    return -kerr_scale * gamma * units.l_eff(delta, alpha) * math.exp(-alpha * z_start)
+
+
+def init_asymmetric(span_len: float, nspan: int, steps_per_span: Sequence[float], T, fs: float,
+                    alpha: float, beta2: float, gamma: float, kerr_scale: float = 1.0,
+                    method: str = "ls", N: int = 4096):
+    """LDBP based on the asymmetric SSM, l = M (Sec. IV-C): per-step LS taps and Kerr coefficients.
+
+    ``T`` is an int or a per-layer sequence of odd tap counts.  Returns (taps, c).
+    """
+    plan = dbp_step_plan(span_len, nspan, steps_per_span)
+    L = len(plan)
+    Ts = [int(T)] * L if np.isscalar(T) else [int(t) for t in T]
+    taps, c = [], np.zeros(L)
+    for i, (d, z0) in enumerate(plan):
+        xi = xi_of(d, beta2, fs)
+        if method == "ls":
+            taps.append(ls_taps(xi, Ts[i], N))
+        elif method == "truncate":
+            taps.append(truncated_idft_taps(xi, Ts[i], N))
+        elif method == "unit":
+            h = np.zeros(Ts[i], dtype=np.complex128)
+            h[(Ts[i] - 1) // 2] = 1.0
+            taps.append(h)
+        else:
+            raise ValueError(method)
+        c[i] = kerr_coef(d, z0, alpha, gamma, kerr_scale)
+    return taps, c
+
+
+def init_symmetric(span_len: float, nspan: int, steps_per_span: Sequence[float], T, fs: float,
+                   alpha: float, beta2: float, gamma: float, kerr_scale: float = 1.0, N: int = 4096):
+    """LDBP based on the symmetric SSM, l = M + 1 with a final linear half-step (Sec. III-C, IV-C)."""
+    plan = dbp_step_plan(span_len, nspan, steps_per_span)
+    deltas = [d for d, _ in plan]
+    merged = merge_half_steps(deltas)
+    L = len(merged)
+    Ts = [int(T)] * L if np.isscalar(T) else [int(t) for t in T]
+    taps = [ls_taps(xi_of(dm, beta2, fs), Ts[i], N) for i, dm in enumerate(merged)]
+    c = np.zeros(L)
+    for i, (d, z0) in enumerate(plan):
+        c[i] = kerr_coef(d, z0, alpha, gamma, kerr_scale)
+    return taps, c
