@@ -1,0 +1,113 @@
+/*
+ * ldbp.h -- C ABI of the MI355X (gfx950) learned-digital-backpropagation library.
+ *
+ * Method: Haeger & Pfister, "Physics-Based Deep Learning for Fiber-Optic
+ * Communication Systems" (arXiv 2010.14258).  The LDBP model is the
+ * parameterised split-step method of eq. (model), Sec. III-B:
+ *
+ *     f_theta(x) = sigma_l(A^(l) ... sigma_1(A^(1) x)),
+ *     A^(i): circular convolution with a centred FIR filter of odd length T_i = 2K_i + 1,
+ *            u_m = sum_{k=-K_i}^{K_i} h^(i)_k x_{(m-k) mod n},
+ *     sigma_i(u) = u exp(j c_i |u|^2)  (Remark 1; c_i real, sign included).
+ *
+ * Conventions shared by every entry point
+ *   - Complex numbers are interleaved (re, im) pairs of float (LDBP_C64) or
+ *     double (LDBP_C128).  Real parameters (c, step lengths) use the same real type.
+ *   - A batch of nwave waveforms of n samples each is stored as [nwave][n][npol]
+ *     complex, contiguous.  npol = 2 is dual polarisation (Manakov): both
+ *     polarisations share the taps and the phase c_i (|u_x|^2 + |u_y|^2) rotates
+ *     both.
+ *   - Tap storage: the l filters are packed back to back, filter i occupies
+ *     ntap[i] complex values starting at sum_{j<i} ntap[j], index K_i + k
+ *     holding h_k (k = -K_i..K_i).  Symmetry is a property of the values only.
+ *   - "host" pointers are read during the call only; "device" pointers must be
+ *     GPU memory of the current device, 16-byte aligned, and are owned by the
+ *     caller.  Inputs and outputs must not overlap unless stated.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
+ *     enqueue work and return without synchronising the host, except where noted.
+ *   - Every function returns LDBP_OK (0) or a negative ldbp_status.  Argument
+ *     checks run before any GPU work is enqueued; on failure nothing is
+ *     enqueued.  ldbp_last_error() returns a thread-local message for the last
+ *     failing call.
+ *   - The library allocates no device memory inside compute calls; scratch
+ *     memory is passed in as a workspace whose size the *_workspace_size
+ *     functions report.
+ */
+#ifndef LDBP_H
+#define LDBP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ldbp_status {
+  LDBP_OK = 0,
+  LDBP_EINVAL = -1,       /* invalid argument (size, null pointer, even tap count, alignment, overlap) */
+  LDBP_EWORKSPACE = -2,   /* workspace missing or smaller than required */
+  LDBP_EUNSUPPORTED = -3, /* valid request the library does not implement (e.g. npol > 2) */
+  LDBP_EHIP = -4          /* a HIP runtime call failed; see ldbp_last_error() */
+};
+
+enum ldbp_dtype { LDBP_C64 = 0, LDBP_C128 = 1 };
+
+#define LDBP_MAX_TAPS 63 /* largest odd filter length per step */
+#define LDBP_MAX_STEPS_PER_PASS 64
+
+/* Execution plan of the time-blocked kernels.  Zero fields mean "choose".
+ *   steps_per_pass  S: number of consecutive FIR+Kerr steps fused in one pass
+ *                   (the signal stays in LDS between them; a halo of sum K over
+ *                   the S steps is recomputed at each tile edge).
+ *   chunks          LDS work size in units of the kernel's chunk (threads x outputs
+ *                   per thread); the tile length is chunks*chunk - 2*halo.        */
+typedef struct ldbp_plan {
+  int32_t steps_per_pass;
+  int32_t chunks;
+  int32_t reserved0;
+  int32_t reserved1;
+} ldbp_plan;
+
+/* Library version string and status text. */
+const char* ldbp_version(void);
+const char* ldbp_status_string(int status);
+const char* ldbp_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * LDBP forward: y = f_theta(x) for every waveform of the batch (eq. model, Sec. III-B;
+ * nonlinear scaling of Remark 1; Manakov phase for npol = 2).
+ *
+ *   dtype        LDBP_C64 or LDBP_C128
+ *   npol         1 or 2
+ *   nwave, n     batch size (>= 1) and samples per waveform (>= 1); circular per waveform
+ *   nstep        l >= 1
+ *   ntap         host [nstep], odd, 1 <= ntap[i] <= LDBP_MAX_TAPS; any value is
+ *                allowed relative to n (wrap-around is part of the definition)
+ *   taps         device [sum ntap] complex
+ *   c            device [nstep] real
+ *   x            device [nwave][n][npol] complex, input
+ *   y            device [nwave][n][npol] complex, output; must not overlap x
+ *   ckpt         device [ceil(nstep/ckpt_every) - 1][nwave][n][npol] complex or NULL.
+ *                When given, the forward runs blocks of ckpt_every steps and
+ *                writes the input of block b (b >= 1) to slot b-1; ldbp_backward
+ *                recomputes from these instead of storing every step.
+ *   ckpt_every   steps per checkpoint block (1..LDBP_MAX_STEPS_PER_PASS) when ckpt != NULL
+ *   plan         host, may be NULL (library default); ignored for S when ckpt != NULL
+ *   ws           device workspace of at least ldbp_forward_workspace_size() bytes (may be
+ *                NULL when that size is 0)
+ * -------------------------------------------------------------------------*/
+int ldbp_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
+                                int32_t nstep, const int32_t* ntap, const void* ckpt,
+                                int32_t ckpt_every, const ldbp_plan* plan, size_t* bytes);
+
+int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
+                 int32_t nstep, const int32_t* ntap, const void* taps, const void* c,
+                 const void* x, void* y, void* ckpt, int32_t ckpt_every,
+                 const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDBP_H */

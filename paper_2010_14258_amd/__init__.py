@@ -1,0 +1,9 @@
+"""MI355X-native learned digital backpropagation (Haeger & Pfister, arXiv 2010.14258).
+
+The compute path lives in the gfx950 HIP library ``libldbp.so`` (C ABI in
+``include/ldbp.h``); this package is its Python binding.
+"""
+from . import _native  # noqa: F401
+from .ldbp import ldbp_forward, ldbp_forward_workspace_size  # noqa: F401
+
+__all__ = ["ldbp_forward", "ldbp_forward_workspace_size"]

@@ -1,0 +1,164 @@
+// C ABI of the LDBP forward (and, later, backward): validation, planning, pass sequencing.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "ldbp_kernels.h"
+
+namespace ldbp {
+
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+struct ModelArgs {
+  int32_t dtype, npol;
+  int64_t nwave, n;
+  int32_t nstep;
+  const int32_t* ntap;
+};
+
+static int check_model(const ModelArgs& m) {
+  if (m.dtype != LDBP_C64 && m.dtype != LDBP_C128) return fail(LDBP_EINVAL, "dtype %d is not LDBP_C64/LDBP_C128", m.dtype);
+  if (m.npol != 1 && m.npol != 2) return fail(LDBP_EUNSUPPORTED, "npol %d not supported (1 or 2)", m.npol);
+  if (m.nwave < 1) return fail(LDBP_EINVAL, "nwave %lld < 1", (long long)m.nwave);
+  if (m.n < 1 || m.n > (1LL << 30)) return fail(LDBP_EINVAL, "n %lld outside [1, 2^30]", (long long)m.n);
+  if (m.nstep < 1) return fail(LDBP_EINVAL, "nstep %d < 1", m.nstep);
+  if (!m.ntap) return fail(LDBP_EINVAL, "ntap is NULL");
+  for (int i = 0; i < m.nstep; ++i) {
+    const int t = m.ntap[i];
+    if (t < 1 || t > LDBP_MAX_TAPS || (t % 2) == 0)
+      return fail(LDBP_EINVAL, "ntap[%d] = %d must be odd and in [1, %d]", i, t, LDBP_MAX_TAPS);
+  }
+  return LDBP_OK;
+}
+
+static int max_chunks(int dtype, int npol) {
+  int c = 1;
+  while (fwd_lds_bytes(dtype, npol, c + 1) <= kMaxLdsBytes) ++c;
+  return c;
+}
+
+// Splits the l steps into passes.  With a checkpoint interval the passes are
+// exactly the checkpoint blocks; otherwise each pass takes steps while twice
+// its halo stays within 1/8 of the LDS work size (or a fixed S from the plan).
+struct PassPlan {
+  std::vector<PassTable> passes;
+  int chunks;
+};
+
+static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* plan, PassPlan& out) {
+  const int chunk = fwd_chunk(m.dtype, m.npol);
+  int chunks = (plan && plan->chunks > 0) ? plan->chunks : 1;
+  const int cmax = max_chunks(m.dtype, m.npol);
+  if (chunks > cmax) return fail(LDBP_EINVAL, "plan chunks %d exceeds the LDS limit (%d)", chunks, cmax);
+  const int fixed_s = ckpt_every > 0 ? ckpt_every : ((plan && plan->steps_per_pass > 0) ? plan->steps_per_pass : 0);
+  if (fixed_s > LDBP_MAX_STEPS_PER_PASS)
+    return fail(LDBP_EINVAL, "steps per pass %d exceeds %d", fixed_s, LDBP_MAX_STEPS_PER_PASS);
+
+  std::vector<int32_t> tapoff(m.nstep);
+  int32_t acc = 0;
+  for (int i = 0; i < m.nstep; ++i) {
+    tapoff[i] = acc;
+    acc += m.ntap[i];
+  }
+  out.passes.clear();
+  int s = 0;
+  int max_halo = 0;
+  while (s < m.nstep) {
+    PassTable pt{};
+    pt.c0 = s;
+    int h = 0;
+    int cnt = 0;
+    while (s + cnt < m.nstep && cnt < LDBP_MAX_STEPS_PER_PASS) {
+      const int k = (m.ntap[s + cnt] - 1) / 2;
+      if (fixed_s > 0) {
+        if (cnt >= fixed_s) break;
+      } else if (cnt > 0 && 2 * (h + k) * 8 > chunks * chunk) {
+        break;
+      }
+      pt.K[cnt] = k;
+      pt.tapoff[cnt] = tapoff[s + cnt];
+      h += k;
+      ++cnt;
+    }
+    pt.nstep = cnt;
+    pt.halo = h;
+    pt.wrap_general = (h >= m.n) ? 1 : 0;
+    max_halo = std::max(max_halo, h);
+    out.passes.push_back(pt);
+    s += cnt;
+  }
+  // Grow the LDS work size when a pass's halo leaves too little room for the tile.
+  while (chunks * chunk - 2 * max_halo < chunk / 2 && chunks < cmax) ++chunks;
+  if (chunks * chunk - 2 * max_halo < 1)
+    return fail(LDBP_EUNSUPPORTED, "halo %d of a %d-step pass does not fit in LDS; use fewer steps per pass",
+                max_halo, fixed_s);
+  out.chunks = chunks;
+  return LDBP_OK;
+}
+
+}  // namespace ldbp
+
+using namespace ldbp;
+
+extern "C" int ldbp_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                           const int32_t* ntap, const void* ckpt, int32_t ckpt_every,
+                                           const ldbp_plan* plan, size_t* bytes) {
+  if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
+  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+  int st = check_model(m);
+  if (st) return st;
+  if (ckpt) {
+    *bytes = 0;
+    return LDBP_OK;
+  }
+  PassPlan pp;
+  st = make_plan(m, 0, plan, pp);
+  if (st) return st;
+  *bytes = pp.passes.size() > 1 ? static_cast<size_t>(nwave) * n * npol * cx_size(dtype) : 0;
+  return LDBP_OK;
+}
+
+extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                            const int32_t* ntap, const void* taps, const void* c, const void* x, void* y,
+                            void* ckpt, int32_t ckpt_every, const ldbp_plan* plan, void* ws, size_t ws_bytes,
+                            void* stream) {
+  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+  int st = check_model(m);
+  if (st) return st;
+  if (!taps || !c || !x || !y) return fail(LDBP_EINVAL, "taps, c, x and y must be non-NULL");
+  if (!aligned16(taps) || !aligned16(x) || !aligned16(y)) return fail(LDBP_EINVAL, "taps, x and y must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(c) % real_size(dtype)) return fail(LDBP_EINVAL, "c is not aligned to its real type");
+  const size_t wave_bytes = static_cast<size_t>(nwave) * n * npol * cx_size(dtype);
+  if (overlaps(x, wave_bytes, y, wave_bytes)) return fail(LDBP_EINVAL, "x and y overlap");
+  if (ckpt) {
+    if (ckpt_every < 1 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
+      return fail(LDBP_EINVAL, "ckpt_every %d outside [1, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
+    if (!aligned16(ckpt)) return fail(LDBP_EINVAL, "ckpt must be 16-byte aligned");
+    const int64_t nslot = (nstep + ckpt_every - 1) / ckpt_every - 1;
+    if (nslot > 0 && (overlaps(ckpt, nslot * wave_bytes, x, wave_bytes) || overlaps(ckpt, nslot * wave_bytes, y, wave_bytes)))
+      return fail(LDBP_EINVAL, "ckpt overlaps x or y");
+  }
+  PassPlan pp;
+  st = make_plan(m, ckpt ? ckpt_every : 0, plan, pp);
+  if (st) return st;
+  const size_t np = pp.passes.size();
+  if (!ckpt && np > 1) {
+    if (!ws || ws_bytes < wave_bytes)
+      return fail(LDBP_EWORKSPACE, "workspace of %zu bytes required, %zu given", wave_bytes, ws ? ws_bytes : 0);
+    if (!aligned16(ws)) return fail(LDBP_EINVAL, "ws must be 16-byte aligned");
+    if (overlaps(ws, wave_bytes, x, wave_bytes) || overlaps(ws, wave_bytes, y, wave_bytes))
+      return fail(LDBP_EINVAL, "workspace overlaps x or y");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* in = x;
+  for (size_t i = 0; i < np; ++i) {
+    void* out;
+    if (i + 1 == np) out = y;
+    else if (ckpt) out = static_cast<char*>(ckpt) + i * wave_bytes;
+    else out = ((np - 1 - i) % 2 == 0) ? y : ws;
+    st = launch_fwd_pass(dtype, npol, in, out, nwave, static_cast<int32_t>(n), pp.chunks, pp.passes[i], taps, c, s);
+    if (st) return st;
+    in = out;
+  }
+  return LDBP_OK;
+}

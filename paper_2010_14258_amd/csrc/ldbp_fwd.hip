@@ -1,0 +1,223 @@
+// LDBP forward: time-blocked fused FIR + Kerr passes (eq. model, Sec. III-B).
+//
+// One pass applies S consecutive steps u = h * x (circular, centred, T = 2K+1
+// taps), y = u exp(j c |u|^2) to a tile of L output samples.  The workgroup
+// loads the tile plus a halo of H = sum K over the S steps (wrapping around the
+// circular waveform), keeps the signal in LDS between steps (ping-pong buffers),
+// and writes only the L samples whose dependency cone was fully loaded.  After
+// step s the valid region has shrunk by K_s on each side.  Each thread
+// produces RB consecutive outputs from a register window of RB + 2K inputs.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "ldbp_kernels.h"
+
+namespace ldbp {
+
+template <typename R, int NPOL, int RB, int THREADS, int K>
+__device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out,
+                                               int lo, int hi, const cx_t<R>* __restrict__ h, R coef) {
+  using V = cx_t<R>;
+  constexpr int W = RB + 2 * K;
+  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
+    V win[W][NPOL];
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) win[j][p] = in[(base - K + j) * NPOL + p];
+    V acc[RB][NPOL];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
+#pragma unroll
+    for (int k = -K; k <= K; ++k) {
+      const V hk = h[K + k];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) cmac(acc[r][p], hk, win[r - k + K][p]);  // x_{m-k}, m = base + r
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      R pw = 0;
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) pw += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
+      R s, co;
+      phase_sincos(coef, pw, s, co);
+      if (base + r < hi) {
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+          V o;
+          o.x = acc[r][p].x * co - acc[r][p].y * s;
+          o.y = acc[r][p].x * s + acc[r][p].y * co;
+          out[(base + r) * NPOL + p] = o;
+        }
+      }
+    }
+  }
+}
+
+// Filters longer than the unrolled range: taps streamed, inputs read from LDS per tap.
+template <typename R, int NPOL, int RB, int THREADS>
+__device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out,
+                                                 int lo, int hi, int K, const cx_t<R>* __restrict__ h, R coef) {
+  using V = cx_t<R>;
+  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
+    V acc[RB][NPOL];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
+    for (int k = -K; k <= K; ++k) {
+      const V hk = h[K + k];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) cmac(acc[r][p], hk, in[(base + r - k) * NPOL + p]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      R pw = 0;
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) pw += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
+      R s, co;
+      phase_sincos(coef, pw, s, co);
+      if (base + r < hi) {
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+          V o;
+          o.x = acc[r][p].x * co - acc[r][p].y * s;
+          o.y = acc[r][p].x * s + acc[r][p].y * co;
+          out[(base + r) * NPOL + p] = o;
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int NPOL, int RB, int THREADS>
+__device__ __forceinline__ void fir_kerr_dispatch(const cx_t<R>* in, cx_t<R>* out, int lo, int hi, int K,
+                                                  const cx_t<R>* h, R coef) {
+  switch (K) {
+#define LDBP_FWD_CASE(k) \
+  case k: fir_kerr_fixed<R, NPOL, RB, THREADS, k>(in, out, lo, hi, h, coef); break;
+    LDBP_FWD_CASE(0) LDBP_FWD_CASE(1) LDBP_FWD_CASE(2) LDBP_FWD_CASE(3)
+    LDBP_FWD_CASE(4) LDBP_FWD_CASE(5) LDBP_FWD_CASE(6) LDBP_FWD_CASE(7)
+    LDBP_FWD_CASE(8) LDBP_FWD_CASE(9) LDBP_FWD_CASE(10) LDBP_FWD_CASE(11)
+    LDBP_FWD_CASE(12)
+#undef LDBP_FWD_CASE
+    default: fir_kerr_generic<R, NPOL, RB, THREADS>(in, out, lo, hi, K, h, coef); break;
+  }
+}
+
+// Loads samples [t0 - H, t0 + Lw + H) of one waveform (circularly) into LDS.
+template <typename R, int NPOL, int THREADS>
+__device__ __forceinline__ void load_tile(const cx_t<R>* __restrict__ xw, cx_t<R>* __restrict__ buf, int n,
+                                          int t0, int H, int W0, int wrap_general) {
+  for (int j = threadIdx.x; j < W0; j += THREADS) {
+    int g = t0 - H + j;
+    if (wrap_general) {
+      g %= n;
+      if (g < 0) g += n;
+    } else {
+      if (g < 0) g += n;
+      else if (g >= n) g -= n;
+    }
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) buf[j * NPOL + p] = xw[static_cast<int64_t>(g) * NPOL + p];
+  }
+}
+
+template <typename R, int NPOL, int RB, int THREADS>
+__global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __restrict__ x, cx_t<R>* __restrict__ y,
+                                                           int32_t n, int32_t tile_len, int32_t ntiles,
+                                                           int32_t work, const cx_t<R>* __restrict__ taps,
+                                                           const R* __restrict__ c, PassTable pt) {
+  using V = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* b0 = reinterpret_cast<V*>(smem);
+  V* b1 = b0 + static_cast<size_t>(work + RB) * NPOL;
+
+  const int tile = static_cast<int>(blockIdx.x % static_cast<uint32_t>(ntiles));
+  const int64_t wave = blockIdx.x / static_cast<uint32_t>(ntiles);
+  const int t0 = tile * tile_len;
+  const int Lw = min(tile_len, n - t0);
+  const int H = pt.halo;
+  const int W0 = Lw + 2 * H;
+  const V* xw = x + wave * static_cast<int64_t>(n) * NPOL;
+  V* yw = y + wave * static_cast<int64_t>(n) * NPOL;
+
+  load_tile<R, NPOL, THREADS>(xw, b0, n, t0, H, W0, pt.wrap_general);
+  __syncthreads();
+
+  int lo = 0;
+  for (int s = 0; s < pt.nstep; ++s) {
+    const int K = pt.K[s];
+    lo += K;
+    const R coef = c[pt.c0 + s] * phase_coef_scale<R>();
+    fir_kerr_dispatch<R, NPOL, RB, THREADS>(b0, b1, lo, W0 - lo, K, taps + pt.tapoff[s], coef);
+    __syncthreads();
+    V* t = b0;
+    b0 = b1;
+    b1 = t;
+  }
+
+  for (int j = threadIdx.x; j < Lw; j += THREADS) {
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) yw[static_cast<int64_t>(t0 + j) * NPOL + p] = b0[(H + j) * NPOL + p];
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+template <typename R, int NPOL> struct FwdCfg;
+template <> struct FwdCfg<float, 1> { static constexpr int RB = 8, THREADS = 256; };
+template <> struct FwdCfg<float, 2> { static constexpr int RB = 4, THREADS = 256; };
+template <> struct FwdCfg<double, 1> { static constexpr int RB = 4, THREADS = 256; };
+template <> struct FwdCfg<double, 2> { static constexpr int RB = 2, THREADS = 256; };
+
+int fwd_chunk(int dtype, int npol) {
+  if (dtype == LDBP_C64) return npol == 1 ? 8 * 256 : 4 * 256;
+  return npol == 1 ? 4 * 256 : 2 * 256;
+}
+
+size_t fwd_lds_bytes(int dtype, int npol, int chunks) {
+  const int rb = fwd_chunk(dtype, npol) / 256;
+  return 2 * static_cast<size_t>(chunks * fwd_chunk(dtype, npol) + rb) * npol * cx_size(dtype);
+}
+
+template <typename R, int NPOL>
+static int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                             const PassTable& pt, const void* taps, const void* c, hipStream_t stream) {
+  using Cfg = FwdCfg<R, NPOL>;
+  const int work = chunks * Cfg::RB * Cfg::THREADS;
+  const int tile_len = work - 2 * pt.halo;
+  if (tile_len < 1) return fail(LDBP_EINVAL, "pass halo %d too large for work size %d", pt.halo, work);
+  const int64_t ntiles = (n + tile_len - 1) / tile_len;
+  const int64_t nblocks = ntiles * nwave;
+  if (nblocks > 0x7fffffffLL) return fail(LDBP_EUNSUPPORTED, "grid too large (%lld blocks)", (long long)nblocks);
+  const size_t lds = 2 * static_cast<size_t>(work + Cfg::RB) * NPOL * sizeof(cx_t<R>);
+  auto kern = ldbp_fwd_kernel<R, NPOL, Cfg::RB, Cfg::THREADS>;
+  if (lds > 65536) LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(nblocks)), dim3(Cfg::THREADS), lds, stream,
+                     static_cast<const cx_t<R>*>(x), static_cast<cx_t<R>*>(y), n, tile_len,
+                     static_cast<int32_t>(ntiles), work, static_cast<const cx_t<R>*>(taps),
+                     static_cast<const R*>(c), pt);
+  LDBP_HIP_CHECK(hipGetLastError());
+  return LDBP_OK;
+}
+
+int launch_fwd_pass(int dtype, int npol, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                    const PassTable& pt, const void* taps, const void* c, hipStream_t stream) {
+  if (dtype == LDBP_C64)
+    return npol == 1 ? launch_fwd_pass_t<float, 1>(x, y, nwave, n, chunks, pt, taps, c, stream)
+                     : launch_fwd_pass_t<float, 2>(x, y, nwave, n, chunks, pt, taps, c, stream);
+  return npol == 1 ? launch_fwd_pass_t<double, 1>(x, y, nwave, n, chunks, pt, taps, c, stream)
+                   : launch_fwd_pass_t<double, 2>(x, y, nwave, n, chunks, pt, taps, c, stream);
+}
+
+}  // namespace ldbp

@@ -1,0 +1,29 @@
+// Internal launch interface between the C ABI (api.hip) and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/ldbp.h"
+
+namespace ldbp {
+
+// Steps fused in one time-blocked pass.  Passed to the kernels by value.
+struct PassTable {
+  int32_t nstep;         // steps in this pass
+  int32_t halo;          // H = sum of K over the pass
+  int32_t c0;            // index of the pass's first step in the global step list
+  int32_t wrap_general;  // 1 when H >= n, so tile loads need a full modulo
+  int32_t K[LDBP_MAX_STEPS_PER_PASS];       // half-lengths
+  int32_t tapoff[LDBP_MAX_STEPS_PER_PASS];  // offsets into the packed taps
+};
+
+// Forward pass kernel geometry.
+int fwd_chunk(int dtype, int npol);
+size_t fwd_lds_bytes(int dtype, int npol, int chunks);
+
+int launch_fwd_pass(int dtype, int npol, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                    const PassTable& pt, const void* taps, const void* c, hipStream_t stream);
+
+}  // namespace ldbp

