@@ -106,6 +106,38 @@ int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
                  const void* x, void* y, void* ckpt, int32_t ckpt_every,
                  const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * LDBP backward: gradients of a real loss L through y = f_theta(x).  The paper
+ * trains the model with standard tools (Sec. IV-B); this is the chain rule of
+ * eq. (model) step by step, with the convention G = dL/dRe + j dL/dIm:
+ *   Kerr step  q = Im(G_y conj(y)), dL/dc_i = sum q |u|^2, G_u = (G_y + 2 c_i q y) e^{-j c_i |u|^2}
+ *   FIR step   dL/dh_k = sum_m G_u,m conj(x_{m-k}), G_x,p = sum_k conj(h_k) G_u,(p+k)
+ * summed over waveforms and polarisations.  The forward is recomputed block by
+ * block (ckpt_every steps) from checkpoints, keeping each block's intermediate
+ * signals in LDS only.  Sums over samples are formed per tile and reduced in
+ * FP64 in a fixed order: results are deterministic.
+ *
+ *   (dtype .. c)  as for ldbp_forward
+ *   x            device [nwave][n][npol] complex: the forward input
+ *   ckpt         device checkpoints written by ldbp_forward with the same ckpt_every,
+ *                or NULL: the backward recomputes them into its workspace
+ *   ckpt_every   block length S (1..LDBP_MAX_STEPS_PER_PASS); 0 = library default
+ *                (only with ckpt == NULL).  Long blocks may not fit in LDS
+ *                (LDBP_EUNSUPPORTED).
+ *   gy           device [nwave][n][npol] complex: dL/dy
+ *   gx           device [nwave][n][npol] complex output dL/dx, or NULL when not needed
+ *   gtaps        device [sum ntap] complex output, overwritten
+ *   gc           device [nstep] real output, overwritten
+ *   ws           device workspace of ldbp_backward_workspace_size() bytes
+ * -------------------------------------------------------------------------*/
+int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                 const int32_t* ntap, const void* ckpt, int32_t ckpt_every, size_t* bytes);
+
+int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                  const int32_t* ntap, const void* taps, const void* c, const void* x,
+                  const void* ckpt, int32_t ckpt_every, const void* gy, void* gx, void* gtaps,
+                  void* gc, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

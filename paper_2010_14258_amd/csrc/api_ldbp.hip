@@ -162,3 +162,141 @@ extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
   }
   return LDBP_OK;
 }
+
+// ---------------------------------------------------------------- backward
+
+namespace ldbp {
+
+constexpr size_t kBwdLdsBudget = 64 * 1024;
+
+static size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+struct BwdLayout {
+  PassPlan blocks;   // checkpoint blocks (passes of exactly S steps)
+  int32_t S;
+  int32_t tile_len;
+  int64_t ntiles;    // total over the batch
+  int32_t ncols;     // sum T + l
+  int32_t ntaps;     // sum T
+  size_t off_ckpt, off_g0, off_g1, off_part, total;
+};
+
+static int default_bwd_S(const ModelArgs& m) { return std::min<int32_t>(m.nstep, 5); }
+
+static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_every, BwdLayout& L) {
+  L.S = ckpt_every > 0 ? ckpt_every : default_bwd_S(m);
+  int st = make_plan(m, L.S, nullptr, L.blocks);
+  if (st) return st;
+  // tile length: the largest multiple of 64 whose LDS footprint fits the budget for every block
+  size_t budget = kBwdLdsBudget;
+  int best = 0;
+  for (; budget <= kMaxLdsBytes && best == 0; budget += 32 * 1024) {
+    for (int Lw = 4096; Lw >= 64; Lw -= 64) {
+      bool ok = true;
+      for (const auto& pt : L.blocks.passes)
+        if (bwd_lds_bytes(m.dtype, m.npol, Lw, pt) > budget) { ok = false; break; }
+      if (ok) { best = Lw; break; }
+    }
+  }
+  if (best == 0)
+    return fail(LDBP_EUNSUPPORTED, "checkpoint blocks of %d steps do not fit in LDS for the backward; use fewer",
+                L.S);
+  L.tile_len = best;
+  L.ntiles = m.nwave * ((m.n + best - 1) / best);
+  L.ntaps = 0;
+  for (int i = 0; i < m.nstep; ++i) L.ntaps += m.ntap[i];
+  L.ncols = L.ntaps + m.nstep;
+  const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
+  const size_t nb = L.blocks.passes.size();
+  size_t off = 0;
+  L.off_ckpt = off;
+  if (!have_ckpt && nb > 1) off += align256((nb - 1) * wave_bytes);
+  L.off_g0 = off;
+  off += align256(wave_bytes);
+  L.off_g1 = off;
+  off += align256(wave_bytes);
+  L.off_part = off;
+  off += align256(static_cast<size_t>(L.ntiles) * L.ncols * sizeof(double) * 2);
+  L.total = off;
+  return LDBP_OK;
+}
+
+}  // namespace ldbp
+
+extern "C" int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                            const int32_t* ntap, const void* ckpt, int32_t ckpt_every,
+                                            size_t* bytes) {
+  if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
+  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+  int st = check_model(m);
+  if (st) return st;
+  if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
+    return fail(LDBP_EINVAL, "ckpt_every %d outside [0, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
+  if (ckpt && ckpt_every == 0) return fail(LDBP_EINVAL, "ckpt given without ckpt_every");
+  BwdLayout L;
+  st = make_bwd_layout(m, ckpt != nullptr, ckpt_every, L);
+  if (st) return st;
+  *bytes = L.total;
+  return LDBP_OK;
+}
+
+extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                             const int32_t* ntap, const void* taps, const void* c, const void* x, const void* ckpt,
+                             int32_t ckpt_every, const void* gy, void* gx, void* gtaps, void* gc, void* ws,
+                             size_t ws_bytes, void* stream) {
+  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+  int st = check_model(m);
+  if (st) return st;
+  if (!taps || !c || !x || !gy || !gtaps || !gc)
+    return fail(LDBP_EINVAL, "taps, c, x, gy, gtaps and gc must be non-NULL");
+  if (!aligned16(taps) || !aligned16(x) || !aligned16(gy) || !aligned16(gtaps) || (gx && !aligned16(gx)) ||
+      (ckpt && !aligned16(ckpt)))
+    return fail(LDBP_EINVAL, "complex arrays must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(c) % real_size(dtype) || reinterpret_cast<uintptr_t>(gc) % real_size(dtype))
+    return fail(LDBP_EINVAL, "c and gc must be aligned to their real type");
+  if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
+    return fail(LDBP_EINVAL, "ckpt_every %d outside [0, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
+  if (ckpt && ckpt_every == 0) return fail(LDBP_EINVAL, "ckpt given without ckpt_every");
+  const size_t wave_bytes = static_cast<size_t>(nwave) * n * npol * cx_size(dtype);
+  if (gx && (overlaps(gx, wave_bytes, gy, wave_bytes) || overlaps(gx, wave_bytes, x, wave_bytes)))
+    return fail(LDBP_EINVAL, "gx overlaps x or gy");
+  BwdLayout L;
+  st = make_bwd_layout(m, ckpt != nullptr, ckpt_every, L);
+  if (st) return st;
+  if (!ws || ws_bytes < L.total)
+    return fail(LDBP_EWORKSPACE, "workspace of %zu bytes required, %zu given", L.total, ws ? ws_bytes : 0);
+  if (!aligned16(ws)) return fail(LDBP_EINVAL, "ws must be 16-byte aligned");
+  if (overlaps(ws, L.total, x, wave_bytes) || overlaps(ws, L.total, gy, wave_bytes) ||
+      (gx && overlaps(ws, L.total, gx, wave_bytes)))
+    return fail(LDBP_EINVAL, "workspace overlaps an argument");
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* wsb = static_cast<char*>(ws);
+  void* g0 = wsb + L.off_g0;
+  void* g1 = wsb + L.off_g1;
+  void* part = wsb + L.off_part;
+  const size_t nb = L.blocks.passes.size();
+  const char* ck = static_cast<const char*>(ckpt);
+  if (!ckpt && nb > 1) {
+    // recompute the block inputs with the forward (its output goes to a scratch buffer)
+    ck = wsb + L.off_ckpt;
+    const void* in = x;
+    for (size_t i = 0; i + 1 < nb; ++i) {
+      void* out = wsb + L.off_ckpt + i * wave_bytes;
+      st = launch_fwd_pass(dtype, npol, in, out, nwave, static_cast<int32_t>(n), L.blocks.chunks,
+                           L.blocks.passes[i], taps, c, s);
+      if (st) return st;
+      in = out;
+    }
+  }
+  const void* gcur = gy;
+  for (size_t bi = nb; bi-- > 0;) {
+    const void* xb = bi == 0 ? x : static_cast<const void*>(ck + (bi - 1) * wave_bytes);
+    void* gin = (bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0);
+    st = launch_bwd_block(dtype, npol, xb, gcur, gin, nwave, static_cast<int32_t>(n), L.tile_len,
+                          L.blocks.passes[bi], taps, c, part, L.ncols, L.ntaps, s);
+    if (st) return st;
+    gcur = gin;
+  }
+  return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s);
+}

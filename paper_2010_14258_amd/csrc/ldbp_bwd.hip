@@ -1,0 +1,414 @@
+// LDBP backward: adjoint of the time-blocked forward, recomputing from block checkpoints.
+//
+// The model (eq. model, Sec. III-B) is differentiated step by step; the paper
+// trains with standard tools, so this adjoint is the chain rule written out:
+//   Kerr  y = u e^{j phi}, phi = c P(u), P = |u|^2 (summed over polarisations):
+//         q = Im(G_y conj(y)),  dc += q P,  G_u = (G_y + 2 c q y) e^{-j phi}
+//         (using u = y e^{-j phi} and P(u) = P(y), so only y is kept)
+//   FIR   u_m = sum_k h_k x_{m-k}:
+//         dh_k += G_u,m conj(x_{m-k}),  G_x,p = sum_k conj(h_k) G_u,(p+k)
+// with G = dL/dRe + j dL/dIm.
+//
+// One workgroup handles a tile of L block-input positions [t0, t0+L) of one
+// block of S steps (halo H = sum K):
+//   1. load the block input over [t0-2H, t0+L+2H) and recompute y_1..y_S in LDS,
+//      y_s kept over [t0-(2H-h_s), t0+L+(2H-h_s)), h_s = K_1 + ... + K_s;
+//   2. load the block-output gradient over [t0-H, t0+L+H);
+//   3. for s = S..1: Kerr adjoint over [t0-h_s, t0+L+h_s), FIR adjoint down to
+//      [t0-h_{s-1}, t0+L+h_{s-1}), tap and Kerr-coefficient gradients summed over
+//      the tile's own positions only (each position is owned by one tile);
+//   4. write the block-input gradient over [t0, t0+L) and the tile's partial
+//      sums (one FP64 value per tap and step) to a [tile][column] buffer that a
+//      second kernel reduces in a fixed order, so results are deterministic.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "ldbp_fir.h"
+#include "ldbp_kernels.h"
+
+namespace ldbp {
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// out[j] = sum_k conj(h_k) in[j+k] for j in [lo, hi); reads in[lo-K, hi+RB+K-2].
+template <typename R, int NPOL, int RB, int THREADS, int K>
+__device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
+                                              int hi, const cx_t<R>* __restrict__ h) {
+  using V = cx_t<R>;
+  constexpr int W = RB + 2 * K;
+  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
+    V win[W][NPOL];
+#pragma unroll
+    for (int j = 0; j < W; ++j)
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) win[j][p] = in[(base - K + j) * NPOL + p];
+    V acc[RB][NPOL];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
+#pragma unroll
+    for (int k = -K; k <= K; ++k) {
+      const V hk = h[K + k];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) cmac_conj(acc[r][p], hk, win[r + k + K][p]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (base + r < hi)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+  }
+}
+
+template <typename R, int NPOL, int RB, int THREADS>
+__device__ __forceinline__ void fir_adj_generic(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
+                                                int hi, int K, const cx_t<R>* __restrict__ h) {
+  using V = cx_t<R>;
+  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
+    V acc[RB][NPOL];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
+    for (int k = -K; k <= K; ++k) {
+      const V hk = h[K + k];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) cmac_conj(acc[r][p], hk, in[(base + r + k) * NPOL + p]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (base + r < hi)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+  }
+}
+
+// acc_k += g conj(y): the conjugate-linear product used by the tap gradient.
+template <typename V>
+__device__ __forceinline__ void cmac_yconj(V& acc, V g, V y) {
+  acc.x = fma(g.x, y.x, acc.x);
+  acc.x = fma(g.y, y.y, acc.x);
+  acc.y = fma(g.y, y.x, acc.y);
+  acc.y = fma(-g.x, y.y, acc.y);
+}
+
+// Tap gradient of one step: for each k, sum over owned j in [own_lo, own_lo+Lw) of
+// gu[j] conj(yprev[j + yshift - k]); per-wave sums land in red[wave * ldr + col0 + K + k].
+template <typename R, int NPOL, int RB2, int THREADS, int K>
+__device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, int own_lo, int Lw,
+                                              const cx_t<R>* __restrict__ yprev, int yshift,
+                                              double2* __restrict__ red, int ldr, int col0) {
+  using V = cx_t<R>;
+  constexpr int T = 2 * K + 1;
+  constexpr int W = RB2 + 2 * K;
+  V acc[T];
+#pragma unroll
+  for (int k = 0; k < T; ++k) acc[k] = V{0, 0};
+  const int own_hi = own_lo + Lw;
+  for (int jb = own_lo + static_cast<int>(threadIdx.x) * RB2; jb < own_hi; jb += THREADS * RB2) {
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) {
+      V win[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) win[j] = yprev[(jb + yshift - K + j) * NPOL + p];
+#pragma unroll
+      for (int r = 0; r < RB2; ++r) {
+        const V g = (jb + r < own_hi) ? gu[(jb + r) * NPOL + p] : V{0, 0};
+#pragma unroll
+        for (int k = -K; k <= K; ++k) cmac_yconj(acc[K + k], g, win[r - k + K]);
+      }
+    }
+  }
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < T; ++k) {
+    const R sx = wave_sum(acc[k].x);
+    const R sy = wave_sum(acc[k].y);
+    if (lane == 0) red[wv * ldr + col0 + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+  }
+}
+
+template <typename R, int NPOL, int RB2, int THREADS>
+__device__ __forceinline__ void tapgrad_generic(const cx_t<R>* __restrict__ gu, int own_lo, int Lw, int K,
+                                                const cx_t<R>* __restrict__ yprev, int yshift,
+                                                double2* __restrict__ red, int ldr, int col0) {
+  using V = cx_t<R>;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int own_hi = own_lo + Lw;
+  for (int k = -K; k <= K; ++k) {
+    V acc{0, 0};
+    for (int j = own_lo + static_cast<int>(threadIdx.x); j < own_hi; j += THREADS)
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) cmac_yconj(acc, gu[j * NPOL + p], yprev[(j + yshift - k) * NPOL + p]);
+    const R sx = wave_sum(acc.x);
+    const R sy = wave_sum(acc.y);
+    if (lane == 0) red[wv * ldr + col0 + K + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+  }
+}
+
+template <typename R, int NPOL, int RB, int RB2, int THREADS>
+__device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga, int lo, int hi, int K,
+                                                  const cx_t<R>* h, int own_lo, int Lw, const cx_t<R>* yprev,
+                                                  int yshift, double2* red, int ldr, int col0) {
+  switch (K) {
+#define LDBP_BWD_CASE(k)                                                                       \
+  case k:                                                                                      \
+    fir_adj_fixed<R, NPOL, RB, THREADS, k>(gb, ga, lo, hi, h);                                 \
+    tapgrad_fixed<R, NPOL, RB2, THREADS, k>(gb, own_lo, Lw, yprev, yshift, red, ldr, col0);    \
+    break;
+    LDBP_BWD_CASE(0) LDBP_BWD_CASE(1) LDBP_BWD_CASE(2) LDBP_BWD_CASE(3)
+    LDBP_BWD_CASE(4) LDBP_BWD_CASE(5) LDBP_BWD_CASE(6) LDBP_BWD_CASE(7)
+    LDBP_BWD_CASE(8) LDBP_BWD_CASE(9) LDBP_BWD_CASE(10) LDBP_BWD_CASE(11)
+    LDBP_BWD_CASE(12)
+#undef LDBP_BWD_CASE
+    default:
+      fir_adj_generic<R, NPOL, RB, THREADS>(gb, ga, lo, hi, K, h);
+      tapgrad_generic<R, NPOL, RB2, THREADS>(gb, own_lo, Lw, K, yprev, yshift, red, ldr, col0);
+      break;
+  }
+}
+
+// LDS footprint (in complex elements) of one tile of length Lw for a block with halo H and
+// cumulative halves h_1..h_S; mirrored exactly by bwd_lds_bytes() on the host.
+__host__ __device__ inline int bwd_y_width(int Lw, int H, int hs) { return Lw + 4 * H - 2 * hs; }
+
+template <typename R, int NPOL, int RB, int RB2, int THREADS>
+__global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
+    const cx_t<R>* __restrict__ xb, const cx_t<R>* __restrict__ gout, cx_t<R>* __restrict__ gin, int32_t n,
+    int32_t tile_len, int32_t ntiles, const cx_t<R>* __restrict__ taps, const R* __restrict__ c, PassTable pt,
+    int32_t pad, double2* __restrict__ part, int32_t ncols, int32_t ccol_base) {
+  using V = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NW = THREADS / 64;
+
+  const int tile = static_cast<int>(blockIdx.x % static_cast<uint32_t>(ntiles));
+  const int64_t wave = blockIdx.x / static_cast<uint32_t>(ntiles);
+  const int t0 = tile * tile_len;
+  const int Lw = min(tile_len, n - t0);
+  const int H = pt.halo;
+  const int S = pt.nstep;
+  const int ntap_blk = pt.tapoff[S - 1] + 2 * pt.K[S - 1] + 1 - pt.tapoff[0];
+  const int ldr = ntap_blk + S;
+
+  // LDS carve-up: red (FP64 partials) | Y_0 .. Y_S | GA | GB; Y_s has width bwd_y_width(Lw, H, h_s) + pad.
+  double2* red = reinterpret_cast<double2*>(smem);
+  V* Y0 = reinterpret_cast<V*>(smem + static_cast<size_t>(NW) * ldr * sizeof(double2));
+  size_t ytot = 0;
+  {
+    int h = 0;
+    for (int s = 0; s <= S; ++s) {
+      if (s > 0) h += pt.K[s - 1];
+      ytot += static_cast<size_t>(bwd_y_width(Lw, H, h) + pad) * NPOL;
+    }
+  }
+  V* GA = Y0 + ytot;
+  V* GB = GA + static_cast<size_t>(Lw + 2 * H + pad) * NPOL;
+  int hs;
+
+  const V* xw = xb + wave * static_cast<int64_t>(n) * NPOL;
+  const V* gw = gout + wave * static_cast<int64_t>(n) * NPOL;
+
+  // 1. block input and forward recompute
+  load_tile<R, NPOL, THREADS>(xw, Y0, n, t0, 2 * H, Lw + 4 * H, (2 * H >= n) ? 1 : 0);
+  __syncthreads();
+  hs = 0;
+  V* ycur = Y0;
+  for (int s = 1; s <= S; ++s) {
+    const int K = pt.K[s - 1];
+    V* ynext = ycur + static_cast<size_t>(bwd_y_width(Lw, H, hs) + pad) * NPOL;
+    hs += K;
+    const R coef = c[pt.c0 + s - 1] * phase_coef_scale<R>();
+    fir_kerr_dispatch<R, NPOL, RB, THREADS>(ycur + K * NPOL, ynext, 0, bwd_y_width(Lw, H, hs), K,
+                                            taps + pt.tapoff[s - 1], coef);
+    __syncthreads();
+    ycur = ynext;
+  }
+  // 2. block-output gradient
+  load_tile<R, NPOL, THREADS>(gw, GA, n, t0, H, Lw + 2 * H, (H >= n) ? 1 : 0);
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  // 3. reverse sweep
+  hs = H;
+  for (int s = S; s >= 1; --s) {
+    const int K = pt.K[s - 1];
+    const R cr = c[pt.c0 + s - 1];
+    const R coef = cr * phase_coef_scale<R>();
+    // Kerr adjoint over GA indices [H - h_s, H + Lw + h_s); Y_s index = i - H + (2H - h_s)
+    const int lo = H - hs, hi = H + Lw + hs, yoff = H - hs;
+    V* yprev = ycur - static_cast<size_t>(bwd_y_width(Lw, H, hs - K) + pad) * NPOL;
+    R accc = 0;
+    for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += THREADS) {
+      V yv[NPOL], gv[NPOL];
+      R pw = 0, q = 0;
+#pragma unroll
+      for (int pp = 0; pp < NPOL; ++pp) {
+        yv[pp] = ycur[(i + yoff) * NPOL + pp];
+        gv[pp] = GA[i * NPOL + pp];
+        pw += yv[pp].x * yv[pp].x + yv[pp].y * yv[pp].y;
+        q += gv[pp].y * yv[pp].x - gv[pp].x * yv[pp].y;
+      }
+      R sn, co;
+      phase_sincos(coef, pw, sn, co);
+      const R tq = 2 * cr * q;
+#pragma unroll
+      for (int pp = 0; pp < NPOL; ++pp) {
+        const R tx = gv[pp].x + tq * yv[pp].x;
+        const R ty = gv[pp].y + tq * yv[pp].y;
+        GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
+      }
+      if (i >= H && i < H + Lw) accc += q * pw;
+    }
+    accc = wave_sum(accc);
+    if (lane == 0) red[wv * ldr + ntap_blk + (s - 1)] = double2{static_cast<double>(accc), 0.0};
+    __syncthreads();
+    // FIR adjoint into GA over [H - h_{s-1}, H + Lw + h_{s-1}); tap gradient over the owned range
+    const int hprev = hs - K;
+    adj_step_dispatch<R, NPOL, RB, RB2, THREADS>(GB, GA, H - hprev, H + Lw + hprev, K, taps + pt.tapoff[s - 1], H,
+                                                 Lw, yprev, H - hprev, red, ldr,
+                                                 pt.tapoff[s - 1] - pt.tapoff[0]);
+    __syncthreads();
+    hs = hprev;
+    ycur = yprev;
+  }
+
+  // 4. block-input gradient and the tile's partial sums
+  if (gin) {
+    V* gi = gin + wave * static_cast<int64_t>(n) * NPOL;
+    for (int j = threadIdx.x; j < Lw; j += THREADS)
+#pragma unroll
+      for (int pp = 0; pp < NPOL; ++pp) gi[static_cast<int64_t>(t0 + j) * NPOL + pp] = GA[(H + j) * NPOL + pp];
+  }
+  double2* prow = part + static_cast<int64_t>(blockIdx.x) * ncols;
+  for (int col = threadIdx.x; col < ldr; col += THREADS) {
+    double sx = 0, sy = 0;
+    for (int w = 0; w < NW; ++w) {
+      sx += red[w * ldr + col].x;
+      sy += red[w * ldr + col].y;
+    }
+    const int g = col < ntap_blk ? pt.tapoff[0] + col : ccol_base + pt.c0 + (col - ntap_blk);
+    prow[g] = double2{sx, sy};
+  }
+}
+
+// Sums part[tile][col] over tiles in a fixed order; one workgroup per column.
+template <typename R>
+__global__ __launch_bounds__(256) void ldbp_grad_reduce(const double2* __restrict__ part, int64_t ntiles,
+                                                        int32_t ncols, int32_t ntaps, cx_t<R>* __restrict__ gtaps,
+                                                        R* __restrict__ gc) {
+  __shared__ double sx[256], sy[256];
+  const int col = blockIdx.x;
+  double ax = 0, ay = 0;
+  for (int64_t t = threadIdx.x; t < ntiles; t += 256) {
+    const double2 v = part[t * ncols + col];
+    ax += v.x;
+    ay += v.y;
+  }
+  sx[threadIdx.x] = ax;
+  sy[threadIdx.x] = ay;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (static_cast<int>(threadIdx.x) < off) {
+      sx[threadIdx.x] += sx[threadIdx.x + off];
+      sy[threadIdx.x] += sy[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (col < ntaps) gtaps[col] = cx_t<R>{static_cast<R>(sx[0]), static_cast<R>(sy[0])};
+    else gc[col - ntaps] = static_cast<R>(sx[0]);
+  }
+}
+
+// ---------------------------------------------------------------- host side
+
+template <typename R, int NPOL> struct BwdCfg;
+template <> struct BwdCfg<float, 1> { static constexpr int RB = 4, RB2 = 4, THREADS = 256; };
+template <> struct BwdCfg<float, 2> { static constexpr int RB = 2, RB2 = 2, THREADS = 256; };
+template <> struct BwdCfg<double, 1> { static constexpr int RB = 2, RB2 = 2, THREADS = 256; };
+template <> struct BwdCfg<double, 2> { static constexpr int RB = 1, RB2 = 1, THREADS = 256; };
+
+static int bwd_pad(int dtype, int npol) {
+  (void)npol;
+  return dtype == LDBP_C64 ? 8 : 4;
+}
+
+size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt) {
+  const int pad = bwd_pad(dtype, npol);
+  const int S = pt.nstep;
+  const int ntap_blk = pt.tapoff[S - 1] + 2 * pt.K[S - 1] + 1 - pt.tapoff[0];
+  size_t elems = 0;
+  int hs = 0;
+  for (int s = 0; s <= S; ++s) {
+    if (s > 0) hs += pt.K[s - 1];
+    elems += static_cast<size_t>(Lw + 4 * pt.halo - 2 * hs + pad);
+  }
+  elems += 2 * static_cast<size_t>(Lw + 2 * pt.halo + pad);
+  return static_cast<size_t>(4) * (ntap_blk + S) * sizeof(double2) + elems * npol * cx_size(dtype);
+}
+
+template <typename R, int NPOL>
+static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
+                              int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
+                              int32_t ncols, int32_t ccol_base, hipStream_t stream) {
+  using Cfg = BwdCfg<R, NPOL>;
+  const int64_t ntiles = (n + tile_len - 1) / tile_len;
+  const int64_t nblocks = ntiles * nwave;
+  if (nblocks > 0x7fffffffLL) return fail(LDBP_EUNSUPPORTED, "grid too large");
+  const size_t lds = bwd_lds_bytes(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL, tile_len, pt);
+  auto kern = ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS>;
+  if (lds > 65536)
+    LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(nblocks)), dim3(Cfg::THREADS), lds, stream,
+                     static_cast<const cx_t<R>*>(xb), static_cast<const cx_t<R>*>(gout), static_cast<cx_t<R>*>(gin),
+                     n, tile_len, static_cast<int32_t>(ntiles), static_cast<const cx_t<R>*>(taps),
+                     static_cast<const R*>(c), pt, bwd_pad(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL),
+                     static_cast<double2*>(part), ncols, ccol_base);
+  LDBP_HIP_CHECK(hipGetLastError());
+  return LDBP_OK;
+}
+
+int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
+                     int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
+                     int32_t ncols, int32_t ccol_base, hipStream_t stream) {
+  if (dtype == LDBP_C64)
+    return npol == 1 ? launch_bwd_block_t<float, 1>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
+                                                    ccol_base, stream)
+                     : launch_bwd_block_t<float, 2>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
+                                                    ccol_base, stream);
+  return npol == 1 ? launch_bwd_block_t<double, 1>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
+                                                   ccol_base, stream)
+                   : launch_bwd_block_t<double, 2>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
+                                                   ccol_base, stream);
+}
+
+int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,
+                       void* gc, hipStream_t stream) {
+  if (dtype == LDBP_C64)
+    hipLaunchKernelGGL(ldbp_grad_reduce<float>, dim3(ncols), dim3(256), 0, stream,
+                       static_cast<const double2*>(part), ntiles, ncols, ntaps, static_cast<float2*>(gtaps),
+                       static_cast<float*>(gc));
+  else
+    hipLaunchKernelGGL(ldbp_grad_reduce<double>, dim3(ncols), dim3(256), 0, stream,
+                       static_cast<const double2*>(part), ntiles, ncols, ntaps, static_cast<double2*>(gtaps),
+                       static_cast<double*>(gc));
+  LDBP_HIP_CHECK(hipGetLastError());
+  return LDBP_OK;
+}
+
+}  // namespace ldbp

@@ -106,3 +106,72 @@ def ldbp_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Seq
                           _ptr(ws), ws.numel() if ws is not None else 0, stream_handle(stream, x.device))
     N.check(st)
     return y
+
+
+def ldbp_backward_workspace_size(x: torch.Tensor, ntap: Sequence[int], npol: int = 1, ckpt=None,
+                                 ckpt_every: int = 0) -> int:
+    lib = N.load()
+    nwave, n = _shape(x, npol)
+    out = ctypes.c_size_t(0)
+    N.check(lib.ldbp_backward_workspace_size(_code(x), npol, nwave, n, len(ntap), N.i32_array(ntap), _ptr(ckpt),
+                                             int(ckpt_every), ctypes.byref(out)))
+    return int(out.value)
+
+
+def ldbp_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], gy: torch.Tensor,
+                  npol: int = 1, ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0, need_gx: bool = True,
+                  ws: Optional[torch.Tensor] = None, stream=None):
+    """Adjoint of ``ldbp_forward``: returns (gx or None, gtaps, gc) for dL/dy = gy (G = dL/dRe + j dL/dIm)."""
+    lib = N.load()
+    code = _code(x)
+    nwave, n = _shape(x, npol)
+    for name, t in (("x", x), ("gy", gy)):
+        _check_dev(name, t, x.dtype)
+    _check_dev("taps", taps, x.dtype)
+    _check_dev("c", c, _real_dtype(code))
+    if ckpt is not None:
+        _check_dev("ckpt", ckpt, x.dtype)
+    gx = torch.empty_like(x) if need_gx else None
+    gtaps = torch.empty_like(taps)
+    gc = torch.empty_like(c)
+    if ws is None:
+        need = ldbp_backward_workspace_size(x, ntap, npol, ckpt, ckpt_every)
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    st = lib.ldbp_backward(code, npol, nwave, n, len(ntap), N.i32_array(ntap), _ptr(taps), _ptr(c), _ptr(x),
+                           _ptr(ckpt), int(ckpt_every), _ptr(gy), _ptr(gx), _ptr(gtaps), _ptr(gc), _ptr(ws),
+                           ws.numel(), stream_handle(stream, x.device))
+    N.check(st)
+    return gx, gtaps, gc
+
+
+def num_checkpoints(nstep: int, ckpt_every: int) -> int:
+    """Checkpoint slots ldbp_forward writes for blocks of ``ckpt_every`` steps."""
+    return 0 if ckpt_every <= 0 else max(0, -(-nstep // ckpt_every) - 1)
+
+
+class LDBPFunction(torch.autograd.Function):
+    """y = f_theta(x) with the hand-written adjoint; checkpoints every ``ckpt_every`` steps.
+
+    apply(x, taps, c, ntap, npol, ckpt_every) -> y
+    """
+
+    @staticmethod
+    def forward(ctx, x, taps, c, ntap, npol=1, ckpt_every=5):
+        ntap = [int(t) for t in ntap]
+        S = max(1, min(int(ckpt_every), len(ntap)))
+        nslot = num_checkpoints(len(ntap), S)
+        ckpt = torch.empty((max(nslot, 1),) + tuple(x.shape), dtype=x.dtype, device=x.device) if nslot else None
+        y = ldbp_forward(x.contiguous(), taps.contiguous(), c.contiguous(), ntap, npol=npol, ckpt=ckpt,
+                         ckpt_every=S if ckpt is not None else 0,
+                         plan=(S, 0) if ckpt is None else None)
+        ctx.save_for_backward(x, taps, c, ckpt if ckpt is not None else torch.empty(0, device=x.device))
+        ctx.ntap, ctx.npol, ctx.S, ctx.has_ckpt = ntap, npol, S, ckpt is not None
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, taps, c, ckpt = ctx.saved_tensors
+        gx, gt, gc = ldbp_backward(x, taps, c, ctx.ntap, gy.contiguous(), npol=ctx.npol,
+                                   ckpt=ckpt if ctx.has_ckpt else None, ckpt_every=ctx.S,
+                                   need_gx=ctx.needs_input_grad[0])
+        return gx, gt, gc, None, None, None
