@@ -138,6 +138,52 @@ int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t
                   const void* ckpt, int32_t ckpt_every, const void* gy, void* gx, void* gtaps,
                   void* gc, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Split-step method (Sec. III-A) for the time-discretised NLSE
+ *   du/dz = -(alpha/2) u - j (beta2/2) d^2u/dt^2 + j gamma |u|^2 u      (eq. nlse)
+ * on the DFT grid of n samples at rate fs (circular waveforms):
+ *   linear step   D(z): X_k <- X_k exp(z (j beta2 w_k^2 / 2 - alpha / 2)), w_k = 2 pi f_k
+ *   Kerr step     N(z): x <- x exp(j kerr_scale gamma L_eff(z) |x|^2), L_eff(z) = (1 - e^{-alpha z}) / alpha
+ *                 (|x|^2 summed over both polarisations for npol = 2; kerr_scale = 8/9 for Manakov)
+ * A link has nspan spans of span_len metres, each cut into nstep steps.  The FFT
+ * is hand written (power-of-two n, 2 <= n <= 2^24).
+ * -------------------------------------------------------------------------*/
+typedef struct ssm_link {
+  double fs;          /* sampling rate [Hz] */
+  double alpha;       /* power attenuation [1/m] (>= 0) */
+  double beta2;       /* group-velocity dispersion [s^2/m] */
+  double gamma;       /* Kerr coefficient [1/(W m)] */
+  double span_len;    /* [m] */
+  double kerr_scale;  /* 1 for the scalar NLSE, 8/9 for the Manakov equation */
+  double ase_var;     /* channel only: per-sample variance of the complex noise each amplifier adds */
+  int32_t nspan;      /* >= 1 */
+  int32_t nstep;      /* steps per span, >= 1 */
+  const double* step_len; /* host [nstep] step lengths in propagation order (sum = span_len), or NULL = uniform */
+  int32_t edfa_gain;  /* 1: amplifier after each span restores the power exactly (gain e^{alpha span_len}) */
+  int32_t reserved;
+} ssm_link;
+
+/* Workspace for ssm_channel / fft_dbp (step program and FP64-generated twiddle tables). */
+int ssm_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const ssm_link* link,
+                       size_t* bytes);
+
+/* Channel simulator (Sec. III-A, Sec. IV-A): for every span, every step applies N(delta_j) then
+ * D(delta_j) (power at the start of the step in the Kerr phase), then the amplifier multiplies by
+ * e^{alpha span_len / 2} (if edfa_gain) and adds sqrt(ase_var) * noise[span].
+ *   x, y    device [nwave][n][npol] complex; y may equal x (in place), no partial overlap
+ *   noise   device [nspan][nwave][n][npol] complex with E|w|^2 = 1, required when ase_var > 0, else
+ *           ignored (may be NULL).  ldbp_randn fills such a buffer from a counter-based generator.
+ * Synchronises the stream once after uploading the step program. */
+int ssm_channel(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const ssm_link* link,
+                const void* x, void* y, const void* noise, void* ws, size_t ws_bytes, void* stream);
+
+/* FFT digital backpropagation: the exact reverse of ssm_channel without noise.  For spans last to
+ * first: multiply by e^{-alpha span_len / 2} (if edfa_gain), then for the steps in reverse order
+ * D^{-1}(delta_j) followed by N^{-1}(delta_j).  With gamma = 0 this is the frequency-domain linear
+ * equaliser.  r, y as x, y of ssm_channel. */
+int fft_dbp(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const ssm_link* link, const void* r,
+            void* y, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

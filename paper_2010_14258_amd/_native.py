@@ -33,6 +33,16 @@ class LdbpPlan(ctypes.Structure):
 
 P_plan = ctypes.POINTER(LdbpPlan)
 
+
+class SsmLink(ctypes.Structure):
+    _fields_ = [("fs", c_double), ("alpha", c_double), ("beta2", c_double), ("gamma", c_double),
+                ("span_len", c_double), ("kerr_scale", c_double), ("ase_var", c_double),
+                ("nspan", c_int32), ("nstep", c_int32), ("step_len", P_f64), ("edfa_gain", c_int32),
+                ("reserved", c_int32)]
+
+
+P_link = ctypes.POINTER(SsmLink)
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "ldbp_version": (ctypes.c_char_p, []),
@@ -47,6 +57,11 @@ SIGNATURES = {
     "ldbp_backward": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]),
+    "ssm_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, P_size]),
+    "ssm_channel": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, c_void_p, c_void_p, c_void_p, c_void_p,
+                              c_size_t, c_void_p]),
+    "fft_dbp": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, c_void_p, c_void_p, c_void_p, c_size_t,
+                          c_void_p]),
 }
 
 _lib = None

@@ -1,0 +1,132 @@
+// In-LDS Stockham FFT building blocks (power-of-two lengths) for gfx950.
+//
+// Data in LDS is laid out as [len][width]: element i of transform w sits at
+// i*width + w, so `width` independent transforms of length `len` are done
+// together.  A stage of radix RAD with Ns = product of the earlier radices
+// reads v_r = in[j + r len/RAD], multiplies by the twiddles W_{Ns RAD}^{r (j mod Ns)},
+// takes an RAD-point DFT in registers and writes out[(j/Ns) Ns RAD + (j mod Ns) + r Ns]
+// (the self-sorting Stockham formulation; no bit reversal).  Stages ping-pong
+// between two buffers.  Twiddles come from a table W_len^k, k < len, computed
+// in FP64 and rounded once.
+#pragma once
+
+#include "common.h"
+
+namespace ldbp {
+
+// cos/sin(2 pi k / 16), k = 0..4 (exact values of the regular 16-gon)
+__device__ constexpr double kC16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                       0.38268343236508977173, 0.0};
+
+template <typename R, int DIR>
+__device__ __forceinline__ cx_t<R> w16(int k) {
+  // W_16^k = exp(DIR * -2 pi i k / 16), DIR = +1 forward, -1 inverse; k in [0, 16)
+  using V = cx_t<R>;
+  k &= 15;
+  const int q = k >> 2, m = k & 3;
+  R c = static_cast<R>(kC16[m]), s = static_cast<R>(kC16[4 - m]);
+  // rotate by quarter turns: (c, s) is cos/sin of 2 pi m / 16
+  R cr, sr;
+  switch (q) {
+    case 0: cr = c; sr = s; break;
+    case 1: cr = -s; sr = c; break;
+    case 2: cr = -c; sr = -s; break;
+    default: cr = s; sr = -c; break;
+  }
+  return V{cr, DIR > 0 ? -sr : sr};
+}
+
+// In-register DFT of RAD points (RAD = 2, 4, 8, 16), natural order in and out.
+// X_k = sum_r v_r W_RAD^{r k} with W = exp(-2 pi i DIR / RAD).
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ void dft_reg(cx_t<R>* v) {
+  using V = cx_t<R>;
+  // decimation in time, iterative radix-2 with compile-time bit reversal of the input
+  constexpr int LOG = RAD == 2 ? 1 : RAD == 4 ? 2 : RAD == 8 ? 3 : 4;
+  V a[RAD];
+#pragma unroll
+  for (int i = 0; i < RAD; ++i) {
+    int r = 0;
+#pragma unroll
+    for (int b = 0; b < LOG; ++b) r |= ((i >> b) & 1) << (LOG - 1 - b);
+    a[r] = v[i];
+  }
+#pragma unroll
+  for (int half = 1; half < RAD; half <<= 1) {
+#pragma unroll
+    for (int g = 0; g < RAD; g += 2 * half) {
+#pragma unroll
+      for (int k = 0; k < half; ++k) {
+        const V w = w16<R, DIR>(k * (16 / (2 * half)));
+        V t;
+        const V o = a[g + k + half];
+        if (k == 0) {
+          t = o;
+        } else {
+          t.x = o.x * w.x - o.y * w.y;
+          t.y = o.x * w.y + o.y * w.x;
+        }
+        const V e = a[g + k];
+        a[g + k] = V{e.x + t.x, e.y + t.y};
+        a[g + k + half] = V{e.x - t.x, e.y - t.y};
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RAD; ++i) v[i] = a[i];
+}
+
+// One Stockham stage over `width` interleaved transforms of length len.
+template <typename R, int RAD, int DIR, int THREADS>
+__device__ __forceinline__ void fft_stage(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int len,
+                                          int width, int Ns, const cx_t<R>* __restrict__ tw) {
+  using V = cx_t<R>;
+  const int nbf = len / RAD;
+  const int total = nbf * width;
+  const int twstep = len / (Ns * RAD);
+  for (int b = threadIdx.x; b < total; b += THREADS) {
+    const int j = b / width;
+    const int w = b - j * width;
+    const int jm = j % Ns;
+    V v[RAD];
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) v[r] = in[(j + r * nbf) * width + w];
+    if (Ns > 1) {
+#pragma unroll
+      for (int r = 1; r < RAD; ++r) {
+        V t = tw[r * jm * twstep];
+        if (DIR < 0) t.y = -t.y;
+        const V o = v[r];
+        v[r] = V{o.x * t.x - o.y * t.y, o.x * t.y + o.y * t.x};
+      }
+    }
+    dft_reg<R, RAD, DIR>(v);
+    const int idxD = (j - jm) * RAD + jm;
+#pragma unroll
+    for (int r = 0; r < RAD; ++r) out[(idxD + r * Ns) * width + w] = v[r];
+  }
+}
+
+// Full transform of `width` interleaved length-len sequences held in A; B is scratch of the same
+// size.  Returns the buffer holding the result.  Ends with a barrier.  len must be a power of two.
+template <typename R, int DIR, int THREADS>
+__device__ cx_t<R>* lds_fft(cx_t<R>* A, cx_t<R>* B, int len, int width, const cx_t<R>* __restrict__ tw) {
+  using V = cx_t<R>;
+  V* in = A;
+  V* out = B;
+  int Ns = 1;
+  while (Ns < len) {
+    const int rem = len / Ns;
+    if (rem >= 16) fft_stage<R, 16, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 16;
+    else if (rem == 8) fft_stage<R, 8, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 8;
+    else if (rem == 4) fft_stage<R, 4, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 4;
+    else fft_stage<R, 2, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 2;
+    __syncthreads();
+    V* t = in;
+    in = out;
+    out = t;
+  }
+  return in;
+}
+
+}  // namespace ldbp

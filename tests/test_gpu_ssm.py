@@ -1,0 +1,151 @@
+"""GPU parity of the hand-written-FFT split-step channel and FFT-DBP (Sec. III-A, IV-A) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import design as D
+from oracle import ssm as S
+from oracle import txrx as X
+from oracle import units as U
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2010_14258_amd import ssm as G  # noqa: E402
+
+DEV = "cuda:0"
+ALPHA = U.alpha_from_db_per_km(0.2)
+BETA2 = U.beta2_from_ps2_per_km(-21.683)
+GAMMA = U.gamma_from_per_w_per_km(1.3)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _links(n_fs, nspan, steps, ase_var=0.0, npol=1, gamma=GAMMA, edfa=True, span=80e3):
+    kw = dict(fs=n_fs, alpha=ALPHA, beta2=BETA2, gamma=gamma, span_len=span, nspan=nspan, edfa_gain=edfa,
+              ase_var=ase_var, kerr_scale=8 / 9 if npol == 2 else 1.0)
+    o = S.Link(step_len=steps, npol=npol, **kw)
+    g = G.Link(nstep=len(steps), step_len=steps, **kw)
+    return o, g
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def _wave(seed, nwave, n, npol, p):
+    shape = (nwave, n) if npol == 1 else (nwave, n, 2)
+    return synth.complex_normal(seed, shape) * math.sqrt(p)
+
+
+CASES = [(256, 1), (4096, 1), (8192, 1), (65536, 1), (2048, 2), (16384, 2)]
+
+
+@pytest.mark.parametrize("n,npol", CASES)
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-10), (torch.complex64, 1e-4)])
+def test_channel_parity(n, npol, dtype, tol):
+    print("case: channel", n, npol, dtype, flush=True)
+    fs = 42.8e9
+    steps = D.log_steps(80e3, 5, ALPHA)
+    var = U.ase_variance_per_sample(ALPHA, 80e3, 5.0, fs)
+    o, g = _links(fs, 2, steps, ase_var=var, npol=npol)
+    x = _wave(1, 2, n, npol, 5e-3)
+    noise = synth.complex_normal(2, (2,) + x.shape)
+    ref = S.ssm_channel(x, o, noise)
+    y = G.ssm_channel(_t(x, dtype), g, noise=_t(noise, dtype), npol=npol)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), ref) <= tol
+
+
+@pytest.mark.parametrize("n,npol", CASES)
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-10), (torch.complex64, 1e-4)])
+def test_fft_dbp_parity(n, npol, dtype, tol):
+    print("case: dbp", n, npol, dtype, flush=True)
+    fs = 21.4e9
+    steps = D.log_steps(100e3, 3, ALPHA)
+    o, g = _links(fs, 3, steps, npol=npol, span=100e3)
+    r = _wave(3, 2, n, npol, 5e-3)
+    ref = S.fft_dbp(r, o)
+    y = G.fft_dbp(_t(r, dtype), g, npol=npol)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), ref) <= tol
+
+
+def test_linear_closed_form_and_in_place():
+    print("case: closed form", flush=True)
+    n, fs = 32768, 42.8e9
+    o, g = _links(fs, 3, S.uniform_steps(80e3, 7), gamma=0.0, edfa=False)
+    x = _wave(4, 3, n, 1, 1e-3)
+    xt = _t(x, torch.complex128)
+    G.ssm_channel(xt, g, y=xt)  # in place
+    torch.cuda.synchronize()
+    w = 2 * np.pi * np.fft.fftfreq(n, 1 / fs)
+    L = 3 * 80e3
+    ref = np.fft.ifft(np.fft.fft(x, axis=-1) * np.exp(L * (1j * BETA2 * w ** 2 / 2 - ALPHA / 2)), axis=-1)
+    assert _rel(xt.cpu().numpy(), ref) <= 1e-11
+
+
+@pytest.mark.parametrize("n", [1024, 131072])
+def test_dbp_inverts_channel(n):
+    print("case: inverse", n, flush=True)
+    fs = 42.8e9
+    o, g = _links(fs, 2, S.uniform_steps(80e3, 10))
+    x = _t(_wave(5, 2, n, 1, 5e-3), torch.complex128)
+    y = G.ssm_channel(x, g)
+    xr = G.fft_dbp(y, g)
+    torch.cuda.synchronize()
+    assert _rel(xr.cpu().numpy(), x.cpu().numpy()) <= 1e-11
+
+
+def test_plain_split_step_4096_fp64_workload():
+    """1,024 16-QAM symbols at 4 samples/symbol (4,096 samples), RRC 0.1, 10.7 GBd, 1 x 80 km
+    (beta2 = -21.7 ps^2/km), 0 dBm; 200-step channel, no noise; 10-step FFT-DBP; matched filter + SNR."""
+    print("case: split-step fp64 workload", flush=True)
+    rs, rho = 10.7e9, 4
+    fs = rho * rs
+    beta2 = U.beta2_from_ps2_per_km(-21.7)
+    s = X.qam16(synth.qam16_indices(101, (1, 1024)))
+    p = U.dbm_to_watt(0.0)
+    x = X.tx_shape(s, rho, p, rs)
+    kw = dict(fs=fs, alpha=ALPHA, beta2=beta2, gamma=GAMMA, span_len=80e3, nspan=1, edfa_gain=True)
+    och = S.Link(step_len=S.uniform_steps(80e3, 200), **kw)
+    odb = S.Link(step_len=S.uniform_steps(80e3, 10), **kw)
+    gch = G.Link(nstep=200, **kw)
+    gdb = G.Link(nstep=10, **kw)
+    y_ref = S.ssm_channel(x, och)
+    z_ref = S.fft_dbp(y_ref, odb)
+    xt = _t(x, torch.complex128)
+    y = G.ssm_channel(xt, gch)
+    z = G.fft_dbp(y, gdb)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), y_ref) <= 1e-10
+    assert _rel(z.cpu().numpy(), z_ref) <= 1e-10
+    snr = lambda zz: X.effective_snr_db(X.phase_correct(X.matched_filter_downsample(zz, rho, p, rs), s), s)
+    assert abs(snr(z.cpu().numpy()) - snr(z_ref)) <= 0.05
+    assert snr(z_ref) > 40.0
+
+
+def test_full_size_batches():
+    """FFT-DBP over 64 x 65,536 complex64 (10 x 100 km, 1 step/span) and the channel over
+    64 x 131,072 (4 samples/symbol, 10 uniform steps of one span), in the launch shapes of the
+    full workloads; two waveforms of each compared with the oracle."""
+    print("case: full size", flush=True)
+    fs = 21.4e9
+    o, g = _links(fs, 10, [100e3], span=100e3)
+    r = _wave(6, 64, 65536, 1, 2.5e-3)
+    y = G.fft_dbp(_t(r, torch.complex64), g)
+    torch.cuda.synchronize()
+    yy = y.cpu().numpy()
+    for b in (0, 63):
+        assert _rel(yy[b], S.fft_dbp(r[b], o)) <= 1e-4
+    o2, g2 = _links(42.8e9, 1, S.uniform_steps(100e3, 10), span=100e3)
+    x = _wave(7, 64, 131072, 1, 2.5e-3)
+    y2 = G.ssm_channel(_t(x, torch.complex64), g2)
+    torch.cuda.synchronize()
+    yy2 = y2.cpu().numpy()
+    for b in (0, 31):
+        assert _rel(yy2[b], S.ssm_channel(x[b], o2)) <= 1e-4
