@@ -184,6 +184,70 @@ int ssm_channel(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const ssm
 int fft_dbp(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const ssm_link* link, const void* r,
             void* y, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched FFT (hand written, power-of-two n in [2, 2^24]): y_k = sum_t x_t e^{-+2 pi i k t / n},
+ * unnormalised, natural order; inverse != 0 selects the + sign.  x, y device [nwave][n][npol];
+ * y may equal x.  The DFT of eq. discretized_nlse (Sec. III-A).
+ * -------------------------------------------------------------------------*/
+int ldbp_fft_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, size_t* bytes);
+int ldbp_fft(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const void* x, void* y, int32_t inverse,
+             void* ws, size_t ws_bytes, void* stream);
+
+/* Transmitter (Sec. IV-A): x(t) = sqrt(P) sum_k s_k p(t - k/R_s) with a root-raised-cosine p of
+ * roll-off `rolloff`, periodic frames, sampled at rho samples/symbol (rho and nsym powers of two):
+ * symbol k sits at sample k*rho, the RRC is applied in the frequency domain and the waveform scaled
+ * by sqrt(P) rho (mean power P for unit-energy symbols).  Symbols are 16-QAM,
+ * s = (2 (i mod 4) - 3 + j (2 (i div 4) - 3)) / sqrt(10) from indices i in 0..15.
+ *   sym_idx device int32 [nwave][nsym][npol]; p_watt device double [nwave];
+ *   x device [nwave][rho nsym][npol] complex (output). */
+int tx_shape_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho, size_t* bytes);
+int tx_shape(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho, double rs, double rolloff,
+             const int32_t* sym_idx, const double* p_watt, void* x, void* ws, size_t ws_bytes, void* stream);
+
+/* Receiver front end (Sec. IV-A): ideal brick-wall low-pass of two-sided bandwidth equal to the new
+ * sampling rate and resampling from n_in to n_out samples per frame (DFT bins |f| < f_out / 2 kept,
+ * Nyquist bin zeroed, sample values of in-band signals preserved).  y [nwave][n_in][npol] ->
+ * r [nwave][n_out][npol]. */
+int rx_lpf_decimate_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n_in, int64_t n_out,
+                                   size_t* bytes);
+int rx_lpf_decimate(int32_t dtype, int32_t npol, int64_t nwave, int64_t n_in, int64_t n_out, const void* y,
+                    void* r, void* ws, size_t ws_bytes, void* stream);
+
+/* Receiver DSP after equalisation and the training loss (Sec. IV-A, IV-B): matched RRC filter and
+ * downsampling by rho (the circulant M), division by sqrt(P), genie phase phi = arg(s^H s~),
+ * s^ = s~ e^{-j phi}; per frame (waveform, polarisation) MSE ||s^ - s||^2 / nsym.  With gz != NULL
+ * also the gradient of the mean MSE over all frames w.r.t. z (convention dL/dRe + j dL/dIm; phi
+ * held fixed, which is exact because it minimises the loss).
+ *   z device [nwave][rho nsym][npol]; sym device [nwave][nsym][npol] complex (transmitted symbols);
+ *   p_watt device double [nwave]; s_hat (nullable) device [nwave][nsym][npol];
+ *   mse device double [nwave * npol]; gz (nullable) device like z. */
+int rx_mse_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho, size_t* bytes);
+int rx_mse(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho, double rs, double rolloff,
+           const void* z, const void* sym, const double* p_watt, void* s_hat, double* mse, void* gz, void* ws,
+           size_t ws_bytes, void* stream);
+
+/* 16-QAM symbols (as in tx_shape) from indices: s device [count] complex. */
+int qam16_symbols(int32_t dtype, int64_t count, const int32_t* sym_idx, void* s, void* stream);
+
+/* Counter-based random numbers (Philox4x32-10, Salmon et al., SC'11) for the channel noise and the
+ * symbols drawn during training.  Number i of a call uses counter (i/2 low, i/2 high, stream_id
+ * low, stream_id high) and key seed; each counter yields 4 words.
+ *   ldbp_randbits: out device uint32 [nwords], the words in counter order.
+ *   ldbp_randn:    out device [count] complex CN(0, 1) (E|w|^2 = 1): words (a, b) map to
+ *                  sqrt(-ln u_a) e^{j 2 pi u_b}, u = (word + 1/2) 2^-32. */
+int ldbp_randbits(uint32_t* out, int64_t nwords, uint64_t seed, uint64_t stream_id, void* stream);
+int ldbp_randn(int32_t dtype, void* out, int64_t count, uint64_t seed, uint64_t stream_id, void* stream);
+
+/* Adam update (Sec. IV-B; Kingma & Ba constants passed in) on `count` real parameters of the
+ * dtype's real type, step t >= 1.  mask (nullable, same type and length): pruned parameters have
+ * their gradient and value forced to 0 (Sec. IV-C).  mirror (nullable, device int32
+ * [count / comps]): element e of a symmetric filter shares its parameter with element mirror[e],
+ * the gradient used is g_e + g_mirror[e] (the centre tap has mirror[e] = e and keeps g_e); comps = 2
+ * when the parameters are interleaved complex values, else 1. */
+int ldbp_adam(int32_t dtype, void* theta, const void* grad, void* m, void* v, const void* mask,
+              const int32_t* mirror, int64_t count, int32_t comps, double lr, double b1, double b2, double eps,
+              int64_t t, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,23 @@ SIGNATURES = {
                               c_size_t, c_void_p]),
     "fft_dbp": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, c_void_p, c_void_p, c_void_p, c_size_t,
                           c_void_p]),
+    "ldbp_fft_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_size]),
+    "ldbp_fft": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_void_p, c_void_p, c_int32, c_void_p, c_size_t,
+                           c_void_p]),
+    "tx_shape_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_size]),
+    "tx_shape": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, c_double, c_double, c_void_p, c_void_p,
+                           c_void_p, c_void_p, c_size_t, c_void_p]),
+    "rx_lpf_decimate_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int64, P_size]),
+    "rx_lpf_decimate": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
+                                  c_size_t, c_void_p]),
+    "rx_mse_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_size]),
+    "rx_mse": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, c_double, c_double, c_void_p, c_void_p,
+                         c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "qam16_symbols": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
+    "ldbp_randbits": (c_int32, [c_void_p, c_int64, c_uint64, c_uint64, c_void_p]),
+    "ldbp_randn": (c_int32, [c_int32, c_void_p, c_int64, c_uint64, c_uint64, c_void_p]),
+    "ldbp_adam": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32,
+                            c_double, c_double, c_double, c_double, c_int64, c_void_p]),
 }
 
 _lib = None
