@@ -18,9 +18,15 @@ listed in the order backpropagation visits them.
 Least-squares taps (Sec. IV-C): minimise ||B h - d||^2 with d_i = e^{j xi w_i^2},
 xi = -beta2 delta' f_s^2 / 2, w_i = 2 pi i / N for i = -N/2..N/2 and B the
 (N+1) x T DFT matrix B_{i,k} = e^{-j k w_i} (centred DTFT of the taps).  The
-constrained in-band variant the paper cites [Sheikh2016] is not reproduced
-(its definition is not in the paper); the full-band fit is used, which on the
-N-point grid is exactly the truncated inverse DFT of the response.
+full-band fit on the N-point grid is exactly the truncated inverse DFT of the
+response.  The paper instead fits only within the signal bandwidth and bounds
+the out-of-band gain, citing [Sheikh2016] for the details, which the paper does
+not give.  Reading: a weighted least-squares fit with weight 1 for
+|w| <= pi (1 + rolloff) / rho (the RRC signal band at rho samples/symbol) and
+weight sqrt(mu) elsewhere, against the same all-pass target everywhere; the
+small out-of-band weight keeps the gain there near one instead of letting the
+cascade of filters amplify out-of-band noise.  mu = 1e-3 by default
+("inband" method).  Parity of this reading against the cited method: unpinned.
 
 Kerr coefficients: a DBP step that undoes forward step delta starting at span
 position z_a uses c = -kerr_scale * gamma * L_eff(delta) * e^{-alpha z_a}: the
@@ -80,6 +86,20 @@ def ls_taps(xi: float, T: int, N: int = 4096) -> np.ndarray:
     return h
 
 
+def ls_taps_inband(xi: float, T: int, band_edge: float, mu: float = 1e-3, N: int = 4096) -> np.ndarray:
+    """Weighted LS on the paper's grid: weight 1 for |w| <= band_edge, sqrt(mu) outside (reading above)."""
+    assert T % 2 == 1
+    K = (T - 1) // 2
+    i = np.arange(-N // 2, N // 2 + 1)
+    w = 2.0 * np.pi * i / N
+    k = np.arange(-K, K + 1)
+    wt = np.where(np.abs(w) <= band_edge, 1.0, np.sqrt(mu))
+    B = np.exp(-1j * np.outer(w, k)) * wt[:, None]
+    d = np.exp(1j * xi * w * w) * wt
+    h, *_ = np.linalg.lstsq(B, d, rcond=None)
+    return h
+
+
 def truncated_idft_taps(xi: float, T: int, N: int = 4096) -> np.ndarray:
     """h_k = (1/N) sum_m e^{j xi w_m^2} e^{j k w_m}, w_m = 2 pi m / N, m = -N/2..N/2-1, k = -K..K."""
     K = (T - 1) // 2
@@ -111,7 +131,7 @@ def kerr_coef(delta: float, z_start: float, alpha: float, gamma: float, kerr_sca
 
 def init_asymmetric(span_len: float, nspan: int, steps_per_span: Sequence[float], T, fs: float,
                     alpha: float, beta2: float, gamma: float, kerr_scale: float = 1.0,
-                    method: str = "ls", N: int = 4096):
+                    method: str = "ls", N: int = 4096, rho: int = 2, rolloff: float = 0.1, mu: float = 1e-3):
     """LDBP based on the asymmetric SSM, l = M (Sec. IV-C): per-step LS taps and Kerr coefficients.
 
     ``T`` is an int or a per-layer sequence of odd tap counts.  Returns (taps, c).
@@ -124,6 +144,8 @@ def init_asymmetric(span_len: float, nspan: int, steps_per_span: Sequence[float]
         xi = xi_of(d, beta2, fs)
         if method == "ls":
             taps.append(ls_taps(xi, Ts[i], N))
+        elif method == "inband":
+            taps.append(ls_taps_inband(xi, Ts[i], np.pi * (1.0 + rolloff) / rho, mu, N))
         elif method == "truncate":
             taps.append(truncated_idft_taps(xi, Ts[i], N))
         elif method == "unit":

@@ -1,0 +1,121 @@
+"""Host-side parameter initialisation for LDBP (Sec. IV-C): units, step sizes, taps, Kerr coefficients.
+
+These run once per model on the CPU (a few hundred small vectors) and produce
+the device parameters the kernels train and apply.
+
+  * log step sizes: every step of a span carries the same integral of
+    exp(-alpha' z), alpha' = 0.4 alpha (the logarithmic heuristic the paper
+    adopts with adjusting factor 0.4), so steps are short where the power is high;
+  * taps: least-squares fit of the inverse-dispersion response exp(j xi w^2),
+    xi = -beta2 delta f_s^2 / 2.  Default ("inband"): the error is weighted 1
+    inside the signal band |w| <= pi (1 + rolloff) / rho and sqrt(mu) outside,
+    against the same all-pass target, which keeps the out-of-band gain near one
+    (the paper fits in band with bounded out-of-band gain); solved from the T x T
+    normal equations, whose matrix is Hermitian Toeplitz.  "full": the full-band
+    fit, which on an N-point grid is the truncated inverse DFT of the response,
+    computed with one FFT;
+  * Kerr coefficients: c = -kerr_scale gamma L_eff(delta) e^{-alpha z_a} for the
+    forward step that starts at span position z_a (unit-gain filters keep the
+    signal at launch power, so the span's power profile is carried by c).
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Sequence, Tuple
+
+import numpy as np
+
+
+def db_per_km_to_alpha(db_per_km: float) -> float:
+    return db_per_km * math.log(10.0) / 10.0 / 1e3
+
+
+def ps2_per_km_to_beta2(v: float) -> float:
+    return v * 1e-27
+
+
+def dbm_to_w(p_dbm: float) -> float:
+    return 10.0 ** (p_dbm / 10.0 - 3.0)
+
+
+def effective_length(z: float, alpha: float) -> float:
+    return z if alpha == 0.0 else -math.expm1(-alpha * z) / alpha
+
+
+def ase_variance(alpha: float, span_len: float, nf_db: float, fs: float, nu: float = 1.946e14,
+                 planck: float = 6.626e-34) -> float:
+    """Per-sample complex noise variance of one amplifier: PSD (e^{alpha L} - 1) h nu n_sp times fs."""
+    g = math.exp(alpha * span_len)
+    n_sp = 10.0 ** (nf_db / 10.0) / (2.0 * (1.0 - 1.0 / g))
+    return (g - 1.0) * planck * nu * n_sp * fs
+
+
+def log_step_sizes(span_len: float, nstep: int, alpha: float, factor: float = 0.4) -> List[float]:
+    a = factor * alpha
+    if nstep == 1 or a == 0.0:
+        return [span_len / nstep] * nstep
+    total = -math.expm1(-a * span_len)            # integral of a e^{-a z} over the span
+    bounds = [0.0]
+    for j in range(1, nstep):
+        bounds.append(-math.log1p(-total * j / nstep) / a)
+    bounds.append(span_len)
+    return [bounds[j + 1] - bounds[j] for j in range(nstep)]
+
+
+def inverse_cd_taps(delta: float, beta2: float, fs: float, ntap: int, grid: int = 4096) -> np.ndarray:
+    """Centred taps h_{-K..K} of the full-band least-squares fit to exp(j xi w^2) (truncated inverse DFT)."""
+    xi = -beta2 * delta * fs * fs / 2.0
+    w = 2.0 * np.pi * np.fft.fftfreq(grid)          # FFT-ordered grid of angular frequencies
+    resp = np.exp(1j * xi * w * w)
+    h_all = np.fft.ifft(resp)                        # h_all[k mod grid] = (1/N) sum_m resp_m e^{j k w_m}
+    K = (ntap - 1) // 2
+    return np.array([h_all[k % grid] for k in range(-K, K + 1)])
+
+
+def inverse_cd_taps_inband(delta: float, beta2: float, fs: float, ntap: int, rho: int = 2, rolloff: float = 0.1,
+                           mu: float = 1e-3, grid: int = 4096) -> np.ndarray:
+    """Weighted least squares: weight 1 for |w| <= pi (1 + rolloff) / rho, sqrt(mu) outside (grid of N+1 points)."""
+    xi = -beta2 * delta * fs * fs / 2.0
+    K = (ntap - 1) // 2
+    w = 2.0 * np.pi * np.arange(-grid // 2, grid // 2 + 1) / grid
+    wt2 = np.where(np.abs(w) <= np.pi * (1.0 + rolloff) / rho, 1.0, mu)   # squared weights
+    resp = np.exp(1j * xi * w * w)
+    lags = np.arange(-2 * K, 2 * K + 1)
+    # normal equations: G[a, b] = sum_i wt2 e^{j (a - b) w_i}, rhs[a] = sum_i wt2 e^{j a w_i} resp_i
+    r = np.array([np.sum(wt2 * np.exp(1j * l * w)) for l in lags])
+    k = np.arange(-K, K + 1)
+    G = r[(k[:, None] - k[None, :]) + 2 * K]
+    rhs = np.array([np.sum(wt2 * np.exp(1j * a * w) * resp) for a in k])
+    return np.linalg.solve(G, rhs)
+
+
+def backprop_schedule(span_len: float, nspan: int, steps: Sequence[float]) -> List[Tuple[float, float]]:
+    """(delta, z_start) of the forward steps in the order backpropagation undoes them."""
+    starts = np.cumsum([0.0] + list(steps))[:-1]
+    order = []
+    for _ in range(nspan):
+        for j in range(len(steps) - 1, -1, -1):
+            order.append((float(steps[j]), float(starts[j])))
+    return order
+
+
+def ldbp_parameters(span_len: float, nspan: int, steps_per_span: int, ntap, fs: float, alpha: float, beta2: float,
+                    gamma: float, kerr_scale: float = 1.0, log_steps: bool = True, unit_taps: bool = False,
+                    method: str = "inband", rho: int = 2, rolloff: float = 0.1, mu: float = 1e-3):
+    """Asymmetric-SSM LDBP (l = nspan * steps_per_span): returns (list of tap vectors, c array)."""
+    steps = log_step_sizes(span_len, steps_per_span, alpha) if log_steps else [span_len / steps_per_span] * steps_per_span
+    sched = backprop_schedule(span_len, nspan, steps)
+    L = len(sched)
+    ts = [int(ntap)] * L if np.isscalar(ntap) else [int(t) for t in ntap]
+    taps, c = [], np.zeros(L)
+    for i, (d, z0) in enumerate(sched):
+        if unit_taps:
+            h = np.zeros(ts[i], dtype=np.complex128)
+            h[(ts[i] - 1) // 2] = 1.0
+        elif method == "inband":
+            h = inverse_cd_taps_inband(d, beta2, fs, ts[i], rho, rolloff, mu)
+        else:
+            h = inverse_cd_taps(d, beta2, fs, ts[i])
+        taps.append(h)
+        c[i] = -kerr_scale * gamma * effective_length(d, alpha) * math.exp(-alpha * z0)
+    return taps, c

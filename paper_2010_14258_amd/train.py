@@ -1,0 +1,257 @@
+"""Training of LDBP on the GPU (Sec. IV-B, IV-C) with data from the GPU split-step channel.
+
+Every iteration draws a batch with the library's own kernels -- Philox symbols and amplifier
+noise, RRC transmitter, split-step channel with amplifiers, low-pass + decimation -- then runs the
+LDBP forward (with block checkpoints), the receiver MSE after matched filter and genie phase, the
+hand-written adjoints (receiver, then LDBP) and an Adam step on the taps and Kerr coefficients.
+The training power of each waveform is drawn uniformly from a power set (Sec. IV-B).
+
+Progressive pruning (Sec. IV-C): filters start with ``t_init`` taps and lose their outermost
+symmetric pair at scheduled iterations until they have ``t_final``.  Events go round-robin over
+the layers; event e of E fires at iteration floor(prune_frac * iters * (e/E)^2), so more taps go
+early.  A pruned pair is removed from the packed filters (equivalent to a zero mask on it) so the
+kernels stop paying for it.
+
+Batches are a pure function of (seed, iteration): a run resumed from a checkpoint continues
+bit for bit like an uninterrupted one.
+"""
+from __future__ import annotations
+
+import json
+import math
+from dataclasses import asdict, dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import init as I
+from . import ldbp as L
+from . import ssm as SS
+from . import txrx as TX
+
+
+@dataclass
+class TrainConfig:
+    nwave: int = 32
+    nsym: int = 8192
+    rho_a: int = 4
+    rho_d: int = 2
+    rs: float = 10.7e9
+    rolloff: float = 0.1
+    nspan: int = 10
+    span_km: float = 100.0
+    channel_steps: int = 100          # uniform steps per span in the channel simulation
+    ldbp_steps: int = 5               # LDBP layers per span (log step sizes)
+    t_init: int = 25
+    t_final: int = 3
+    iters: int = 5000
+    prune_frac: float = 0.6
+    lr: float = 1e-3
+    powers_dbm: Sequence[float] = (2.0, 3.0, 4.0)
+    alpha_db_km: float = 0.2
+    beta2_ps2_km: float = -21.683
+    gamma_w_km: float = 1.3
+    nf_db: float = 5.0
+    npol: int = 1
+    symmetric: bool = True
+    train_c: bool = True
+    ckpt_every: int = 5
+    seed: int = 301
+    complex128: bool = False
+    unit_init: bool = False
+
+
+def pruning_plan(t_init: Sequence[int], t_final: Sequence[int], iters: int, frac: float):
+    """(iteration, layer) pairs: round-robin over layers, front-loaded quadratic timing."""
+    cur = list(t_init)
+    layers = []
+    while any(c > f for c, f in zip(cur, t_final)):
+        for i in range(len(cur)):
+            if cur[i] > t_final[i]:
+                cur[i] -= 2
+                layers.append(i)
+    E = len(layers)
+    when = [int(math.floor(frac * iters * ((e + 1) / E) ** 2)) for e in range(E)]
+    return list(zip(when, layers))
+
+
+class Trainer:
+    def __init__(self, cfg: TrainConfig, device="cuda:0"):
+        self.cfg = cfg
+        self.dev = torch.device(device)
+        self.cdt = torch.complex128 if cfg.complex128 else torch.complex64
+        self.rdt = torch.float64 if cfg.complex128 else torch.float32
+        self.alpha = I.db_per_km_to_alpha(cfg.alpha_db_km)
+        self.beta2 = I.ps2_per_km_to_beta2(cfg.beta2_ps2_km)
+        self.gamma = cfg.gamma_w_km / 1e3
+        self.span = cfg.span_km * 1e3
+        self.kerr_scale = 8.0 / 9.0 if cfg.npol == 2 else 1.0
+        self.fs_a = cfg.rho_a * cfg.rs
+        self.fs_d = cfg.rho_d * cfg.rs
+        self.n_a = cfg.rho_a * cfg.nsym
+        self.n_d = cfg.rho_d * cfg.nsym
+        self.channel = SS.Link(fs=self.fs_a, alpha=self.alpha, beta2=self.beta2, gamma=self.gamma,
+                               span_len=self.span, nspan=cfg.nspan, nstep=cfg.channel_steps, edfa_gain=True,
+                               ase_var=I.ase_variance(self.alpha, self.span, cfg.nf_db, self.fs_a),
+                               kerr_scale=self.kerr_scale)
+        taps, c = I.ldbp_parameters(self.span, cfg.nspan, cfg.ldbp_steps, cfg.t_init, self.fs_d, self.alpha,
+                                    self.beta2, self.gamma, kerr_scale=self.kerr_scale, unit_taps=cfg.unit_init)
+        self.ntap = [len(h) for h in taps]
+        self.taps = torch.from_numpy(np.concatenate(taps)).to(self.dev, self.cdt)
+        self.c = torch.from_numpy(c).to(self.dev, self.rdt)
+        self.m_t = torch.zeros(2 * self.taps.numel(), dtype=self.rdt, device=self.dev)
+        self.v_t = torch.zeros_like(self.m_t)
+        self.m_c = torch.zeros_like(self.c)
+        self.v_c = torch.zeros_like(self.c)
+        self.t = 0
+        self.it = 0
+        self.plan = pruning_plan(self.ntap, [cfg.t_final] * len(self.ntap), cfg.iters, cfg.prune_frac) \
+            if cfg.t_final < cfg.t_init else []
+        self.events_done = 0
+        self._mirror = None
+        self.history: List[dict] = []
+
+    # ------------------------------------------------------------------ data
+    def powers(self, it: int) -> torch.Tensor:
+        g = np.random.Generator(np.random.PCG64([self.cfg.seed, it, 7]))
+        p = g.choice(np.asarray(self.cfg.powers_dbm, dtype=np.float64), size=self.cfg.nwave)
+        return torch.from_numpy(10.0 ** (p / 10.0 - 3.0)).to(self.dev)
+
+    def batch(self, it: int, p_watt: Optional[torch.Tensor] = None):
+        """Received waveforms r [nwave, n_d(, 2)], transmitted symbols, powers: a function of (seed, it)."""
+        cfg = self.cfg
+        p = self.powers(it) if p_watt is None else p_watt
+        shape = (cfg.nwave, cfg.nsym) if cfg.npol == 1 else (cfg.nwave, cfg.nsym, 2)
+        words = TX.randbits(int(np.prod(shape)), cfg.seed, 2 * it, device=self.dev).view(shape)
+        x = TX.tx_shape(words, p, cfg.rho_a, cfg.rs, cfg.rolloff, npol=cfg.npol, dtype=self.cdt)
+        noise = TX.randn((cfg.nspan,) + tuple(x.shape), cfg.seed, 2 * it + 1, dtype=self.cdt, device=self.dev)
+        y = SS.ssm_channel(x, self.channel, noise=noise, npol=cfg.npol, y=x)
+        del noise
+        r = TX.rx_lpf_decimate(y, self.n_d, npol=cfg.npol)
+        s = TX.qam16_symbols(words, dtype=self.cdt)
+        return r, s, p
+
+    # ------------------------------------------------------------------ model
+    def mirror(self) -> torch.Tensor:
+        if self._mirror is None:
+            mir, off = [], 0
+            for T in self.ntap:
+                mir.extend(off + T - 1 - j for j in range(T))
+                off += T
+            self._mirror = torch.tensor(mir, dtype=torch.int32, device=self.dev)
+        return self._mirror
+
+    def _prune(self, layer: int):
+        """Removes the outermost pair of filter `layer` from the packed taps and the Adam moments."""
+        keep, off = [], 0
+        for i, T in enumerate(self.ntap):
+            if i == layer:
+                keep.extend(range(off + 1, off + T - 1))
+            else:
+                keep.extend(range(off, off + T))
+            off += T
+        idx = torch.tensor(keep, dtype=torch.int64, device=self.dev)
+        self.taps = self.taps.index_select(0, idx).contiguous()
+        self.m_t = self.m_t.view(-1, 2).index_select(0, idx).reshape(-1).contiguous()
+        self.v_t = self.v_t.view(-1, 2).index_select(0, idx).reshape(-1).contiguous()
+        self.ntap[layer] -= 2
+        self._mirror = None
+
+    def forward(self, r: torch.Tensor, ckpt: bool = False):
+        cfg = self.cfg
+        if not ckpt:
+            return L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=cfg.npol), None
+        S = max(1, min(cfg.ckpt_every, len(self.ntap)))
+        nslot = L.num_checkpoints(len(self.ntap), S)
+        ck = torch.empty((nslot,) + tuple(r.shape), dtype=r.dtype, device=r.device) if nslot else None
+        z = L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=cfg.npol, ckpt=ck, ckpt_every=S if ck is not None else 0,
+                           plan=(S, 0) if ck is None else None)
+        return z, ck
+
+    def step(self):
+        """One training iteration; returns the batch loss (mean MSE over frames)."""
+        cfg = self.cfg
+        while self.events_done < len(self.plan) and self.plan[self.events_done][0] <= self.it:
+            self._prune(self.plan[self.events_done][1])
+            self.events_done += 1
+        r, s, p = self.batch(self.it)
+        z, ck = self.forward(r, ckpt=True)
+        S = max(1, min(cfg.ckpt_every, len(self.ntap)))
+        mse, _, gz = TX.rx_mse(z, s, p, cfg.rho_d, cfg.rs, cfg.rolloff, npol=cfg.npol, want_grad=True)
+        _, gt, gc = L.ldbp_backward(r, self.taps, self.c, self.ntap, gz, npol=cfg.npol, ckpt=ck, ckpt_every=S,
+                                    need_gx=False)
+        self.t += 1
+        TX.adam_(self.taps, gt, self.m_t, self.v_t, self.t, lr=cfg.lr,
+                 mirror=self.mirror() if cfg.symmetric else None)
+        if cfg.train_c:
+            TX.adam_(self.c, gc, self.m_c, self.v_c, self.t, lr=cfg.lr)
+        loss = float(mse.mean().item())
+        self.history.append({"it": self.it, "loss": loss, "taps": int(sum(self.ntap))})
+        self.it += 1
+        return loss
+
+    def train(self, iters: Optional[int] = None, log=None):
+        n = self.cfg.iters - self.it if iters is None else iters
+        for _ in range(n):
+            loss = self.step()
+            if log is not None:
+                log.write(json.dumps(self.history[-1]) + "\n")
+        return self.history
+
+    # ------------------------------------------------------------------ evaluation
+    def evaluate(self, nbatch: int = 4, p_dbm: Optional[float] = None, offset: int = 1_000_000):
+        """Effective SNR [dB] (symbols / total squared error) of LDBP on held-out batches."""
+        err, cnt = 0.0, 0
+        for b in range(nbatch):
+            p = None if p_dbm is None else torch.full((self.cfg.nwave,), I.dbm_to_w(p_dbm), dtype=torch.float64,
+                                                      device=self.dev)
+            r, s, pp = self.batch(offset + b, p)
+            z, _ = self.forward(r)
+            mse, _, _ = TX.rx_mse(z, s, pp, self.cfg.rho_d, self.cfg.rs, self.cfg.rolloff, npol=self.cfg.npol)
+            err += float(mse.sum().item())
+            cnt += mse.numel()
+        return 10.0 * math.log10(cnt / err)
+
+    def dbp_link(self, steps_per_span: int, log_steps: bool = True) -> SS.Link:
+        steps = I.log_step_sizes(self.span, steps_per_span, self.alpha) if log_steps else None
+        return SS.Link(fs=self.fs_d, alpha=self.alpha, beta2=self.beta2, gamma=self.gamma, span_len=self.span,
+                       nspan=self.cfg.nspan, nstep=steps_per_span, step_len=steps, edfa_gain=True,
+                       kerr_scale=self.kerr_scale)
+
+    def evaluate_fft_dbp(self, steps_per_span: int, nbatch: int = 4, p_dbm: Optional[float] = None,
+                         offset: int = 1_000_000, gamma_zero: bool = False):
+        link = self.dbp_link(steps_per_span)
+        if gamma_zero:
+            link.gamma = 0.0
+        err, cnt = 0.0, 0
+        for b in range(nbatch):
+            p = None if p_dbm is None else torch.full((self.cfg.nwave,), I.dbm_to_w(p_dbm), dtype=torch.float64,
+                                                      device=self.dev)
+            r, s, pp = self.batch(offset + b, p)
+            z = SS.fft_dbp(r, link, npol=self.cfg.npol)
+            mse, _, _ = TX.rx_mse(z, s, pp, self.cfg.rho_d, self.cfg.rs, self.cfg.rolloff, npol=self.cfg.npol)
+            err += float(mse.sum().item())
+            cnt += mse.numel()
+        return 10.0 * math.log10(cnt / err)
+
+    # ------------------------------------------------------------------ checkpoints
+    def state_dict(self):
+        return {"cfg": asdict(self.cfg), "taps": self.taps.cpu(), "c": self.c.cpu(), "ntap": list(self.ntap),
+                "m_t": self.m_t.cpu(), "v_t": self.v_t.cpu(), "m_c": self.m_c.cpu(), "v_c": self.v_c.cpu(),
+                "t": self.t, "it": self.it, "events_done": self.events_done}
+
+    def load_state_dict(self, st):
+        self.taps = st["taps"].to(self.dev)
+        self.c = st["c"].to(self.dev)
+        self.ntap = [int(t) for t in st["ntap"]]
+        self.m_t, self.v_t = st["m_t"].to(self.dev), st["v_t"].to(self.dev)
+        self.m_c, self.v_c = st["m_c"].to(self.dev), st["v_c"].to(self.dev)
+        self.t, self.it, self.events_done = int(st["t"]), int(st["it"]), int(st["events_done"])
+        self._mirror = None
+
+    def save(self, path: str):
+        torch.save(self.state_dict(), path)
+
+    def load(self, path: str):
+        self.load_state_dict(torch.load(path, weights_only=True))

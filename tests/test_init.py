@@ -1,0 +1,54 @@
+"""CPU checks of the product's host-side initialisation against the oracle (Sec. IV-C)."""
+import numpy as np
+import pytest
+
+from oracle import design as D
+from oracle import train as OT
+from oracle import units as U
+from paper_2010_14258_amd import init as I
+from paper_2010_14258_amd import train as T
+
+ALPHA = U.alpha_from_db_per_km(0.2)
+BETA2 = U.beta2_from_ps2_per_km(-21.683)
+GAMMA = U.gamma_from_per_w_per_km(1.3)
+
+
+def test_units():
+    assert abs(I.db_per_km_to_alpha(0.2) - ALPHA) < 1e-18
+    assert abs(I.ps2_per_km_to_beta2(-21.683) - BETA2) < 1e-40
+    assert abs(I.ase_variance(ALPHA, 1e5, 5.0, 4.28e10) - U.ase_variance_per_sample(ALPHA, 1e5, 5.0, 4.28e10)) < 1e-18
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 10])
+def test_log_steps(n):
+    np.testing.assert_allclose(I.log_step_sizes(1e5, n, ALPHA), D.log_steps(1e5, n, ALPHA), rtol=1e-12)
+
+
+def test_ldbp_parameters_match_oracle_init():
+    steps = D.log_steps(1e5, 5, ALPHA)
+    ot, oc = D.init_asymmetric(1e5, 10, steps, 15, 21.4e9, ALPHA, BETA2, GAMMA, method="truncate")
+    pt, pc = I.ldbp_parameters(1e5, 10, 5, 15, 21.4e9, ALPHA, BETA2, GAMMA, method="full")
+    np.testing.assert_allclose(pc, oc, rtol=1e-12)
+    for a, b in zip(pt, ot):
+        np.testing.assert_allclose(a, b, atol=1e-12)
+    # and the paper's (N+1)-point least-squares grid agrees to O(1/N)
+    lt, _ = D.init_asymmetric(1e5, 10, steps, 15, 21.4e9, ALPHA, BETA2, GAMMA, method="ls")
+    assert max(np.max(np.abs(a - b)) for a, b in zip(pt, lt)) < 2e-3
+
+
+def test_pruning_plan_matches_oracle_schedule():
+    plan = T.pruning_plan([25] * 50, [3] * 50, 5000, 0.6)
+    ev = OT.pruning_events([25] * 50, [3] * 50)
+    its = OT.pruning_iterations(len(ev), 5000, 0.6)
+    assert [l for _, l in plan] == ev
+    assert [w for w, _ in plan] == its
+
+
+def test_inband_taps_match_oracle_reading():
+    steps = D.log_steps(1e5, 1, ALPHA)
+    for T in (5, 9, 15):
+        ot, oc = D.init_asymmetric(1e5, 3, steps, T, 21.4e9, ALPHA, BETA2, GAMMA, method="inband")
+        pt, pc = I.ldbp_parameters(1e5, 3, 1, T, 21.4e9, ALPHA, BETA2, GAMMA, method="inband")
+        for a, b in zip(pt, ot):
+            np.testing.assert_allclose(a, b, atol=1e-9)
+            np.testing.assert_allclose(a, a[::-1], atol=1e-9)   # symmetric filters

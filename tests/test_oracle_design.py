@@ -147,3 +147,19 @@ def test_adam_minimises_quadratic():
     for _ in range(2000):
         th = opt.step(th, 2 * (th - np.array([1.0, 0.5])))
     np.testing.assert_allclose(th, [1.0, 0.5], atol=1e-2)
+
+
+def test_inband_fit_reduces_to_full_band_and_improves_band_error():
+    xi, T = 0.497, 9
+    np.testing.assert_allclose(D.ls_taps_inband(xi, T, 1.1 * np.pi / 2, mu=1.0), D.ls_taps(xi, T), atol=1e-12)
+    w = 2 * np.pi * np.arange(-2048, 2049) / 4096
+    band = np.abs(w) <= 1.1 * np.pi / 2
+    k = np.arange(-(T // 2), T // 2 + 1)
+
+    def band_err(h):
+        return np.max(np.abs(np.exp(-1j * np.outer(w[band], k)) @ h - np.exp(1j * xi * w[band] ** 2)))
+
+    hb = D.ls_taps_inband(xi, T, 1.1 * np.pi / 2)
+    assert band_err(hb) < 0.2 * band_err(D.ls_taps(xi, T))
+    # out-of-band gain stays bounded (no blow-up of the cascade)
+    assert np.max(np.abs(np.exp(-1j * np.outer(w, k)) @ hb)) < 2.0
