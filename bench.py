@@ -1,17 +1,23 @@
-"""Throughput benchmark of the LDBP hot path on one MI355X.
+"""Throughput benchmark of the LDBP hot path on one MI355X; prints one JSON line.
 
-Workload (default): a batch of 64 received waveforms x 65,536 complex64 samples
-(16-QAM, 2 samples/symbol, RRC 0.1, 10.7 GBd, 10 x 100 km), equalised by an
-LDBP of l = 50 steps (5 per span, log step sizes) with 15-tap filters and
-per-step Kerr coefficients, least-squares initialised.
+Workload: 64 received waveforms x 65,536 complex64 samples (16-QAM at 2 samples/symbol, RRC
+roll-off 0.1, 10.7 GBd) after 10 x 100 km of fiber with an amplifier per span (NF 5 dB), launch
+power 4 dBm.  The waveforms are generated on the GPU by the library itself: Philox symbols, RRC
+transmitter at 4 samples/symbol, split-step channel with 100 uniform steps per span and amplifier
+noise, brick-wall low-pass and decimation to 2 samples/symbol.  The equaliser is LDBP with
+l = 50 steps (5 per span, logarithmic step sizes) of 15-tap filters and per-step Kerr
+coefficients, least-squares initialised.
 
-One timed step = one LDBP forward over the whole batch.  The metric is
-samples x steps per second (sum over waveforms of n * l per second), with the
-inputs already resident in GPU memory.  Prints one JSON line.
+One timed step = one LDBP forward over the whole batch (inputs resident in GPU memory).
+value = samples x steps per second = nwave * n * l / time.  Also reported: forward + backward
+(block checkpoints every 5 steps), FFT-DBP on the same waveforms at the smallest steps/span whose
+effective SNR is within 0.1 dB of LDBP's, one training iteration of the 32 x 16,384 training
+configuration, the roofline position of the forward kernel and the FP64 oracle on the host.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -23,14 +29,86 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_PEAK_TFLOPS = 78.6        # 256 CU x 64 lanes x 2 flop (FMA) x 2.4 GHz, packed FP32 disabled
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
+FP32_PEAK_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; packed FP32 is not used
+NWAVE, NSYM, RHO_A, RHO_D = 64, 32768, 4, 2
+NSPAN, SPAN_KM, CH_STEPS = 10, 100.0, 100
+LDBP_STPS, TAPS = 5, 15
+P_DBM = 4.0
+RS = 10.7e9
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ldbp_fwd_traffic.json")
+KERNEL_SOURCES = ["paper_2010_14258_amd/csrc/ldbp_fwd.hip", "paper_2010_14258_amd/csrc/ldbp_fir.h",
+                  "paper_2010_14258_amd/csrc/common.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def fwd_flops_per_sample_step(T: int) -> int:
-    # general complex FIR: T complex multiplies (6 flops) + T-1 complex adds (2) = 8T - 2;
-    # Kerr: |u|^2 (3) + c * p (1) + rotation (complex multiply, 6) = 10.  Transcendentals not counted.
+    # general complex FIR: T complex multiplies (6 flops) + T-1 complex additions (2) = 8T - 2;
+    # Kerr: |u|^2 (3) + c |u|^2 (1) + rotation, a complex multiply (6) = 10; sine/cosine not counted.
     return 8 * T - 2 + 10
+
+
+def event_time(torch, stream, fn, steps: int, warmup: int):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def build_workload(torch, dev, cheap: bool = False):
+    from paper_2010_14258_amd import init as I
+    from paper_2010_14258_amd import ssm as SS
+    from paper_2010_14258_amd import txrx as TX
+
+    alpha = I.db_per_km_to_alpha(0.2)
+    beta2 = I.ps2_per_km_to_beta2(-21.683)
+    gamma = 1.3e-3
+    span = SPAN_KM * 1e3
+    fs_a, fs_d = RHO_A * RS, RHO_D * RS
+    p = torch.full((NWAVE,), I.dbm_to_w(P_DBM), dtype=torch.float64, device=dev)
+    words = TX.randbits(NWAVE * NSYM, 201, 0, device=dev).view(NWAVE, NSYM)
+    if cheap:
+        # kernel-trace and counter runs: same shapes and power, without the channel simulation
+        r = TX.randn((NWAVE, RHO_D * NSYM), 203, 0, dtype=torch.complex64, device=dev) * math.sqrt(I.dbm_to_w(P_DBM))
+    else:
+        x = TX.tx_shape(words, p, RHO_A, RS, dtype=torch.complex64)
+        noise = TX.randn((NSPAN,) + tuple(x.shape), 202, 0, dtype=torch.complex64, device=dev)
+        ch = SS.Link(fs=fs_a, alpha=alpha, beta2=beta2, gamma=gamma, span_len=span, nspan=NSPAN, nstep=CH_STEPS,
+                     edfa_gain=True, ase_var=I.ase_variance(alpha, span, 5.0, fs_a))
+        SS.ssm_channel(x, ch, noise=noise, y=x)
+        del noise
+        r = TX.rx_lpf_decimate(x, RHO_D * NSYM)
+        del x
+    s = TX.qam16_symbols(words, dtype=torch.complex64)
+    taps, c = I.ldbp_parameters(span, NSPAN, LDBP_STPS, TAPS, fs_d, alpha, beta2, gamma)
+    ntap = [len(h) for h in taps]
+    tt = torch.from_numpy(np.concatenate(taps)).to(dev, torch.complex64)
+    ct = torch.from_numpy(c).to(dev, torch.float32)
+
+    def dbp_link(k):
+        return SS.Link(fs=fs_d, alpha=alpha, beta2=beta2, gamma=gamma, span_len=span, nspan=NSPAN, nstep=k,
+                       step_len=I.log_step_sizes(span, k, alpha), edfa_gain=True)
+
+    return dict(r=r.contiguous(), s=s, p=p, taps=tt, c=ct, ntap=ntap, dbp_link=dbp_link)
+
+
+def snr_db(TX, z, s, p):
+    mse, _, _ = TX.rx_mse(z, s, p, RHO_D, RS)
+    return 10.0 * math.log10(1.0 / float(mse.mean().item()))
 
 
 def main():
@@ -39,116 +117,162 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-waves", type=int, default=8, help="waveforms in the oracle's bounded sample")
+    ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc"], default="full",
+                    help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print("bench.py runs on one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_2010_14258_amd import ldbp as G
     from paper_2010_14258_amd import _native
+    from paper_2010_14258_amd import ldbp as L
+    from paper_2010_14258_amd import ssm as SS
+    from paper_2010_14258_amd import txrx as TX
 
     _native.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-
-    nwave, n, L, T = 64, 65536, 50, 15
-    # Inputs generated on the GPU: received-like complex Gaussian samples at 4 dBm
-    # (mean power 2.5 mW) and 15-tap filters with the magnitude profile of the
-    # least-squares inverse-dispersion taps of a 20 km step (unit energy).
-    g = torch.Generator(device=dev)
-    g.manual_seed(201)
-    p = 10 ** ((4.0 - 30) / 10)
-    x = (torch.randn((nwave, n), dtype=torch.complex64, device=dev, generator=g) * math.sqrt(p)).contiguous()
-    k = torch.arange(-(T // 2), T // 2 + 1, device=dev, dtype=torch.float64)
-    xi = 0.0993
-    h = torch.exp(1j * (-(k ** 2) / (4 * xi) + math.pi / 4)) * torch.exp(-(k / 6.0) ** 2)
-    h = (h / torch.linalg.vector_norm(h)).to(torch.complex64)
-    taps = h.repeat(L).contiguous()
-    c = torch.full((L,), -1.3e-3 * 8e3, dtype=torch.float32, device=dev)
-    ntap = [T] * L
-    y = torch.empty_like(x)
-    wsz = G.ldbp_forward_workspace_size(x, ntap)
-    ws = torch.empty(max(wsz, 1), dtype=torch.uint8, device=dev)
-
     stream = torch.cuda.current_stream(dev)
+    W = build_workload(torch, dev, cheap=args.mode != "full")
+    r, taps, c, ntap = W["r"], W["taps"], W["c"], W["ntap"]
+    nwave, n = r.shape
+    ell = len(ntap)
+    y = torch.empty_like(r)
+    ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap), 1), dtype=torch.uint8, device=dev)
 
-    def step():
-        G.ldbp_forward(x, taps, c, ntap, y=y, ws=ws, stream=stream)
+    def fwd():
+        L.ldbp_forward(r, taps, c, ntap, y=y, ws=ws, stream=stream)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    if args.mode == "pmc":
+        for _ in range(3):
+            fwd()
+        big = torch.empty(64 << 20, dtype=torch.complex64, device=dev)   # 512 MiB copy probe
+        dst = torch.empty_like(big)
+        for _ in range(3):
+            dst.copy_(big)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "fwd_launches": 3 * L.ldbp_forward_plan_query(0, 1, nwave, n, ntap)[0],
+                          "copy_bytes": 2 * big.numel() * 8, "kernel_hash": kernel_hash()}))
+        return
+
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step()
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms_fwd = event_time(torch, stream, fwd, args.steps, args.warmup)
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    ms_per_step = ms / args.steps
-    ss = nwave * n * L
-    value = ss / (ms_per_step * 1e-3)
-
-    # launches per forward: same pass split the library uses
-    from paper_2010_14258_amd._native import load as _load  # noqa: F401
-    npass = _passes(L, T)
-    launch_ms = ms_per_step / npass
-    flops_launch = ss * fwd_flops_per_sample_step(T) / npass
+    npass, tile_len, spp = L.ldbp_forward_plan_query(0, 1, nwave, n, ntap)
+    ss = nwave * n * ell
+    value = ss / (ms_fwd * 1e-3)
+    launch_ms = ms_fwd / npass
+    flops_launch = nwave * n * sum(fwd_flops_per_sample_step(t) for t in ntap) / npass
     achieved_tflops = flops_launch / (launch_ms * 1e-3) / 1e12
-    bytes_launch = nwave * n * 8 * 2  # read + write one complex64 per sample per pass
+    bytes_launch = nwave * n * 8 * 2
     achieved_gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == [nwave, n, ell, TAPS]:
+            traffic = tr.get("bytes_per_launch")
 
     out = {
-        "metric": "samples*steps/s LDBP forward (equalised waveform samples x LDBP steps per second)",
+        "metric": "samples*steps/s of the LDBP forward (waveform samples x LDBP steps per second)",
         "value": value,
         "unit": "samples*steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms_fwd,
         "wall_s": wall,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "c64",
-        "data": "synthetic",
-        "config": {"workload": "LDBP inference 64 x 65536 c64, l=50 steps (5/span), 15 taps", "nwave": nwave,
-                   "n": n, "steps_l": L, "taps": T, "passes": npass},
+        "data": "synthetic: GPU-simulated 16-QAM over 10 x 100 km SSMF with ASE (library kernels)",
+        "config": {"workload": "LDBP inference, 64 waveforms x 65,536 c64 samples, l = 50 (5 steps/span), 15 taps",
+                   "nwave": nwave, "n": n, "steps_l": ell, "taps": TAPS, "launch_dbm": P_DBM,
+                   "passes": npass, "tile_len": tile_len, "steps_per_pass": spp},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": None,
-                     "hbm_achieved_gbs": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
-                     "kernel": "ldbp_fwd_kernel<float,1,8,256>", "launch_ms": launch_ms},
+                     "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
+                     "kernel": "ldbp_fwd_kernel<float,1,8,256>", "launch_ms": launch_ms,
+                     "flops_per_launch": flops_launch, "algorithmic_bytes_per_launch": bytes_launch,
+                     "hbm_achieved_gbs": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_waves, n, L, T)
+
+    if args.mode == "full":
+        # forward with block checkpoints + backward
+        S = 5
+        ck = torch.empty((L.num_checkpoints(ell, S),) + tuple(r.shape), dtype=r.dtype, device=dev)
+        z = L.ldbp_forward(r, taps, c, ntap)
+        _, _, gy = TX.rx_mse(z, W["s"], W["p"], RHO_D, RS, want_grad=True)
+        bws = torch.empty(L.ldbp_backward_workspace_size(r, ntap, ckpt=ck, ckpt_every=S), dtype=torch.uint8,
+                          device=dev)
+
+        def fwd_bwd():
+            L.ldbp_forward(r, taps, c, ntap, y=y, ckpt=ck, ckpt_every=S, stream=stream)
+            L.ldbp_backward(r, taps, c, ntap, gy, ckpt=ck, ckpt_every=S, need_gx=False, ws=bws, stream=stream)
+
+        ms_fb = event_time(torch, stream, fwd_bwd, max(5, args.steps // 5), 2)
+        out["fwd_bwd"] = {"value": ss / (ms_fb * 1e-3), "unit": "samples*steps/s", "ms_per_step": ms_fb,
+                          "ckpt_every": S}
+        # equal-SNR comparison with FFT-DBP on the same waveforms
+        snr_ldbp = snr_db(TX, z, W["s"], W["p"])
+        sweep = {}
+        chosen = None
+        for k in (1, 2, 3, 5, 10, 20):
+            link = W["dbp_link"](k)
+            zd = SS.fft_dbp(r, link)
+            sweep[k] = snr_db(TX, zd, W["s"], W["p"])
+            if chosen is None and sweep[k] >= snr_ldbp - 0.1:
+                chosen = k
+        k = chosen if chosen is not None else max(sweep)
+        link = W["dbp_link"](k)
+        yd = torch.empty_like(r)
+        dws = torch.empty(SS.ssm_workspace_size(r, link), dtype=torch.uint8, device=dev)
+        ms_dbp = event_time(torch, stream, lambda: SS.fft_dbp(r, link, y=yd, ws=dws, stream=stream),
+                            max(3, args.steps // 10), 1)
+        link1 = W["dbp_link"](1)
+        ms_dbp1 = event_time(torch, stream, lambda: SS.fft_dbp(r, link1, y=yd, ws=dws, stream=stream),
+                             max(3, args.steps // 10), 1)
+        out["equal_snr"] = {
+            "ldbp_snr_db": snr_ldbp, "fft_dbp_snr_db_by_steps_per_span": sweep,
+            "fft_dbp_steps_per_span": k, "fft_dbp_reaches_ldbp_snr": chosen is not None,
+            "ldbp_equalised_samples_per_s": nwave * n / (ms_fwd * 1e-3),
+            "fft_dbp_equalised_samples_per_s": nwave * n / (ms_dbp * 1e-3),
+            "ldbp_speedup_at_equal_snr": ms_dbp / ms_fwd,
+            "fft_dbp_1stps_samples_steps_per_s": nwave * n * NSPAN / (ms_dbp1 * 1e-3),
+            "fft_dbp_1stps_ms": ms_dbp1,
+        }
+        # one iteration of the 32 x 16,384 training configuration (l = 50, 25 taps, channel 1,000 steps)
+        from paper_2010_14258_amd import train as TRN
+        trn = TRN.Trainer(TRN.TrainConfig(iters=5000), device=dev)
+        trn.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(3):
+            trn.step()
+        torch.cuda.synchronize()
+        out["train_iteration_ms"] = (time.perf_counter() - t1) / 3 * 1e3
+
+    if not args.no_cpu_baseline and args.mode == "full":
+        out["cpu_baseline"] = cpu_baseline(args.cpu_waves, n, ntap)
     print(json.dumps(out), flush=True)
 
 
-def _passes(L, T):
-    # mirrors the library's default pass split: steps join a pass while 2*halo*8 <= 2048
-    K = (T - 1) // 2
-    per = max(1, min(64, 2048 // (16 * K))) if K > 0 else 64
-    return math.ceil(L / per)
-
-
-def cpu_baseline(nw, n, L, T):
-    """The FP64 oracle (plain NumPy, not tuned) on a bounded sample of the same workload."""
+def cpu_baseline(nw, n, ntap):
+    """The FP64 oracle (plain NumPy, not tuned) on a bounded sample of the same workload shape."""
     import synth
     from oracle import ldbp as O
 
-    taps = synth.random_taps(1, [T] * L)
-    c = np.full(L, -1e-2)
+    taps = synth.random_taps(1, ntap)
+    c = np.full(len(ntap), -1e-2)
     x = synth.complex_normal(2, (nw, n)) * 0.05
     t0 = time.perf_counter()
     O.ldbp_forward(x, taps, c)
     dt = time.perf_counter() - t0
-    return {"value": nw * n * L / dt, "unit": "samples*steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nw} of 64 waveforms x {n} samples x {L} steps, FP64 NumPy, single process ({dt:.1f} s)"}
+    return {"value": nw * n * len(ntap) / dt, "unit": "samples*steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{nw} of 64 waveforms x {n} samples x {len(ntap)} steps ({len(ntap) * ntap[0]} taps), "
+                      f"FP64 NumPy direct convolution, single process, {dt:.1f} s"}
 
 
 if __name__ == "__main__":

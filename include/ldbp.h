@@ -106,6 +106,12 @@ int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
                  const void* x, void* y, void* ckpt, int32_t ckpt_every,
                  const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream);
 
+/* Execution plan the forward would use: number of passes (kernel launches), the shortest tile
+ * length over the passes, and the largest number of fused steps in a pass.  Host only. */
+int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                            const int32_t* ntap, int32_t ckpt_every, const ldbp_plan* plan, int32_t* npasses,
+                            int32_t* tile_len, int32_t* max_steps_per_pass);
+
 /* ---------------------------------------------------------------------------
  * LDBP backward: gradients of a real loss L through y = f_theta(x).  The paper
  * trains the model with standard tools (Sec. IV-B); this is the chain rule of

@@ -300,3 +300,25 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
   }
   return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s);
 }
+
+extern "C" int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                       const int32_t* ntap, int32_t ckpt_every, const ldbp_plan* plan,
+                                       int32_t* npasses, int32_t* tile_len, int32_t* max_steps_per_pass) {
+  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+  int st = check_model(m);
+  if (st) return st;
+  if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
+    return fail(LDBP_EINVAL, "ckpt_every %d outside [0, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
+  PassPlan pp;
+  st = make_plan(m, ckpt_every, plan, pp);
+  if (st) return st;
+  int maxs = 0, minlen = 1 << 30;
+  for (const auto& pt : pp.passes) {
+    maxs = std::max(maxs, pt.nstep);
+    minlen = std::min(minlen, pp.chunks * fwd_chunk(dtype, npol) - 2 * pt.halo);
+  }
+  if (npasses) *npasses = static_cast<int32_t>(pp.passes.size());
+  if (tile_len) *tile_len = minlen;
+  if (max_steps_per_pass) *max_steps_per_pass = maxs;
+  return LDBP_OK;
+}

@@ -79,6 +79,18 @@ def ldbp_forward_workspace_size(x: torch.Tensor, ntap: Sequence[int], npol: int 
     return int(out.value)
 
 
+def ldbp_forward_plan_query(dtype: int, npol: int, nwave: int, n: int, ntap: Sequence[int], ckpt_every: int = 0,
+                            plan=None):
+    """(passes, shortest tile length, most steps fused in a pass) of the forward's execution plan."""
+    lib = N.load()
+    a, b, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    pl = _plan(plan)
+    N.check(lib.ldbp_forward_plan_query(dtype, npol, nwave, n, len(ntap), N.i32_array(ntap), int(ckpt_every),
+                                        ctypes.byref(pl) if pl is not None else None, ctypes.byref(a),
+                                        ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
 def ldbp_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], npol: int = 1,
                  y: Optional[torch.Tensor] = None, ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
                  plan=None, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
