@@ -56,17 +56,25 @@ enum ldbp_dtype { LDBP_C64 = 0, LDBP_C128 = 1 };
 #define LDBP_MAX_TAPS 63 /* largest odd filter length per step */
 #define LDBP_MAX_STEPS_PER_PASS 64
 
-/* Execution plan of the time-blocked kernels.  Zero fields mean "choose".
- *   steps_per_pass  S: number of consecutive FIR+Kerr steps fused in one pass
- *                   (the signal stays in LDS between them; a halo of sum K over
- *                   the S steps is recomputed at each tile edge).
- *   chunks          LDS work size in units of the kernel's chunk (threads x outputs
- *                   per thread); the tile length is chunks*chunk - 2*halo.        */
+/* Execution plan of the time-blocked forward.  Zero fields mean "choose".
+ *   steps_per_pass      S: number of consecutive FIR+Kerr steps fused in one pass
+ *                       (the signal stays in LDS between them; a halo of sum K over
+ *                       the S steps is recomputed at each tile edge).
+ *   chunks              LDS work size in units of the kernel's chunk (256 threads x
+ *                       outputs per thread); the tile length is chunks*chunk - 2*halo.
+ *   outputs_per_thread  consecutive outputs each thread computes from one register window
+ *                       (c64: 7, 8, 9 for npol 1, 3, 4, 5 for npol 2; c128: 3, 4 / 1, 2).
+ *   flags               LDBP_PLAN_SYMMETRIC: the caller guarantees h_{-k} = h_k for every
+ *                       filter; the forward then evaluates the folded form
+ *                       h_0 x_m + sum_{k>=1} h_k (x_{m-k} + x_{m+k}) (Sec. III-B).
+ * Results are bit-identical for any steps_per_pass and chunks at fixed
+ * outputs_per_thread and flags. */
+#define LDBP_PLAN_SYMMETRIC 1
 typedef struct ldbp_plan {
   int32_t steps_per_pass;
   int32_t chunks;
-  int32_t reserved0;
-  int32_t reserved1;
+  int32_t outputs_per_thread;
+  int32_t flags;
 } ldbp_plan;
 
 /* Library version string and status text. */

@@ -28,7 +28,11 @@ LDBP_C64, LDBP_C128 = 0, 1
 
 
 class LdbpPlan(ctypes.Structure):
-    _fields_ = [("steps_per_pass", c_int32), ("chunks", c_int32), ("reserved0", c_int32), ("reserved1", c_int32)]
+    _fields_ = [("steps_per_pass", c_int32), ("chunks", c_int32), ("outputs_per_thread", c_int32),
+                ("flags", c_int32)]
+
+
+LDBP_PLAN_SYMMETRIC = 1
 
 
 P_plan = ctypes.POINTER(LdbpPlan)

@@ -1,0 +1,120 @@
+"""Plan autotuner for the time-blocked LDBP forward.
+
+For a problem signature (device, dtype, npol, nwave, n, tap profile, symmetric) it times every
+plan in a candidate set -- outputs per thread x steps per pass x LDS chunks -- with HIP events on
+the caller's stream and keeps the fastest.  Results are cached in memory and, when a path is
+given (argument or LDBP_AUTOTUNE_CACHE), in a JSON file; a missing or unreadable cache file just
+means tuning again.  All candidates produce identical results for a fixed outputs-per-thread
+and symmetry flag; across those the results agree to rounding.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, List, Optional, Sequence, Tuple
+
+import torch
+
+from . import _native as N
+from . import ldbp as L
+
+_MEM: Dict[str, dict] = {}
+
+RB_CHOICES = {(N.LDBP_C64, 1): (7, 8, 9), (N.LDBP_C64, 2): (3, 4, 5),
+              (N.LDBP_C128, 1): (3, 4), (N.LDBP_C128, 2): (1, 2)}
+
+
+def signature(x: torch.Tensor, ntap: Sequence[int], npol: int, symmetric: bool) -> str:
+    code = L._code(x)
+    nwave, n = L._shape(x, npol)
+    name = torch.cuda.get_device_name(x.device)
+    prof = ",".join(str(int(t)) for t in ntap)
+    return f"{name}|{code}|{npol}|{nwave}|{n}|{prof}|{int(bool(symmetric))}"
+
+
+def _load(path: Optional[str]) -> dict:
+    if not path or not os.path.exists(path):
+        return {}
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+        return data if isinstance(data, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: Optional[str], data: dict) -> None:
+    if not path:
+        return
+    tmp = path + ".tmp"
+    try:
+        with open(tmp, "w") as fh:
+            json.dump(data, fh, indent=1)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def candidates(code: int, npol: int, nstep: int, symmetric: bool) -> List[Tuple[int, int, int, int]]:
+    steps = sorted({s for s in (1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 16, 18, 20, 25, 32, 40, 50, 64) if s <= nstep}
+                   | {min(nstep, 64)})
+    out = []
+    for rb in RB_CHOICES[(code, npol)]:
+        for s in steps:
+            for ch in (1, 2):
+                out.append((s, ch, rb, 1 if symmetric else 0))
+    return out
+
+
+def _time(fn, stream, reps: int) -> float:
+    fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], npol: int = 1,
+                 symmetric: bool = False, reps: int = 5, cache_path: Optional[str] = None,
+                 plans: Optional[Iterable[Tuple[int, int, int, int]]] = None, stream=None):
+    """Returns (best plan tuple, best ms, list of (plan, ms)) for y = ldbp_forward(x, ...)."""
+    cache_path = cache_path or os.environ.get("LDBP_AUTOTUNE_CACHE")
+    key = signature(x, ntap, npol, symmetric)
+    if key in _MEM:
+        e = _MEM[key]
+        return tuple(e["plan"]), e["ms"], e.get("table", [])
+    disk = _load(cache_path)
+    if key in disk and isinstance(disk[key].get("plan"), list) and len(disk[key]["plan"]) == 4:
+        _MEM[key] = disk[key]
+        return tuple(disk[key]["plan"]), disk[key]["ms"], disk[key].get("table", [])
+    stream = stream or torch.cuda.current_stream(x.device)
+    y = torch.empty_like(x)
+    code = L._code(x)
+    table = []
+    ws_cache = {}
+    for plan in (plans or candidates(code, npol, len(ntap), symmetric)):
+        try:
+            need = L.ldbp_forward_workspace_size(x, ntap, npol, plan=plan)
+        except N.LdbpError:
+            continue
+        if need not in ws_cache:
+            ws_cache[need] = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+        ws = ws_cache[need]
+        fn = lambda: L.ldbp_forward(x, taps, c, ntap, npol=npol, y=y, plan=plan, ws=ws, stream=stream)
+        try:
+            ms = _time(fn, stream, reps)
+        except N.LdbpError:
+            continue
+        table.append((list(plan), ms))
+    if not table:
+        raise RuntimeError("no forward plan could run for this problem")
+    best = min(table, key=lambda t: t[1])
+    entry = {"plan": best[0], "ms": best[1], "table": table}
+    _MEM[key] = entry
+    disk[key] = entry
+    _store(cache_path, disk)
+    return tuple(best[0]), best[1], table

@@ -31,9 +31,9 @@ static int check_model(const ModelArgs& m) {
   return LDBP_OK;
 }
 
-static int max_chunks(int dtype, int npol) {
+static int max_chunks(int dtype, int npol, int rb) {
   int c = 1;
-  while (fwd_lds_bytes(dtype, npol, c + 1) <= kMaxLdsBytes) ++c;
+  while (fwd_lds_bytes(dtype, npol, rb, c + 1) <= kMaxLdsBytes) ++c;
   return c;
 }
 
@@ -43,12 +43,19 @@ static int max_chunks(int dtype, int npol) {
 struct PassPlan {
   std::vector<PassTable> passes;
   int chunks;
+  int rb;   // outputs per thread
+  int sym;  // folded evaluation of symmetric filters
 };
 
 static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* plan, PassPlan& out) {
-  const int chunk = fwd_chunk(m.dtype, m.npol);
+  const int rb = (plan && plan->outputs_per_thread > 0) ? plan->outputs_per_thread : fwd_rb_default(m.dtype, m.npol);
+  if (!fwd_rb_supported(m.dtype, m.npol, rb))
+    return fail(LDBP_EUNSUPPORTED, "outputs_per_thread %d not available for this dtype/npol", rb);
+  out.rb = rb;
+  out.sym = (plan && (plan->flags & LDBP_PLAN_SYMMETRIC)) ? 1 : 0;
+  const int chunk = fwd_chunk(m.dtype, m.npol, rb);
   int chunks = (plan && plan->chunks > 0) ? plan->chunks : 1;
-  const int cmax = max_chunks(m.dtype, m.npol);
+  const int cmax = max_chunks(m.dtype, m.npol, rb);
   if (chunks > cmax) return fail(LDBP_EINVAL, "plan chunks %d exceeds the LDS limit (%d)", chunks, cmax);
   const int fixed_s = ckpt_every > 0 ? ckpt_every : ((plan && plan->steps_per_pass > 0) ? plan->steps_per_pass : 0);
   if (fixed_s > LDBP_MAX_STEPS_PER_PASS)
@@ -156,7 +163,8 @@ extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
     if (i + 1 == np) out = y;
     else if (ckpt) out = static_cast<char*>(ckpt) + i * wave_bytes;
     else out = ((np - 1 - i) % 2 == 0) ? y : ws;
-    st = launch_fwd_pass(dtype, npol, in, out, nwave, static_cast<int32_t>(n), pp.chunks, pp.passes[i], taps, c, s);
+    st = launch_fwd_pass(dtype, npol, pp.rb, in, out, nwave, static_cast<int32_t>(n), pp.chunks, pp.passes[i], taps, c,
+                         pp.sym, s);
     if (st) return st;
     in = out;
   }
@@ -283,8 +291,8 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
     const void* in = x;
     for (size_t i = 0; i + 1 < nb; ++i) {
       void* out = wsb + L.off_ckpt + i * wave_bytes;
-      st = launch_fwd_pass(dtype, npol, in, out, nwave, static_cast<int32_t>(n), L.blocks.chunks,
-                           L.blocks.passes[i], taps, c, s);
+      st = launch_fwd_pass(dtype, npol, L.blocks.rb, in, out, nwave, static_cast<int32_t>(n), L.blocks.chunks,
+                           L.blocks.passes[i], taps, c, 0, s);
       if (st) return st;
       in = out;
     }
@@ -315,7 +323,7 @@ extern "C" int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwav
   int maxs = 0, minlen = 1 << 30;
   for (const auto& pt : pp.passes) {
     maxs = std::max(maxs, pt.nstep);
-    minlen = std::min(minlen, pp.chunks * fwd_chunk(dtype, npol) - 2 * pt.halo);
+    minlen = std::min(minlen, pp.chunks * fwd_chunk(dtype, npol, pp.rb) - 2 * pt.halo);
   }
   if (npasses) *npasses = static_cast<int32_t>(pp.passes.size());
   if (tile_len) *tile_len = minlen;

@@ -8,7 +8,11 @@ namespace ldbp {
 
 // out[j] = sigma(sum_{k=-K}^{K} h_k in[j-k]) for j in [lo, hi), RB consecutive outputs per thread
 // from a register window of RB + 2K inputs.  Reads in[lo-K, hi+RB+K-2]; writes out[lo, hi).
-template <typename R, int NPOL, int RB, int THREADS, int K>
+// SYM: the caller guarantees h_{-k} = h_k and the sum is evaluated folded,
+// h_0 x_m + sum_{k>=1} h_k (x_{m-k} + x_{m+k}) (the folded structure of Sec. III-B), which
+// needs K + 1 complex multiplies instead of 2K + 1.
+// An odd RB keeps the lanes' window starts on distinct LDS banks (stride RB * 8 bytes).
+template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM>
 __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out,
                                                int lo, int hi, const cx_t<R>* __restrict__ h, R coef) {
   using V = cx_t<R>;
@@ -20,17 +24,39 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
 #pragma unroll
       for (int p = 0; p < NPOL; ++p) win[j][p] = in[(base - K + j) * NPOL + p];
     V acc[RB][NPOL];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
-#pragma unroll
-    for (int k = -K; k <= K; ++k) {
-      const V hk = h[K + k];
+    if constexpr (SYM) {
+      const V h0 = h[K];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) cmac(acc[r][p], hk, win[r - k + K][p]);  // x_{m-k}, m = base + r
+        for (int p = 0; p < NPOL; ++p) {
+          const V c = win[r + K][p];
+          acc[r][p] = V{h0.x * c.x - h0.y * c.y, h0.x * c.y + h0.y * c.x};
+        }
+#pragma unroll
+      for (int k = 1; k <= K; ++k) {
+        const V hk = h[K + k];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int p = 0; p < NPOL; ++p) {
+            const V a = win[r + K - k][p], b = win[r + K + k][p];
+            cmac(acc[r][p], hk, V{a.x + b.x, a.y + b.y});
+          }
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
+#pragma unroll
+      for (int k = -K; k <= K; ++k) {
+        const V hk = h[K + k];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int p = 0; p < NPOL; ++p) cmac(acc[r][p], hk, win[r - k + K][p]);  // x_{m-k}, m = base + r
+      }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
@@ -90,12 +116,12 @@ __device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in,
   }
 }
 
-template <typename R, int NPOL, int RB, int THREADS>
-__device__ __forceinline__ void fir_kerr_dispatch(const cx_t<R>* in, cx_t<R>* out, int lo, int hi, int K,
-                                                  const cx_t<R>* h, R coef) {
+template <typename R, int NPOL, int RB, int THREADS, bool SYM>
+__device__ __forceinline__ void fir_kerr_dispatch_t(const cx_t<R>* in, cx_t<R>* out, int lo, int hi, int K,
+                                                    const cx_t<R>* h, R coef) {
   switch (K) {
 #define LDBP_FWD_CASE(k) \
-  case k: fir_kerr_fixed<R, NPOL, RB, THREADS, k>(in, out, lo, hi, h, coef); break;
+  case k: fir_kerr_fixed<R, NPOL, RB, THREADS, k, SYM>(in, out, lo, hi, h, coef); break;
     LDBP_FWD_CASE(0) LDBP_FWD_CASE(1) LDBP_FWD_CASE(2) LDBP_FWD_CASE(3)
     LDBP_FWD_CASE(4) LDBP_FWD_CASE(5) LDBP_FWD_CASE(6) LDBP_FWD_CASE(7)
     LDBP_FWD_CASE(8) LDBP_FWD_CASE(9) LDBP_FWD_CASE(10) LDBP_FWD_CASE(11)
@@ -103,6 +129,13 @@ __device__ __forceinline__ void fir_kerr_dispatch(const cx_t<R>* in, cx_t<R>* ou
 #undef LDBP_FWD_CASE
     default: fir_kerr_generic<R, NPOL, RB, THREADS>(in, out, lo, hi, K, h, coef); break;
   }
+}
+
+template <typename R, int NPOL, int RB, int THREADS>
+__device__ __forceinline__ void fir_kerr_dispatch(const cx_t<R>* in, cx_t<R>* out, int lo, int hi, int K,
+                                                  const cx_t<R>* h, R coef, bool sym = false) {
+  if (sym) fir_kerr_dispatch_t<R, NPOL, RB, THREADS, true>(in, out, lo, hi, K, h, coef);
+  else fir_kerr_dispatch_t<R, NPOL, RB, THREADS, false>(in, out, lo, hi, K, h, coef);
 }
 
 // Loads samples [t0 - H, t0 + Lw + H) of one waveform (circularly) into LDS.

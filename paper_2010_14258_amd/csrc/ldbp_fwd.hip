@@ -20,7 +20,7 @@ template <typename R, int NPOL, int RB, int THREADS>
 __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __restrict__ x, cx_t<R>* __restrict__ y,
                                                            int32_t n, int32_t tile_len, int32_t ntiles,
                                                            int32_t work, const cx_t<R>* __restrict__ taps,
-                                                           const R* __restrict__ c, PassTable pt) {
+                                                           const R* __restrict__ c, PassTable pt, int32_t sym) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   V* b0 = reinterpret_cast<V*>(smem);
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
     const int K = pt.K[s];
     lo += K;
     const R coef = c[pt.c0 + s] * phase_coef_scale<R>();
-    fir_kerr_dispatch<R, NPOL, RB, THREADS>(b0, b1, lo, W0 - lo, K, taps + pt.tapoff[s], coef);
+    fir_kerr_dispatch<R, NPOL, RB, THREADS>(b0, b1, lo, W0 - lo, K, taps + pt.tapoff[s], coef, sym != 0);
     __syncthreads();
     V* t = b0;
     b0 = b1;
@@ -58,52 +58,65 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
 
 // ---------------------------------------------------------------- host side
 
-template <typename R, int NPOL> struct FwdCfg;
-template <> struct FwdCfg<float, 1> { static constexpr int RB = 8, THREADS = 256; };
-template <> struct FwdCfg<float, 2> { static constexpr int RB = 4, THREADS = 256; };
-template <> struct FwdCfg<double, 1> { static constexpr int RB = 4, THREADS = 256; };
-template <> struct FwdCfg<double, 2> { static constexpr int RB = 2, THREADS = 256; };
+// Outputs per thread (RB) available for each real type and polarisation count; the chunk of a
+// workgroup is 256 * RB samples.  Index 0 is the default.
+static constexpr int kThreads = 256;
 
-int fwd_chunk(int dtype, int npol) {
-  if (dtype == LDBP_C64) return npol == 1 ? 8 * 256 : 4 * 256;
-  return npol == 1 ? 4 * 256 : 2 * 256;
+int fwd_rb_default(int dtype, int npol) {
+  if (dtype == LDBP_C64) return npol == 1 ? 7 : 3;
+  return npol == 1 ? 3 : 1;
 }
 
-size_t fwd_lds_bytes(int dtype, int npol, int chunks) {
-  const int rb = fwd_chunk(dtype, npol) / 256;
-  return 2 * static_cast<size_t>(chunks * fwd_chunk(dtype, npol) + rb) * npol * cx_size(dtype);
+bool fwd_rb_supported(int dtype, int npol, int rb) {
+  if (dtype == LDBP_C64) return npol == 1 ? (rb == 7 || rb == 8 || rb == 9) : (rb == 3 || rb == 4 || rb == 5);
+  return npol == 1 ? (rb == 3 || rb == 4) : (rb == 1 || rb == 2);
 }
 
-template <typename R, int NPOL>
+int fwd_chunk(int dtype, int npol, int rb) {
+  (void)dtype;
+  (void)npol;
+  return kThreads * rb;
+}
+
+size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks) {
+  return 2 * static_cast<size_t>(chunks * fwd_chunk(dtype, npol, rb) + rb) * npol * cx_size(dtype);
+}
+
+template <typename R, int NPOL, int RB>
 static int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
-                             const PassTable& pt, const void* taps, const void* c, hipStream_t stream) {
-  using Cfg = FwdCfg<R, NPOL>;
-  const int work = chunks * Cfg::RB * Cfg::THREADS;
+                             const PassTable& pt, const void* taps, const void* c, int sym, hipStream_t stream) {
+  const int work = chunks * RB * kThreads;
   const int tile_len = work - 2 * pt.halo;
   if (tile_len < 1) return fail(LDBP_EINVAL, "pass halo %d too large for work size %d", pt.halo, work);
   const int64_t ntiles = (n + tile_len - 1) / tile_len;
   const int64_t nblocks = ntiles * nwave;
   if (nblocks > 0x7fffffffLL) return fail(LDBP_EUNSUPPORTED, "grid too large (%lld blocks)", (long long)nblocks);
-  const size_t lds = 2 * static_cast<size_t>(work + Cfg::RB) * NPOL * sizeof(cx_t<R>);
-  auto kern = ldbp_fwd_kernel<R, NPOL, Cfg::RB, Cfg::THREADS>;
+  const size_t lds = 2 * static_cast<size_t>(work + RB) * NPOL * sizeof(cx_t<R>);
+  auto kern = ldbp_fwd_kernel<R, NPOL, RB, kThreads>;
   if (lds > 65536) LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
                                                       static_cast<int>(lds)));
-  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(nblocks)), dim3(Cfg::THREADS), lds, stream,
+  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(nblocks)), dim3(kThreads), lds, stream,
                      static_cast<const cx_t<R>*>(x), static_cast<cx_t<R>*>(y), n, tile_len,
                      static_cast<int32_t>(ntiles), work, static_cast<const cx_t<R>*>(taps),
-                     static_cast<const R*>(c), pt);
+                     static_cast<const R*>(c), pt, sym);
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }
 
-int launch_fwd_pass(int dtype, int npol, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
-                    const PassTable& pt, const void* taps, const void* c, hipStream_t stream) {
-  if (dtype == LDBP_C64)
-    return npol == 1 ? launch_fwd_pass_t<float, 1>(x, y, nwave, n, chunks, pt, taps, c, stream)
-                     : launch_fwd_pass_t<float, 2>(x, y, nwave, n, chunks, pt, taps, c, stream);
-  return npol == 1 ? launch_fwd_pass_t<double, 1>(x, y, nwave, n, chunks, pt, taps, c, stream)
-                   : launch_fwd_pass_t<double, 2>(x, y, nwave, n, chunks, pt, taps, c, stream);
+int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                    const PassTable& pt, const void* taps, const void* c, int sym, hipStream_t stream) {
+#define LDBP_FWD_LAUNCH(R, NP, B) \
+  if (npol == NP && rb == B) return launch_fwd_pass_t<R, NP, B>(x, y, nwave, n, chunks, pt, taps, c, sym, stream);
+  if (dtype == LDBP_C64) {
+    LDBP_FWD_LAUNCH(float, 1, 7) LDBP_FWD_LAUNCH(float, 1, 8) LDBP_FWD_LAUNCH(float, 1, 9)
+    LDBP_FWD_LAUNCH(float, 2, 3) LDBP_FWD_LAUNCH(float, 2, 4) LDBP_FWD_LAUNCH(float, 2, 5)
+  } else {
+    LDBP_FWD_LAUNCH(double, 1, 3) LDBP_FWD_LAUNCH(double, 1, 4)
+    LDBP_FWD_LAUNCH(double, 2, 1) LDBP_FWD_LAUNCH(double, 2, 2)
+  }
+#undef LDBP_FWD_LAUNCH
+  return fail(LDBP_EUNSUPPORTED, "outputs per thread %d not available for this dtype/npol", rb);
 }
 
 }  // namespace ldbp

@@ -19,12 +19,14 @@ struct PassTable {
   int32_t tapoff[LDBP_MAX_STEPS_PER_PASS];  // offsets into the packed taps
 };
 
-// Forward pass kernel geometry.
-int fwd_chunk(int dtype, int npol);
-size_t fwd_lds_bytes(int dtype, int npol, int chunks);
+// Forward pass kernel geometry: rb = outputs per thread, chunk = 256 * rb samples.
+int fwd_rb_default(int dtype, int npol);
+bool fwd_rb_supported(int dtype, int npol, int rb);
+int fwd_chunk(int dtype, int npol, int rb);
+size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks);
 
-int launch_fwd_pass(int dtype, int npol, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
-                    const PassTable& pt, const void* taps, const void* c, hipStream_t stream);
+int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                    const PassTable& pt, const void* taps, const void* c, int sym, hipStream_t stream);
 
 // Backward (adjoint) block kernel and the deterministic gradient reduction.
 size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt);

@@ -48,12 +48,14 @@ def _check_dev(name: str, t: torch.Tensor, dtype=None):
 
 
 def _plan(plan) -> Optional[N.LdbpPlan]:
+    """None, an LdbpPlan, or a tuple (steps_per_pass, chunks[, outputs_per_thread[, symmetric]])."""
     if plan is None:
         return None
     if isinstance(plan, N.LdbpPlan):
         return plan
-    s, ch = plan
-    return N.LdbpPlan(int(s), int(ch), 0, 0)
+    vals = list(plan) + [0] * (4 - len(plan))
+    s, ch, rb, sym = vals[:4]
+    return N.LdbpPlan(int(s), int(ch), int(rb), N.LDBP_PLAN_SYMMETRIC if sym else 0)
 
 
 def _shape(x: torch.Tensor, npol: int):

@@ -89,6 +89,11 @@ def test_plans_and_checkpoints_are_bitwise_identical():
     ref = _run(x, taps, c)
     for plan in [(1, 1), (3, 1), (7, 2), (30, 2), (13, 3)]:
         np.testing.assert_array_equal(_run(x, taps, c, plan=plan), ref)
+    for rb in (8, 9):
+        base = _run(x, taps, c, plan=(0, 0, rb))
+        assert _rel(base, ref) <= 1e-5
+        for plan in [(2, 1, rb), (11, 2, rb)]:
+            np.testing.assert_array_equal(_run(x, taps, c, plan=plan), base)
     # checkpoints: block inputs equal the oracle's intermediate signals
     tp, ntap = W.pack_taps(taps)
     xt = torch.from_numpy(x).to(DEV, torch.complex64)
@@ -134,3 +139,21 @@ def test_forward_full_size_64x65536_sampled():
     snr_gpu = X.effective_snr_db(X.phase_correct(X.matched_filter_downsample(y[sub], 2, p, W.RS), s[sub]), s[sub])
     snr_ref = X.effective_snr_db(X.phase_correct(X.matched_filter_downsample(ref, 2, p, W.RS), s[sub]), s[sub])
     assert abs(snr_gpu - snr_ref) <= 0.05
+
+
+@pytest.mark.parametrize("npol", [1, 2])
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, TOL64), (torch.complex128, TOL128)])
+def test_forward_symmetric_folded_evaluation(npol, dtype, tol):
+    """Folded evaluation h_0 x_m + sum_k h_k (x_{m-k} + x_{m+k}) for symmetric filters (Sec. III-B)."""
+    print("case: symmetric", npol, dtype, flush=True)
+    Ts = [15, 3, 5, 9, 25, 1, 7]
+    taps, c = _mixed_model(60, len(Ts), Ts, 0.3)
+    taps = [(h + h[::-1]) / 2 for h in taps]
+    shape = (3, 4099) if npol == 1 else (2, 3001, 2)
+    x = synth.complex_normal(61, shape) * 0.6
+    ref = O.ldbp_forward(x, taps, c, npol=npol)
+    rbs = {(torch.complex64, 1): (7, 8, 9), (torch.complex64, 2): (3, 4, 5),
+           (torch.complex128, 1): (3, 4), (torch.complex128, 2): (1, 2)}[(dtype, npol)]
+    for rb in rbs:
+        y = _run(x, taps, c, npol=npol, dtype=dtype, plan=(0, 0, rb, 1))
+        assert _rel(y, ref) <= tol, rb
