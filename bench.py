@@ -201,7 +201,7 @@ def main():
 
     if args.mode == "full":
         # forward with block checkpoints + backward
-        S = 5
+        S = 2
         ck = torch.empty((L.num_checkpoints(ell, S),) + tuple(r.shape), dtype=r.dtype, device=dev)
         z = L.ldbp_forward(r, taps, c, ntap)
         _, _, gy = TX.rx_mse(z, W["s"], W["p"], RHO_D, RS, want_grad=True)

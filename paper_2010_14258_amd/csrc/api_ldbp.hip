@@ -1,5 +1,6 @@
 // C ABI of the LDBP forward (and, later, backward): validation, planning, pass sequencing.
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "common.h"
@@ -175,7 +176,18 @@ extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
 
 namespace ldbp {
 
-constexpr size_t kBwdLdsBudget = 64 * 1024;
+constexpr size_t kBwdLdsBudget = 53 * 1024;   // three workgroups per CU
+
+// LDS budget of one backward workgroup; LDBP_BWD_LDS_KIB overrides it (a tuning knob: a smaller
+// budget gives more workgroups per CU, a larger one longer tiles and less halo recompute).
+static size_t bwd_lds_budget() {
+  const char* e = std::getenv("LDBP_BWD_LDS_KIB");
+  if (e) {
+    const long v = std::strtol(e, nullptr, 10);
+    if (v >= 16 && v <= 160) return static_cast<size_t>(v) * 1024;
+  }
+  return kBwdLdsBudget;
+}
 
 static size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
@@ -189,14 +201,14 @@ struct BwdLayout {
   size_t off_ckpt, off_g0, off_g1, off_part, total;
 };
 
-static int default_bwd_S(const ModelArgs& m) { return std::min<int32_t>(m.nstep, 5); }
+static int default_bwd_S(const ModelArgs& m) { return std::min<int32_t>(m.nstep, m.dtype == LDBP_C64 ? 2 : 3); }
 
 static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_every, BwdLayout& L) {
   L.S = ckpt_every > 0 ? ckpt_every : default_bwd_S(m);
   int st = make_plan(m, L.S, nullptr, L.blocks);
   if (st) return st;
   // tile length: the largest multiple of 64 whose LDS footprint fits the budget for every block
-  size_t budget = kBwdLdsBudget;
+  size_t budget = bwd_lds_budget();
   int best = 0;
   for (; budget <= kMaxLdsBytes && best == 0; budget += 32 * 1024) {
     for (int Lw = 4096; Lw >= 64; Lw -= 64) {

@@ -36,6 +36,29 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// DPP source operand: the value of another lane selected by `ctrl` (0 where masked or out of range).
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK,
+                                                               BANK_MASK, true));
+}
+
+// Sum over the 64 lanes of a wave using row shifts and row broadcasts (full-rate VALU adds, no
+// LDS round trip); the total is valid in lane 63 only.
+__device__ __forceinline__ float wave_sum_last(float v) {
+  float s = v + dpp_f32<0x111, 0xf, 0xf>(v);    // row_shr:1
+  s += dpp_f32<0x112, 0xf, 0xf>(v);             // row_shr:2
+  s += dpp_f32<0x113, 0xf, 0xf>(v);             // row_shr:3   -> lane i holds v[i-3..i] within its row
+  s += dpp_f32<0x114, 0xf, 0xe>(s);             // row_shr:4, banks 1-3 -> 8-lane partial sums
+  s += dpp_f32<0x118, 0xf, 0xc>(s);             // row_shr:8, banks 2-3 -> lane 15 of a row holds the row sum
+  s += dpp_f32<0x142, 0xa, 0xf>(s);             // row_bcast:15 into rows 1, 3
+  s += dpp_f32<0x143, 0xc, 0xf>(s);             // row_bcast:31 into rows 2, 3 -> lane 63 holds the total
+  return s;
+}
+__device__ __forceinline__ double wave_sum_last(double v) { return wave_sum(v); }
+
+constexpr int kLastLane = 63;
+
 // out[j] = sum_k conj(h_k) in[j+k] for j in [lo, hi); reads in[lo-K, hi+RB+K-2].
 template <typename R, int NPOL, int RB, int THREADS, int K>
 __device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
@@ -134,9 +157,9 @@ __device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, in
   const int wv = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < T; ++k) {
-    const R sx = wave_sum(acc[k].x);
-    const R sy = wave_sum(acc[k].y);
-    if (lane == 0) red[wv * ldr + col0 + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+    const R sx = wave_sum_last(acc[k].x);
+    const R sy = wave_sum_last(acc[k].y);
+    if (lane == kLastLane) red[wv * ldr + col0 + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
   }
 }
 
@@ -153,9 +176,9 @@ __device__ __forceinline__ void tapgrad_generic(const cx_t<R>* __restrict__ gu, 
     for (int j = own_lo + static_cast<int>(threadIdx.x); j < own_hi; j += THREADS)
 #pragma unroll
       for (int p = 0; p < NPOL; ++p) cmac_yconj(acc, gu[j * NPOL + p], yprev[(j + yshift - k) * NPOL + p]);
-    const R sx = wave_sum(acc.x);
-    const R sy = wave_sum(acc.y);
-    if (lane == 0) red[wv * ldr + col0 + K + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+    const R sx = wave_sum_last(acc.x);
+    const R sy = wave_sum_last(acc.y);
+    if (lane == kLastLane) red[wv * ldr + col0 + K + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
   }
 }
 
@@ -273,8 +296,8 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
       }
       if (i >= H && i < H + Lw) accc += q * pw;
     }
-    accc = wave_sum(accc);
-    if (lane == 0) red[wv * ldr + ntap_blk + (s - 1)] = double2{static_cast<double>(accc), 0.0};
+    accc = wave_sum_last(accc);
+    if (lane == kLastLane) red[wv * ldr + ntap_blk + (s - 1)] = double2{static_cast<double>(accc), 0.0};
     __syncthreads();
     // FIR adjoint into GA over [H - h_{s-1}, H + Lw + h_{s-1}); tap gradient over the owned range
     const int hprev = hs - K;
@@ -337,9 +360,10 @@ __global__ __launch_bounds__(256) void ldbp_grad_reduce(const double2* __restric
 // ---------------------------------------------------------------- host side
 
 template <typename R, int NPOL> struct BwdCfg;
-template <> struct BwdCfg<float, 1> { static constexpr int RB = 4, RB2 = 4, THREADS = 256; };
-template <> struct BwdCfg<float, 2> { static constexpr int RB = 2, RB2 = 2, THREADS = 256; };
-template <> struct BwdCfg<double, 1> { static constexpr int RB = 2, RB2 = 2, THREADS = 256; };
+// Odd window widths keep the lanes' LDS reads on distinct banks.
+template <> struct BwdCfg<float, 1> { static constexpr int RB = 5, RB2 = 5, THREADS = 256; };
+template <> struct BwdCfg<float, 2> { static constexpr int RB = 3, RB2 = 3, THREADS = 256; };
+template <> struct BwdCfg<double, 1> { static constexpr int RB = 3, RB2 = 3, THREADS = 256; };
 template <> struct BwdCfg<double, 2> { static constexpr int RB = 1, RB2 = 1, THREADS = 256; };
 
 static int bwd_pad(int dtype, int npol) {

@@ -56,7 +56,7 @@ class TrainConfig:
     npol: int = 1
     symmetric: bool = True
     train_c: bool = True
-    ckpt_every: int = 5
+    ckpt_every: int = 2
     seed: int = 301
     complex128: bool = False
     unit_init: bool = False
