@@ -153,6 +153,37 @@ int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t
                   void* gc, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Batched LDBP inference over uneven waveforms (eq. model for each waveform of the batch).
+ * Waveform b has wave_len[b] samples, wave_nstep[b] steps with tap counts
+ * step_ntap[sum_{j<b} wave_nstep[j] + s], its own taps and Kerr coefficients.  Packed layouts:
+ *   x, y   device [sum_b wave_len[b]][npol] complex (waveforms back to back)
+ *   taps   device, all steps of all waveforms back to back, each step ntap centred taps
+ *   c      device [sum_b wave_nstep[b]] real
+ * Every waveform is processed with all its steps fused in one pass (halo = sum of its K), so the
+ * whole batch is one kernel launch over independent (waveform, tile) items ordered by decreasing
+ * cost.  A waveform whose total halo exceeds the LDS work size is rejected (LDBP_EUNSUPPORTED).
+ * The plan owns small device tables (allocated by ldbp_batch_plan_create, freed by
+ * ldbp_batch_plan_destroy); the forward calls allocate nothing.
+ * -------------------------------------------------------------------------*/
+typedef struct ldbp_batch_plan ldbp_batch_plan;
+
+/* Host tables are copied; plan may be NULL (outputs_per_thread, chunks and flags are used). */
+int ldbp_batch_plan_create(int32_t dtype, int32_t npol, int32_t nwave, const int64_t* wave_len,
+                           const int32_t* wave_nstep, const int32_t* step_ntap, const ldbp_plan* plan,
+                           ldbp_batch_plan** out);
+int ldbp_batch_plan_destroy(ldbp_batch_plan* plan);
+/* Totals of the batch: samples, sample x steps, taps, steps; work items and LDS work size. */
+int ldbp_batch_plan_info(const ldbp_batch_plan* plan, int64_t* total_samples, int64_t* total_sample_steps,
+                         int64_t* total_taps, int64_t* total_steps, int32_t* nitems, int32_t* work);
+/* One launch on `stream`. */
+int ldbp_batch_forward(const ldbp_batch_plan* plan, const void* taps, const void* c, const void* x, void* y,
+                       void* stream);
+/* The same launch captured once into a hipGraph (re-captured when any pointer changes) and
+ * replayed on `stream`.  Not thread-safe for one plan. */
+int ldbp_batch_forward_graph(ldbp_batch_plan* plan, const void* taps, const void* c, const void* x, void* y,
+                             void* stream);
+
+/* ---------------------------------------------------------------------------
  * Split-step method (Sec. III-A) for the time-discretised NLSE
  *   du/dz = -(alpha/2) u - j (beta2/2) d^2u/dt^2 + j gamma |u|^2 u      (eq. nlse)
  * on the DFT grid of n samples at rate fs (circular waveforms):

@@ -63,6 +63,12 @@ SIGNATURES = {
     "ldbp_backward": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p, c_void_p, c_void_p,
                                 c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]),
+    "ldbp_batch_plan_create": (c_int32, [c_int32, c_int32, c_int32, P_i64, P_i32, P_i32, P_plan,
+                                         ctypes.POINTER(c_void_p)]),
+    "ldbp_batch_plan_destroy": (c_int32, [c_void_p]),
+    "ldbp_batch_plan_info": (c_int32, [c_void_p, P_i64, P_i64, P_i64, P_i64, P_i32, P_i32]),
+    "ldbp_batch_forward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ldbp_batch_forward_graph": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ssm_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, P_size]),
     "ssm_channel": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_size_t, c_void_p]),

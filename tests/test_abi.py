@@ -87,3 +87,20 @@ def test_forward_rejects_bad_arguments_before_any_gpu_work():
     assert _fwd(ntap=[5] * 100, n=100000, x=1 << 30, y=1 << 31) == N.LDBP_EWORKSPACE   # multi-pass needs ws
     assert _fwd(ckpt=1 << 20, every=0) == N.LDBP_EINVAL
     assert _fwd(ckpt=4096 + 512, every=1, y=1 << 24) == N.LDBP_EINVAL  # ckpt overlaps x
+
+
+def test_batch_plan_rejects_bad_tables_before_any_gpu_work():
+    lib = N.load()
+    h = ctypes.c_void_p(0)
+    lens = (ctypes.c_int64 * 2)(100, 200)
+    ns = N.i32_array([2, 1])
+    assert lib.ldbp_batch_plan_create(0, 1, 2, lens, ns, N.i32_array([3, 4, 5]), None, ctypes.byref(h)) == N.LDBP_EINVAL
+    assert lib.ldbp_batch_plan_create(0, 1, 0, lens, ns, N.i32_array([3, 5, 5]), None, ctypes.byref(h)) == N.LDBP_EINVAL
+    assert lib.ldbp_batch_plan_create(0, 3, 2, lens, ns, N.i32_array([3, 5, 5]), None, ctypes.byref(h)) == N.LDBP_EUNSUPPORTED
+    bad = (ctypes.c_int64 * 2)(100, 0)
+    assert lib.ldbp_batch_plan_create(0, 1, 2, bad, ns, N.i32_array([3, 5, 5]), None, ctypes.byref(h)) == N.LDBP_EINVAL
+    # total halo larger than any LDS work size
+    assert lib.ldbp_batch_plan_create(0, 1, 1, lens, N.i32_array([200]), N.i32_array([63] * 200), None,
+                                      ctypes.byref(h)) == N.LDBP_EUNSUPPORTED
+    assert h.value in (None, 0)
+    assert lib.ldbp_batch_forward(None, 16, 16, 16, 32, None) == N.LDBP_EINVAL
