@@ -49,10 +49,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def fwd_flops_per_sample_step(T: int) -> int:
+def fwd_flops_per_sample_step(T: int, folded: bool = False) -> int:
     # general complex FIR: T complex multiplies (6 flops) + T-1 complex additions (2) = 8T - 2;
+    # folded symmetric FIR (K = (T-1)/2): K pair additions (2) + K+1 complex multiplies (6) + K
+    # complex additions (2) = 10K + 6;
     # Kerr: |u|^2 (3) + c |u|^2 (1) + rotation, a complex multiply (6) = 10; sine/cosine not counted.
-    return 8 * T - 2 + 10
+    K = (T - 1) // 2
+    return (10 * K + 6 if folded else 8 * T - 2) + 10
 
 
 def event_time(torch, stream, fn, steps: int, warmup: int):
@@ -106,6 +109,62 @@ def build_workload(torch, dev, cheap: bool = False):
     return dict(r=r.contiguous(), s=s, p=p, taps=tt, c=ct, ntap=ntap, dbp_link=dbp_link)
 
 
+def even_5smooth(v: float) -> int:
+    best, bd = 2, float("inf")
+    for m in range(max(2, int(v * 0.8)), int(v * 1.25) + 2):
+        if m % 2:
+            continue
+        k = m
+        for q in (2, 3, 5):
+            while k % q == 0:
+                k //= q
+        if k == 1 and abs(m - v) < bd:
+            best, bd = m, abs(m - v)
+    return best
+
+
+def uneven_batch(torch, dev, reps: int):
+    """256 waveforms, lengths log-uniform in [4,096, 262,144] (even 5-smooth), 1-25 spans of 100 km,
+    2 steps per span, 3/5/7/9 taps per waveform; one graph-captured launch per batch."""
+    import synth
+    from paper_2010_14258_amd import batch as BT
+    from paper_2010_14258_amd import init as I
+    from paper_2010_14258_amd import txrx as TX
+
+    lengths = [even_5smooth(v) for v in synth.log_uniform_lengths(401, 256, 4096, 262144)]
+    g = synth.rng(401, 9)
+    nspan = g.integers(1, 26, size=256).tolist()
+    taps_b = g.choice([3, 5, 7, 9], size=256).tolist()
+    alpha = I.db_per_km_to_alpha(0.2)
+    beta2 = I.ps2_per_km_to_beta2(-21.683)
+    span_model = {}
+    taps, cs, nsteps, ntap = [], [], [], []
+    for ns, T in zip(nspan, taps_b):
+        if T not in span_model:
+            tp, c = I.ldbp_parameters(1e5, 1, 2, T, 2 * RS, alpha, beta2, 1.3e-3)
+            span_model[T] = ([I.unit_peak_gain(h) for h in tp], c)
+        tp, c = span_model[T]
+        taps.extend(tp * ns)
+        cs.append(np.tile(c, ns))
+        nsteps.append(2 * ns)
+        ntap.extend([T] * (2 * ns))
+    tt = torch.from_numpy(np.concatenate(taps)).to(dev, torch.complex64)
+    ct = torch.from_numpy(np.concatenate(cs)).to(dev, torch.float32)
+    x = TX.randn((sum(lengths),), 404, 0, device=dev) * math.sqrt(2.5e-3)
+    y = torch.empty_like(x)
+    best = None
+    for plan in [(0, 0, rb, sym) for rb in (7, 9) for sym in (0, 1)]:
+        bp = BT.BatchPlan(lengths, nsteps, ntap, plan=plan)
+        stream = torch.cuda.current_stream(dev)
+        ms = event_time(torch, stream, lambda: bp.forward(tt, ct, x, y=y, graph=True, stream=stream), reps, 2)
+        if best is None or ms < best[1]:
+            best = (plan, ms, bp.total_sample_steps, bp.total_samples, bp.nitems)
+    plan, ms, ss, ns_tot, nitems = best
+    return {"value": ss / (ms * 1e-3), "unit": "samples*steps/s", "ms_per_batch": ms, "plan": list(plan),
+            "total_samples": ns_tot, "total_sample_steps": ss, "work_items": nitems,
+            "workload": "256 uneven waveforms (4,096-262,144 samples), 2-50 steps, 3-9 taps, one hipGraph launch"}
+
+
 def snr_db(TX, z, s, p):
     mse, _, _ = TX.rx_mse(z, s, p, RHO_D, RS)
     return 10.0 * math.log10(1.0 / float(mse.mean().item()))
@@ -120,6 +179,8 @@ def main():
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
     ap.add_argument("--mode", choices=["full", "fwd", "pmc"], default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe")
+    ap.add_argument("--plan", default=None,
+                    help="forward plan S,chunks,outputs_per_thread,symmetric (default: autotuned, folded)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -140,10 +201,18 @@ def main():
     nwave, n = r.shape
     ell = len(ntap)
     y = torch.empty_like(r)
-    ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap), 1), dtype=torch.uint8, device=dev)
+    from paper_2010_14258_amd import autotune as AT
+    if args.plan:
+        plan = tuple(int(v) for v in args.plan.split(","))
+        plan_gen, ms_gen_tuned = None, None
+    else:
+        plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=5)
+        plan_gen, ms_gen_tuned, _ = AT.tune_forward(r, taps, c, ntap, symmetric=False, reps=5)
+    folded = bool(plan[3])
+    ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, plan=plan), 1), dtype=torch.uint8, device=dev)
 
     def fwd():
-        L.ldbp_forward(r, taps, c, ntap, y=y, ws=ws, stream=stream)
+        L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan, ws=ws, stream=stream)
 
     if args.mode == "pmc":
         for _ in range(3):
@@ -153,18 +222,19 @@ def main():
         for _ in range(3):
             dst.copy_(big)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": True, "fwd_launches": 3 * L.ldbp_forward_plan_query(0, 1, nwave, n, ntap)[0],
+        print(json.dumps({"pmc_probe": True, "plan": list(plan),
+                          "fwd_launches": 3 * L.ldbp_forward_plan_query(0, 1, nwave, n, ntap, plan=plan)[0],
                           "copy_bytes": 2 * big.numel() * 8, "kernel_hash": kernel_hash()}))
         return
 
     t0 = time.perf_counter()
     ms_fwd = event_time(torch, stream, fwd, args.steps, args.warmup)
     wall = time.perf_counter() - t0
-    npass, tile_len, spp = L.ldbp_forward_plan_query(0, 1, nwave, n, ntap)
+    npass, tile_len, spp = L.ldbp_forward_plan_query(0, 1, nwave, n, ntap, plan=plan)
     ss = nwave * n * ell
     value = ss / (ms_fwd * 1e-3)
     launch_ms = ms_fwd / npass
-    flops_launch = nwave * n * sum(fwd_flops_per_sample_step(t) for t in ntap) / npass
+    flops_launch = nwave * n * sum(fwd_flops_per_sample_step(t, folded) for t in ntap) / npass
     achieved_tflops = flops_launch / (launch_ms * 1e-3) / 1e12
     bytes_launch = nwave * n * 8 * 2
     achieved_gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
@@ -172,7 +242,8 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == [nwave, n, ell, TAPS]:
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == [nwave, n, ell, TAPS] \
+                and tr.get("plan") == list(plan):
             traffic = tr.get("bytes_per_launch")
 
     out = {
@@ -191,14 +262,22 @@ def main():
         "data": "synthetic: GPU-simulated 16-QAM over 10 x 100 km SSMF with ASE (library kernels)",
         "config": {"workload": "LDBP inference, 64 waveforms x 65,536 c64 samples, l = 50 (5 steps/span), 15 taps",
                    "nwave": nwave, "n": n, "steps_l": ell, "taps": TAPS, "launch_dbm": P_DBM,
+                   "plan": list(plan), "folded_symmetric_filters": folded,
                    "passes": npass, "tile_len": tile_len, "steps_per_pass": spp},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "ldbp_fwd_kernel<float,1,8,256>", "launch_ms": launch_ms,
+                     "kernel": f"ldbp_fwd_kernel<float,1,{plan[2]},256>" + (" folded" if folded else ""),
+                     "launch_ms": launch_ms,
                      "flops_per_launch": flops_launch, "algorithmic_bytes_per_launch": bytes_launch,
                      "hbm_achieved_gbs": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS},
     }
 
+    if plan_gen is not None:
+        fl_gen = nwave * n * sum(fwd_flops_per_sample_step(t) for t in ntap)
+        out["general_taps_forward"] = {"value": ss / (ms_gen_tuned * 1e-3), "unit": "samples*steps/s",
+                                       "ms_per_step": ms_gen_tuned, "plan": list(plan_gen),
+                                       "achieved_tflops": fl_gen / (ms_gen_tuned * 1e-3) / 1e12,
+                                       "frac": fl_gen / (ms_gen_tuned * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
     if args.mode == "full":
         # forward with block checkpoints + backward
         S = 2
@@ -253,6 +332,8 @@ def main():
             trn.step()
         torch.cuda.synchronize()
         out["train_iteration_ms"] = (time.perf_counter() - t1) / 3 * 1e3
+        del trn
+        out["uneven_batch"] = uneven_batch(torch, dev, max(5, args.steps // 5))
 
     if not args.no_cpu_baseline and args.mode == "full":
         out["cpu_baseline"] = cpu_baseline(args.cpu_waves, n, ntap)

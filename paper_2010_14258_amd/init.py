@@ -89,6 +89,13 @@ def inverse_cd_taps_inband(delta: float, beta2: float, fs: float, ntap: int, rho
     return np.linalg.solve(G, rhs)
 
 
+def unit_peak_gain(h: np.ndarray, grid: int = 4096) -> np.ndarray:
+    """Scales a filter so that its largest gain over all frequencies is one (non-expansive cascade)."""
+    K = (len(h) - 1) // 2
+    resp = np.fft.fft(np.concatenate([h[K:], np.zeros(grid - len(h), dtype=complex), h[:K]]))
+    return h / np.max(np.abs(resp))
+
+
 def backprop_schedule(span_len: float, nspan: int, steps: Sequence[float]) -> List[Tuple[float, float]]:
     """(delta, z_start) of the forward steps in the order backpropagation undoes them."""
     starts = np.cumsum([0.0] + list(steps))[:-1]
