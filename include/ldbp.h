@@ -191,7 +191,7 @@ int ldbp_batch_forward_graph(ldbp_batch_plan* plan, const void* taps, const void
  *   Kerr step     N(z): x <- x exp(j kerr_scale gamma L_eff(z) |x|^2), L_eff(z) = (1 - e^{-alpha z}) / alpha
  *                 (|x|^2 summed over both polarisations for npol = 2; kerr_scale = 8/9 for Manakov)
  * A link has nspan spans of span_len metres, each cut into nstep steps.  The FFT
- * is hand written (power-of-two n, 2 <= n <= 2^24).
+ * is hand written (power-of-two n, 2 <= n <= 2^24; with two polarisations n <= 2^22).
  * -------------------------------------------------------------------------*/
 typedef struct ssm_link {
   double fs;          /* sampling rate [Hz] */

@@ -81,7 +81,8 @@ static int prepare(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const 
   if (st) return st;
   g = make_geom(dtype, nwave, n, npol, L->fs, L->alpha, L->beta2);
   if (ssm_lds_bytes(dtype, g) > kSsmMaxLds)
-    return fail(LDBP_EUNSUPPORTED, "n = %lld needs more LDS per workgroup than available", (long long)n);
+    return fail(LDBP_EUNSUPPORTED, "n = %lld with npol = %d is beyond the FFT sizes supported (npol 2: n <= 2^22)",
+                (long long)n, npol);
   M = L->nspan * L->nstep;
   return LDBP_OK;
 }
