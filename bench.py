@@ -177,8 +177,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
-    ap.add_argument("--mode", choices=["full", "fwd", "pmc"], default="full",
-                    help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe")
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp"], default="full",
+                    help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
+                         "dbp: FFT-DBP at one step per span only (for kernel traces of the split-step passes)")
     ap.add_argument("--plan", default=None,
                     help="forward plan S,chunks,outputs_per_thread,symmetric (default: autotuned, folded)")
     args = ap.parse_args()
@@ -201,6 +202,16 @@ def main():
     nwave, n = r.shape
     ell = len(ntap)
     y = torch.empty_like(r)
+    if args.mode == "dbp":
+        # FFT-DBP at one step per span on the same received batch (the split-step passes alone)
+        link = W["dbp_link"](1)
+        wsd = torch.empty(SS.ssm_workspace_size(r, link), dtype=torch.uint8, device=dev)
+        ms = event_time(torch, stream, lambda: SS.fft_dbp(r, link, y=y, ws=wsd, stream=stream), args.steps,
+                        args.warmup)
+        nstep = link.nspan * link.nstep
+        print(json.dumps({"fft_dbp_ms": ms, "dbp_steps": nstep, "us_per_step": ms / nstep * 1e3,
+                          "nwave": nwave, "n": n}))
+        return
     from paper_2010_14258_amd import autotune as AT
     if args.plan:
         plan = tuple(int(v) for v in args.plan.split(","))
