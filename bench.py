@@ -9,10 +9,13 @@ l = 50 steps (5 per span, logarithmic step sizes) of 15-tap filters and per-step
 coefficients, least-squares initialised.
 
 One timed step = one LDBP forward over the whole batch (inputs resident in GPU memory).
-value = samples x steps per second = nwave * n * l / time.  Also reported: forward + backward
-(block checkpoints every 5 steps), FFT-DBP on the same waveforms at the smallest steps/span whose
-effective SNR is within 0.1 dB of LDBP's, one training iteration of the 32 x 16,384 training
-configuration, the roofline position of the forward kernel and the FP64 oracle on the host.
+value = samples x steps per second = nwave * n * l / time.  Also reported: the per-call time
+distribution, forward + backward (block checkpoints every 2 steps), FFT-DBP on the same waveforms
+at the smallest steps/span whose effective SNR is within 0.1 dB of LDBP's, one training iteration of
+the 32 x 16,384 training configuration, the same forward on 1,024 waveforms (512 MiB per buffer,
+beyond the 256 MB last-level cache), the dual-polarisation 8 x 2^20 x 2 configuration (32 x 80 km,
+l = 64, 5 shared taps), the 256-waveform uneven batch, the roofline position of the forward kernel
+and the FP64 oracle on the host (one core and all cores of the process's CPU set).
 """
 from __future__ import annotations
 
@@ -70,6 +73,21 @@ def event_time(torch, stream, fn, steps: int, warmup: int):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def time_distribution(torch, stream, fn, reps: int, warmup: int):
+    """HIP-event time of each of `reps` calls (ms): median, 10th and 90th percentile."""
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"median_ms": float(np.median(t)), "p10_ms": float(np.percentile(t, 10)),
+            "p90_ms": float(np.percentile(t, 90)), "calls": reps}
 
 
 def build_workload(torch, dev, cheap: bool = False):
@@ -165,6 +183,96 @@ def uneven_batch(torch, dev, reps: int):
             "workload": "256 uneven waveforms (4,096-262,144 samples), 2-50 steps, 3-9 taps, one hipGraph launch"}
 
 
+def big_batch(torch, dev, W, reps: int):
+    """The inference forward on 1,024 waveforms (the 64 received waveforms repeated 16 times): 512 MiB
+    per buffer, so input and output no longer fit the 256 MB last-level cache."""
+    from paper_2010_14258_amd import autotune as AT
+    from paper_2010_14258_amd import ldbp as L
+
+    r = W["r"].repeat(16, 1)
+    taps, c, ntap = W["taps"], W["c"], W["ntap"]
+    nwave, n = r.shape
+    stream = torch.cuda.current_stream(dev)
+    plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=3)
+    y = torch.empty_like(r)
+    ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, plan=plan), 1), dtype=torch.uint8, device=dev)
+    ms = event_time(torch, stream, lambda: L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan, ws=ws, stream=stream),
+                    reps, 2)
+    npass = L.ldbp_forward_plan_query(0, 1, nwave, n, ntap, plan=plan)[0]
+    ss = nwave * n * len(ntap)
+    flops = nwave * n * sum(fwd_flops_per_sample_step(t, bool(plan[3])) for t in ntap)
+    moved = npass * nwave * n * 16
+    return {"nwave": nwave, "n": n, "plan": list(plan), "passes": npass, "ms": ms, "value": ss / (ms * 1e-3),
+            "unit": "samples*steps/s", "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+            "alu_frac": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+            "algorithmic_hbm_gbs": moved / (ms * 1e-3) / 1e9, "hbm_frac": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def manakov(torch, dev, reps: int):
+    """Dual polarisation: 8 waveforms x 2^20 samples x 2 polarisations (524,288 16-QAM symbols per
+    polarisation), 32 x 80 km, PMD-free Manakov channel (Kerr phase 8/9 gamma (|x|^2 + |y|^2)) with 10
+    uniform steps per span and amplifier noise, LDBP l = 64 (2 steps per span) with 5 taps shared by
+    both polarisations.  Forward and forward + backward."""
+    from paper_2010_14258_amd import autotune as AT
+    from paper_2010_14258_amd import init as I
+    from paper_2010_14258_amd import ldbp as L
+    from paper_2010_14258_amd import ssm as SS
+    from paper_2010_14258_amd import txrx as TX
+
+    nw, nsym, nspan, span = 8, 524288, 32, 80e3
+    alpha = I.db_per_km_to_alpha(0.2)
+    beta2 = I.ps2_per_km_to_beta2(-21.683)
+    gamma = 1.3e-3
+    fs_a, fs_d = RHO_A * RS, RHO_D * RS
+    p_w = I.dbm_to_w(2.0)
+    p = torch.full((nw,), p_w, dtype=torch.float64, device=dev)
+    words = TX.randbits(nw * nsym * 2, 501, 0, device=dev).view(nw, nsym, 2)
+    x = TX.tx_shape(words, p, RHO_A, RS, npol=2, dtype=torch.complex64)
+    ch = SS.Link(fs=fs_a, alpha=alpha, beta2=beta2, gamma=gamma, span_len=span, nspan=nspan, nstep=10,
+                 edfa_gain=True, ase_var=I.ase_variance(alpha, span, 5.0, fs_a), kerr_scale=8.0 / 9.0)
+    noise = TX.randn((nspan,) + tuple(x.shape), 502, 0, dtype=torch.complex64, device=dev)
+    SS.ssm_channel(x, ch, noise=noise, y=x, npol=2)
+    del noise
+    r = TX.rx_lpf_decimate(x, RHO_D * nsym, npol=2).contiguous()
+    del x
+    torch.cuda.empty_cache()
+    tp, cc = I.ldbp_parameters(span, nspan, 2, 5, fs_d, alpha, beta2, gamma, kerr_scale=8.0 / 9.0)
+    ntap = [len(h) for h in tp]
+    taps = torch.from_numpy(np.concatenate(tp)).to(dev, torch.complex64)
+    c = torch.from_numpy(cc).to(dev, torch.float32)
+    ell = len(ntap)
+    n = r.shape[1]
+    stream = torch.cuda.current_stream(dev)
+    plan, _, _ = AT.tune_forward(r, taps, c, ntap, npol=2, symmetric=True, reps=3)
+    y = torch.empty_like(r)
+    ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, 2, plan=plan), 1), dtype=torch.uint8, device=dev)
+    ms = event_time(torch, stream,
+                    lambda: L.ldbp_forward(r, taps, c, ntap, npol=2, y=y, plan=plan, ws=ws, stream=stream), reps, 2)
+    S = 2
+    ck = torch.empty((L.num_checkpoints(ell, S),) + tuple(r.shape), dtype=r.dtype, device=dev)
+    z = L.ldbp_forward(r, taps, c, ntap, npol=2)
+    s = TX.qam16_symbols(words, dtype=torch.complex64)
+    mse, _, gy = TX.rx_mse(z, s, p, RHO_D, RS, npol=2, want_grad=True)
+    bws = torch.empty(L.ldbp_backward_workspace_size(r, ntap, 2, ckpt=ck, ckpt_every=S), dtype=torch.uint8,
+                      device=dev)
+
+    def fwd_bwd():
+        L.ldbp_forward(r, taps, c, ntap, npol=2, y=y, ckpt=ck, ckpt_every=S, stream=stream)
+        L.ldbp_backward(r, taps, c, ntap, gy, npol=2, ckpt=ck, ckpt_every=S, need_gx=False, ws=bws, stream=stream)
+
+    ms_fb = event_time(torch, stream, fwd_bwd, max(3, reps // 3), 1)
+    ss = nw * n * ell
+    return {"workload": "8 waveforms x 1,048,576 samples x 2 polarisations, 32 x 80 km Manakov, l = 64, 5 shared taps",
+            "plan": list(plan), "fwd_ms": ms, "fwd_time_samples_steps_per_s": ss / (ms * 1e-3),
+            "fwd_pol_samples_steps_per_s": 2 * ss / (ms * 1e-3), "fwd_bwd_ms": ms_fb,
+            "fwd_bwd_time_samples_steps_per_s": ss / (ms_fb * 1e-3), "ckpt_every": S,
+            "launch_dbm_per_pol": 2.0,
+            "ls_init_snr_db": 10.0 * math.log10(1.0 / float(mse.mean().item())),
+            "note": "the timing does not depend on the filter values; 5-tap least-squares filters do not equalise "
+                    "this link before training (their gain above one outside the signal band compounds over 64 "
+                    "steps), so the LS-initialised SNR is not a quality figure"}
+
+
 def snr_db(TX, z, s, p):
     mse, _, _ = TX.rx_mse(z, s, p, RHO_D, RS)
     return 10.0 * math.log10(1.0 / float(mse.mean().item()))
@@ -186,6 +294,9 @@ def main():
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if not args.no_cpu_baseline and args.mode == "full":
+        cpu = cpu_baseline(args.cpu_waves, RHO_D * NSYM, [TAPS] * (NSPAN * LDBP_STPS))
 
     import torch
     from paper_2010_14258_amd import _native
@@ -241,6 +352,7 @@ def main():
     t0 = time.perf_counter()
     ms_fwd = event_time(torch, stream, fwd, args.steps, args.warmup)
     wall = time.perf_counter() - t0
+    dist = time_distribution(torch, stream, fwd, args.steps, 2)
     npass, tile_len, spp = L.ldbp_forward_plan_query(0, 1, nwave, n, ntap, plan=plan)
     ss = nwave * n * ell
     value = ss / (ms_fwd * 1e-3)
@@ -266,6 +378,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_fwd,
         "wall_s": wall,
+        "per_call": dist,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -345,26 +458,79 @@ def main():
         out["train_iteration_ms"] = (time.perf_counter() - t1) / 3 * 1e3
         del trn
         out["uneven_batch"] = uneven_batch(torch, dev, max(5, args.steps // 5))
+        out["big_batch"] = big_batch(torch, dev, W, max(5, args.steps // 5))
+        out["manakov"] = manakov(torch, dev, max(5, args.steps // 5))
 
-    if not args.no_cpu_baseline and args.mode == "full":
-        out["cpu_baseline"] = cpu_baseline(args.cpu_waves, n, ntap)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(nw, n, ntap):
-    """The FP64 oracle (plain NumPy, not tuned) on a bounded sample of the same workload shape."""
+def _oracle_ldbp_chunk(args):
+    """One worker's share of the oracle baseline: LDBP forward on `k` seeded waveforms."""
     import synth
     from oracle import ldbp as O
 
+    seed, k, n, ntap = args
     taps = synth.random_taps(1, ntap)
     c = np.full(len(ntap), -1e-2)
-    x = synth.complex_normal(2, (nw, n)) * 0.05
-    t0 = time.perf_counter()
+    x = synth.complex_normal(seed, (k, n)) * 0.05
     O.ldbp_forward(x, taps, c)
-    dt = time.perf_counter() - t0
-    return {"value": nw * n * len(ntap) / dt, "unit": "samples*steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{nw} of 64 waveforms x {n} samples x {len(ntap)} steps ({len(ntap) * ntap[0]} taps), "
-                      f"FP64 NumPy direct convolution, single process, {dt:.1f} s"}
+    return k
+
+
+def cpu_baseline(nw, n, ntap):
+    """The FP64 oracle (plain NumPy, not tuned) on the host, on a bounded sample of the same workload
+    shape: LDBP by direct convolution in one process (NumPy runs these element-wise operations on one
+    core) and over a fork pool of one process per core of the CPU set (at most 16); FFT-DBP at one step
+    per span in one process.  Runs before the GPU is touched."""
+    import multiprocessing as mp
+    import platform
+
+    import synth
+    from oracle import ssm as OS
+
+    ell = len(ntap)
+    t0 = time.perf_counter()
+    _oracle_ldbp_chunk((2, nw, n, ntap))
+    dt1 = time.perf_counter() - t0
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    per = 4
+    jobs = [(100 + j, per, n, ntap) for j in range(cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        pool.map(_oracle_ldbp_chunk, [(99, 1, 256, ntap)] * cores)   # start the workers
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_ldbp_chunk, jobs))
+        dtp = time.perf_counter() - t0
+    # FFT-DBP, 1 step per span over 10 x 100 km
+    alpha = 0.2 * math.log(10) / 10 / 1e3
+    link = OS.Link(fs=RHO_D * RS, alpha=alpha, beta2=-21.683e-27, gamma=1.3e-3, span_len=SPAN_KM * 1e3,
+                   nspan=NSPAN, step_len=[SPAN_KM * 1e3])
+    nd = 16
+    r = synth.complex_normal(3, (nd, n)) * 0.05
+    t0 = time.perf_counter()
+    OS.fft_dbp(r, link)
+    dtd = time.perf_counter() - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"value": done * n * ell / dtp, "unit": "samples*steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} waveforms x {n} samples x {ell} steps ({ntap[0]} taps), FP64 NumPy direct convolution "
+                      f"over a pool of {cores} processes, {dtp:.1f} s",
+            "single_core": {"value": nw * n * ell / dt1, "cores": 1,
+                            "sample": f"{nw} waveforms in one process, {dt1:.1f} s"},
+            "fft_dbp_single_core": {"value": nd * n * NSPAN / dtd, "unit": "samples*steps/s", "cores": 1,
+                                    "sample": f"{nd} waveforms, FFT-DBP 1 step/span x {NSPAN} spans, NumPy FFT, "
+                                              f"{dtd:.1f} s"},
+            "host": {"cpu_model": model, "os_cpu_count": os.cpu_count(),
+                     "affinity": len(os.sched_getaffinity(0)), "python": platform.python_version()},
+            "note": "the FP64 correctness oracle timed as it stands, not a tuned CPU implementation"}
 
 
 if __name__ == "__main__":

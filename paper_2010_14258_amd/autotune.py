@@ -2,7 +2,8 @@
 
 For a problem signature (device, dtype, npol, nwave, n, tap profile, symmetric) it times every
 plan in a candidate set -- outputs per thread x steps per pass x LDS chunks -- with HIP events on
-the caller's stream and keeps the fastest.  Results are cached in memory and, when a path is
+the caller's stream and keeps the plan with the fewest steps per pass among those within 2% of the
+fastest.  Results are cached in memory and, when a path is
 given (argument or LDBP_AUTOTUNE_CACHE), in a JSON file; a missing or unreadable cache file just
 means tuning again.  All candidates produce identical results for a fixed outputs-per-thread
 and symmetry flag; across those the results agree to rounding.
@@ -66,6 +67,15 @@ def candidates(code: int, npol: int, nstep: int, symmetric: bool) -> List[Tuple[
     return out
 
 
+def pick(table, within: float = 0.02):
+    """The plan with the fewest steps per pass among those within `within` of the fastest (then the
+    fewest LDS chunks, then the fastest): more steps per pass only add halo once time stops falling,
+    and the rule keeps the choice stable against timing noise between near-equal plans."""
+    fastest = min(ms for _, ms in table)
+    ok = [(plan, ms) for plan, ms in table if ms <= fastest * (1.0 + within)]
+    return min(ok, key=lambda t: (t[0][0], t[0][1], t[1]))
+
+
 def _time(fn, stream, reps: int) -> float:
     fn()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -112,7 +122,7 @@ def tune_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Seq
         table.append((list(plan), ms))
     if not table:
         raise RuntimeError("no forward plan could run for this problem")
-    best = min(table, key=lambda t: t[1])
+    best = pick(table)
     entry = {"plan": best[0], "ms": best[1], "table": table}
     _MEM[key] = entry
     disk[key] = entry
