@@ -142,6 +142,12 @@ int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
  *   gx           device [nwave][n][npol] complex output dL/dx, or NULL when not needed
  *   gtaps        device [sum ntap] complex output, overwritten
  *   gc           device [nstep] real output, overwritten
+ *   plan         host, may be NULL; only flags is used.  LDBP_PLAN_SYMMETRIC: the caller
+ *                guarantees h_{-k} = h_k; the three FIR products (recompute, adjoint, tap
+ *                correlation) are evaluated folded, and gtaps holds the gradient projected on
+ *                symmetric filters: entries k and -k both hold (dL/dh_k + dL/dh_{-k}) / 2, the
+ *                centre dL/dh_0 (so their sum over a mirrored pair is the gradient of the shared
+ *                parameter).  Other flag bits: LDBP_EINVAL.
  *   ws           device workspace of ldbp_backward_workspace_size() bytes
  * -------------------------------------------------------------------------*/
 int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
@@ -150,7 +156,7 @@ int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int
 int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
                   const int32_t* ntap, const void* taps, const void* c, const void* x,
                   const void* ckpt, int32_t ckpt_every, const void* gy, void* gx, void* gtaps,
-                  void* gc, void* ws, size_t ws_bytes, void* stream);
+                  void* gc, const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched LDBP inference over uneven waveforms (eq. model for each waveform of the batch).

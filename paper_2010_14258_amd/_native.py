@@ -61,8 +61,8 @@ SIGNATURES = {
     "ldbp_backward_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p,
                                                c_int32, P_size]),
     "ldbp_backward": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p, c_void_p, c_void_p,
-                                c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
-                                c_void_p]),
+                                c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, P_plan, c_void_p,
+                                c_size_t, c_void_p]),
     "ldbp_batch_plan_create": (c_int32, [c_int32, c_int32, c_int32, P_i64, P_i32, P_i32, P_plan,
                                          ctypes.POINTER(c_void_p)]),
     "ldbp_batch_plan_destroy": (c_int32, [c_void_p]),

@@ -262,11 +262,14 @@ extern "C" int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t
 
 extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
                              const int32_t* ntap, const void* taps, const void* c, const void* x, const void* ckpt,
-                             int32_t ckpt_every, const void* gy, void* gx, void* gtaps, void* gc, void* ws,
-                             size_t ws_bytes, void* stream) {
+                             int32_t ckpt_every, const void* gy, void* gx, void* gtaps, void* gc,
+                             const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream) {
   ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
   int st = check_model(m);
   if (st) return st;
+  if (plan && (plan->flags & ~LDBP_PLAN_SYMMETRIC))
+    return fail(LDBP_EINVAL, "plan flags 0x%x: only LDBP_PLAN_SYMMETRIC is defined", plan->flags);
+  const int sym = (plan && (plan->flags & LDBP_PLAN_SYMMETRIC)) ? 1 : 0;
   if (!taps || !c || !x || !gy || !gtaps || !gc)
     return fail(LDBP_EINVAL, "taps, c, x, gy, gtaps and gc must be non-NULL");
   if (!aligned16(taps) || !aligned16(x) || !aligned16(gy) || !aligned16(gtaps) || (gx && !aligned16(gx)) ||
@@ -304,7 +307,7 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
     for (size_t i = 0; i + 1 < nb; ++i) {
       void* out = wsb + L.off_ckpt + i * wave_bytes;
       st = launch_fwd_pass(dtype, npol, L.blocks.rb, in, out, nwave, static_cast<int32_t>(n), L.blocks.chunks,
-                           L.blocks.passes[i], taps, c, 0, s);
+                           L.blocks.passes[i], taps, c, sym, s);
       if (st) return st;
       in = out;
     }
@@ -314,7 +317,7 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
     const void* xb = bi == 0 ? x : static_cast<const void*>(ck + (bi - 1) * wave_bytes);
     void* gin = (bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0);
     st = launch_bwd_block(dtype, npol, xb, gcur, gin, nwave, static_cast<int32_t>(n), L.tile_len,
-                          L.blocks.passes[bi], taps, c, part, L.ncols, L.ntaps, s);
+                          L.blocks.passes[bi], taps, c, part, L.ncols, L.ntaps, sym, s);
     if (st) return st;
     gcur = gin;
   }

@@ -20,6 +20,12 @@
 //   4. write the block-input gradient over [t0, t0+L) and the tile's partial
 //      sums (one FP64 value per tap and step) to a [tile][column] buffer that a
 //      second kernel reduces in a fixed order, so results are deterministic.
+// Symmetric filters (h_{-k} = h_k) are evaluated folded in all three FIR products:
+//   recompute  u_m = h_0 x_m + sum_{k>=1} h_k (x_{m-k} + x_{m+k})
+//   adjoint    G_x,p = conj(h_0) G_u,p + sum_{k>=1} conj(h_k) (G_u,(p+k) + G_u,(p-k))
+//   taps       g_k = sum_m G_u,m conj(x_{m-k} + x_{m+k}) = dL/dh_k + dL/dh_{-k}  (k >= 1)
+// and the tap gradient is returned as its projection on symmetric filters, g_k / 2 in both
+// entries k and -k (g_0 = dL/dh_0 in the centre).
 #include <algorithm>
 #include <vector>
 
@@ -59,8 +65,8 @@ __device__ __forceinline__ double wave_sum_last(double v) { return wave_sum(v); 
 
 constexpr int kLastLane = 63;
 
-// out[j] = sum_k conj(h_k) in[j+k] for j in [lo, hi); reads in[lo-K, hi+RB+K-2].
-template <typename R, int NPOL, int RB, int THREADS, int K>
+// out[j] = sum_k conj(h_k) in[j+k] for j in [lo, hi); reads in[lo-K, hi+RB+K-2].  SYM: folded.
+template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM>
 __device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
                                               int hi, const cx_t<R>* __restrict__ h) {
   using V = cx_t<R>;
@@ -76,13 +82,32 @@ __device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx
     for (int r = 0; r < RB; ++r)
 #pragma unroll
       for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
-#pragma unroll
-    for (int k = -K; k <= K; ++k) {
-      const V hk = h[K + k];
+    if constexpr (SYM) {
+      const V h0 = h[K];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) cmac_conj(acc[r][p], hk, win[r + k + K][p]);
+        for (int p = 0; p < NPOL; ++p) cmac_conj(acc[r][p], h0, win[r + K][p]);
+#pragma unroll
+      for (int k = 1; k <= K; ++k) {
+        const V hk = h[K + k];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int p = 0; p < NPOL; ++p) {
+            const V a = win[r + K + k][p], b = win[r + K - k][p];
+            cmac_conj(acc[r][p], hk, V{a.x + b.x, a.y + b.y});
+          }
+      }
+    } else {
+#pragma unroll
+      for (int k = -K; k <= K; ++k) {
+        const V hk = h[K + k];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+          for (int p = 0; p < NPOL; ++p) cmac_conj(acc[r][p], hk, win[r + k + K][p]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
@@ -92,6 +117,7 @@ __device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx
   }
 }
 
+// Long filters (K > 12): direct form (symmetric taps give the same values unfolded).
 template <typename R, int NPOL, int RB, int THREADS>
 __device__ __forceinline__ void fir_adj_generic(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
                                                 int hi, int K, const cx_t<R>* __restrict__ h) {
@@ -128,16 +154,18 @@ __device__ __forceinline__ void cmac_yconj(V& acc, V g, V y) {
 
 // Tap gradient of one step: for each k, sum over owned j in [own_lo, own_lo+Lw) of
 // gu[j] conj(yprev[j + yshift - k]); per-wave sums land in red[wave * ldr + col0 + K + k].
-template <typename R, int NPOL, int RB2, int THREADS, int K>
+// SYM: the K + 1 folded sums g_k (see the top of the file); columns K + k and K - k both receive g_k / 2.
+template <typename R, int NPOL, int RB2, int THREADS, int K, bool SYM>
 __device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, int own_lo, int Lw,
                                               const cx_t<R>* __restrict__ yprev, int yshift,
                                               double2* __restrict__ red, int ldr, int col0) {
   using V = cx_t<R>;
   constexpr int T = 2 * K + 1;
+  constexpr int NA = SYM ? K + 1 : T;  // accumulators: folded k = 0..K, or k = -K..K
   constexpr int W = RB2 + 2 * K;
-  V acc[T];
+  V acc[NA];
 #pragma unroll
-  for (int k = 0; k < T; ++k) acc[k] = V{0, 0};
+  for (int k = 0; k < NA; ++k) acc[k] = V{0, 0};
   const int own_hi = own_lo + Lw;
   for (int jb = own_lo + static_cast<int>(threadIdx.x) * RB2; jb < own_hi; jb += THREADS * RB2) {
 #pragma unroll
@@ -148,49 +176,81 @@ __device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, in
 #pragma unroll
       for (int r = 0; r < RB2; ++r) {
         const V g = (jb + r < own_hi) ? gu[(jb + r) * NPOL + p] : V{0, 0};
+        if constexpr (SYM) {
+          cmac_yconj(acc[0], g, win[r + K]);
 #pragma unroll
-        for (int k = -K; k <= K; ++k) cmac_yconj(acc[K + k], g, win[r - k + K]);
+          for (int k = 1; k <= K; ++k) {
+            const V a = win[r - k + K], b = win[r + k + K];
+            cmac_yconj(acc[k], g, V{a.x + b.x, a.y + b.y});
+          }
+        } else {
+#pragma unroll
+          for (int k = -K; k <= K; ++k) cmac_yconj(acc[K + k], g, win[r - k + K]);
+        }
       }
     }
   }
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
 #pragma unroll
-  for (int k = 0; k < T; ++k) {
+  for (int k = 0; k < NA; ++k) {
     const R sx = wave_sum_last(acc[k].x);
     const R sy = wave_sum_last(acc[k].y);
-    if (lane == kLastLane) red[wv * ldr + col0 + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+    if (lane == kLastLane) {
+      if constexpr (SYM) {
+        const double f = k == 0 ? 1.0 : 0.5;
+        const double2 v{f * static_cast<double>(sx), f * static_cast<double>(sy)};
+        red[wv * ldr + col0 + K + k] = v;
+        red[wv * ldr + col0 + K - k] = v;
+      } else {
+        red[wv * ldr + col0 + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+      }
+    }
   }
 }
 
+// Long filters (K > 12): one tap at a time; with sym the mirrored pair is summed and halved as in
+// tapgrad_fixed.
 template <typename R, int NPOL, int RB2, int THREADS>
 __device__ __forceinline__ void tapgrad_generic(const cx_t<R>* __restrict__ gu, int own_lo, int Lw, int K,
                                                 const cx_t<R>* __restrict__ yprev, int yshift,
-                                                double2* __restrict__ red, int ldr, int col0) {
+                                                double2* __restrict__ red, int ldr, int col0, bool sym) {
   using V = cx_t<R>;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int own_hi = own_lo + Lw;
-  for (int k = -K; k <= K; ++k) {
+  for (int k = sym ? 0 : -K; k <= K; ++k) {
     V acc{0, 0};
     for (int j = own_lo + static_cast<int>(threadIdx.x); j < own_hi; j += THREADS)
 #pragma unroll
-      for (int p = 0; p < NPOL; ++p) cmac_yconj(acc, gu[j * NPOL + p], yprev[(j + yshift - k) * NPOL + p]);
+      for (int p = 0; p < NPOL; ++p) {
+        V y = yprev[(j + yshift - k) * NPOL + p];
+        if (sym && k > 0) {
+          const V b = yprev[(j + yshift + k) * NPOL + p];
+          y = V{y.x + b.x, y.y + b.y};
+        }
+        cmac_yconj(acc, gu[j * NPOL + p], y);
+      }
     const R sx = wave_sum_last(acc.x);
     const R sy = wave_sum_last(acc.y);
-    if (lane == kLastLane) red[wv * ldr + col0 + K + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+    if (lane == kLastLane) {
+      const double f = (sym && k > 0) ? 0.5 : 1.0;
+      const double2 v{f * static_cast<double>(sx), f * static_cast<double>(sy)};
+      red[wv * ldr + col0 + K + k] = v;
+      if (sym) red[wv * ldr + col0 + K - k] = v;
+    }
   }
 }
 
-template <typename R, int NPOL, int RB, int RB2, int THREADS>
-__device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga, int lo, int hi, int K,
-                                                  const cx_t<R>* h, int own_lo, int Lw, const cx_t<R>* yprev,
-                                                  int yshift, double2* red, int ldr, int col0) {
+template <typename R, int NPOL, int RB, int RB2, int THREADS, bool SYM>
+__device__ __forceinline__ void adj_step_dispatch_t(const cx_t<R>* gb, cx_t<R>* ga, int lo, int hi, int K,
+                                                    const cx_t<R>* h, int own_lo, int Lw, const cx_t<R>* yprev,
+                                                    int yshift, double2* red, int ldr, int col0) {
   switch (K) {
-#define LDBP_BWD_CASE(k)                                                                       \
-  case k:                                                                                      \
-    fir_adj_fixed<R, NPOL, RB, THREADS, k>(gb, ga, lo, hi, h);                                 \
-    tapgrad_fixed<R, NPOL, RB2, THREADS, k>(gb, own_lo, Lw, yprev, yshift, red, ldr, col0);    \
+#define LDBP_BWD_CASE(k)                                                                         \
+  case k:                                                                                        \
+    fir_adj_fixed<R, NPOL, RB, THREADS, k, SYM>(gb, ga, lo, hi, h);                              \
+    tapgrad_fixed<R, NPOL, RB2, THREADS, k, SYM>(gb, own_lo, Lw, yprev, yshift, red, ldr, col0); \
     break;
     LDBP_BWD_CASE(0) LDBP_BWD_CASE(1) LDBP_BWD_CASE(2) LDBP_BWD_CASE(3)
     LDBP_BWD_CASE(4) LDBP_BWD_CASE(5) LDBP_BWD_CASE(6) LDBP_BWD_CASE(7)
@@ -199,9 +259,21 @@ __device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga
 #undef LDBP_BWD_CASE
     default:
       fir_adj_generic<R, NPOL, RB, THREADS>(gb, ga, lo, hi, K, h);
-      tapgrad_generic<R, NPOL, RB2, THREADS>(gb, own_lo, Lw, K, yprev, yshift, red, ldr, col0);
+      tapgrad_generic<R, NPOL, RB2, THREADS>(gb, own_lo, Lw, K, yprev, yshift, red, ldr, col0, SYM);
       break;
   }
+}
+
+template <typename R, int NPOL, int RB, int RB2, int THREADS>
+__device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga, int lo, int hi, int K,
+                                                  const cx_t<R>* h, int own_lo, int Lw, const cx_t<R>* yprev,
+                                                  int yshift, double2* red, int ldr, int col0, bool sym) {
+  if (sym)
+    adj_step_dispatch_t<R, NPOL, RB, RB2, THREADS, true>(gb, ga, lo, hi, K, h, own_lo, Lw, yprev, yshift, red, ldr,
+                                                         col0);
+  else
+    adj_step_dispatch_t<R, NPOL, RB, RB2, THREADS, false>(gb, ga, lo, hi, K, h, own_lo, Lw, yprev, yshift, red, ldr,
+                                                          col0);
 }
 
 // LDS footprint (in complex elements) of one tile of length Lw for a block with halo H and
@@ -212,7 +284,7 @@ template <typename R, int NPOL, int RB, int RB2, int THREADS>
 __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const cx_t<R>* __restrict__ xb, const cx_t<R>* __restrict__ gout, cx_t<R>* __restrict__ gin, int32_t n,
     int32_t tile_len, int32_t ntiles, const cx_t<R>* __restrict__ taps, const R* __restrict__ c, PassTable pt,
-    int32_t pad, double2* __restrict__ part, int32_t ncols, int32_t ccol_base) {
+    int32_t pad, double2* __restrict__ part, int32_t ncols, int32_t ccol_base, int32_t sym) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = THREADS / 64;
@@ -255,7 +327,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     hs += K;
     const R coef = c[pt.c0 + s - 1] * phase_coef_scale<R>();
     fir_kerr_dispatch<R, NPOL, RB, THREADS>(ycur + K * NPOL, ynext, 0, bwd_y_width(Lw, H, hs), K,
-                                            taps + pt.tapoff[s - 1], coef);
+                                            taps + pt.tapoff[s - 1], coef, sym != 0);
     __syncthreads();
     ycur = ynext;
   }
@@ -303,7 +375,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const int hprev = hs - K;
     adj_step_dispatch<R, NPOL, RB, RB2, THREADS>(GB, GA, H - hprev, H + Lw + hprev, K, taps + pt.tapoff[s - 1], H,
                                                  Lw, yprev, H - hprev, red, ldr,
-                                                 pt.tapoff[s - 1] - pt.tapoff[0]);
+                                                 pt.tapoff[s - 1] - pt.tapoff[0], sym != 0);
     __syncthreads();
     hs = hprev;
     ycur = yprev;
@@ -388,7 +460,7 @@ size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt) {
 template <typename R, int NPOL>
 static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                               int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
-                              int32_t ncols, int32_t ccol_base, hipStream_t stream) {
+                              int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream) {
   using Cfg = BwdCfg<R, NPOL>;
   const int64_t ntiles = (n + tile_len - 1) / tile_len;
   const int64_t nblocks = ntiles * nwave;
@@ -402,23 +474,23 @@ static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64
                      static_cast<const cx_t<R>*>(xb), static_cast<const cx_t<R>*>(gout), static_cast<cx_t<R>*>(gin),
                      n, tile_len, static_cast<int32_t>(ntiles), static_cast<const cx_t<R>*>(taps),
                      static_cast<const R*>(c), pt, bwd_pad(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL),
-                     static_cast<double2*>(part), ncols, ccol_base);
+                     static_cast<double2*>(part), ncols, ccol_base, sym);
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }
 
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
-                     int32_t ncols, int32_t ccol_base, hipStream_t stream) {
+                     int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream) {
   if (dtype == LDBP_C64)
     return npol == 1 ? launch_bwd_block_t<float, 1>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                    ccol_base, stream)
+                                                    ccol_base, sym, stream)
                      : launch_bwd_block_t<float, 2>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                    ccol_base, stream);
+                                                    ccol_base, sym, stream);
   return npol == 1 ? launch_bwd_block_t<double, 1>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                   ccol_base, stream)
+                                                   ccol_base, sym, stream)
                    : launch_bwd_block_t<double, 2>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                   ccol_base, stream);
+                                                   ccol_base, sym, stream);
 }
 
 int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,

@@ -138,21 +138,37 @@ __device__ __forceinline__ void fir_kerr_dispatch(const cx_t<R>* in, cx_t<R>* ou
   else fir_kerr_dispatch_t<R, NPOL, RB, THREADS, false>(in, out, lo, hi, K, h, coef);
 }
 
-// Loads samples [t0 - H, t0 + Lw + H) of one waveform (circularly) into LDS.
+// Loads samples [t0 - H, t0 + Lw + H) of one waveform (circularly) into LDS.  Each thread issues a
+// batch of global loads (64 bytes of samples) before its first LDS store, so the loads of a tile are
+// in flight together instead of one round trip per element.
 template <typename R, int NPOL, int THREADS>
 __device__ __forceinline__ void load_tile(const cx_t<R>* __restrict__ xw, cx_t<R>* __restrict__ buf, int n,
                                           int t0, int H, int W0, int wrap_general) {
-  for (int j = threadIdx.x; j < W0; j += THREADS) {
-    int g = t0 - H + j;
-    if (wrap_general) {
-      g %= n;
-      if (g < 0) g += n;
-    } else {
-      if (g < 0) g += n;
-      else if (g >= n) g -= n;
+  using V = cx_t<R>;
+  constexpr int kLoadBatch = 64 / static_cast<int>(sizeof(V) * NPOL);
+  for (int j0 = threadIdx.x; j0 < W0; j0 += kLoadBatch * THREADS) {
+    V v[kLoadBatch][NPOL];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int j = min(j0 + u * THREADS, W0 - 1);  // past the end: reload the last sample, not stored
+      int g = t0 - H + j;
+      if (wrap_general) {
+        g %= n;
+        if (g < 0) g += n;
+      } else {
+        if (g < 0) g += n;
+        else if (g >= n) g -= n;
+      }
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) v[u][p] = xw[static_cast<int64_t>(g) * NPOL + p];
     }
 #pragma unroll
-    for (int p = 0; p < NPOL; ++p) buf[j * NPOL + p] = xw[static_cast<int64_t>(g) * NPOL + p];
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int j = j0 + u * THREADS;
+      if (j < W0)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) buf[j * NPOL + p] = v[u][p];
+    }
   }
 }
 

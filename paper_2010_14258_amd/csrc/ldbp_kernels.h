@@ -32,7 +32,7 @@ int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t
 size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt);
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
-                     int32_t ncols, int32_t ccol_base, hipStream_t stream);
+                     int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream);
 int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,
                        void* gc, hipStream_t stream);
 

@@ -134,8 +134,11 @@ def ldbp_backward_workspace_size(x: torch.Tensor, ntap: Sequence[int], npol: int
 
 def ldbp_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], gy: torch.Tensor,
                   npol: int = 1, ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0, need_gx: bool = True,
-                  ws: Optional[torch.Tensor] = None, stream=None):
-    """Adjoint of ``ldbp_forward``: returns (gx or None, gtaps, gc) for dL/dy = gy (G = dL/dRe + j dL/dIm)."""
+                  symmetric: bool = False, ws: Optional[torch.Tensor] = None, stream=None):
+    """Adjoint of ``ldbp_forward``: returns (gx or None, gtaps, gc) for dL/dy = gy (G = dL/dRe + j dL/dIm).
+
+    symmetric: the taps satisfy h_{-k} = h_k; the FIR products are evaluated folded and gtaps is the
+    gradient projected on symmetric filters ((dL/dh_k + dL/dh_{-k}) / 2 in both entries)."""
     lib = N.load()
     code = _code(x)
     nwave, n = _shape(x, npol)
@@ -151,9 +154,10 @@ def ldbp_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Se
     if ws is None:
         need = ldbp_backward_workspace_size(x, ntap, npol, ckpt, ckpt_every)
         ws = torch.empty(need, dtype=torch.uint8, device=x.device)
+    pl = N.LdbpPlan(0, 0, 0, N.LDBP_PLAN_SYMMETRIC if symmetric else 0)
     st = lib.ldbp_backward(code, npol, nwave, n, len(ntap), N.i32_array(ntap), _ptr(taps), _ptr(c), _ptr(x),
-                           _ptr(ckpt), int(ckpt_every), _ptr(gy), _ptr(gx), _ptr(gtaps), _ptr(gc), _ptr(ws),
-                           ws.numel(), stream_handle(stream, x.device))
+                           _ptr(ckpt), int(ckpt_every), _ptr(gy), _ptr(gx), _ptr(gtaps), _ptr(gc), ctypes.byref(pl),
+                           _ptr(ws), ws.numel(), stream_handle(stream, x.device))
     N.check(st)
     return gx, gtaps, gc
 

@@ -97,6 +97,10 @@ class Trainer:
                                kerr_scale=self.kerr_scale)
         taps, c = I.ldbp_parameters(self.span, cfg.nspan, cfg.ldbp_steps, cfg.t_init, self.fs_d, self.alpha,
                                     self.beta2, self.gamma, kerr_scale=self.kerr_scale, unit_taps=cfg.unit_init)
+        if cfg.symmetric:
+            # the least-squares fit of an even response is symmetric up to rounding; make it exact, since
+            # the folded kernels read only one side of each filter
+            taps = [0.5 * (h + h[::-1]) for h in taps]
         self.ntap = [len(h) for h in taps]
         self.taps = torch.from_numpy(np.concatenate(taps)).to(self.dev, self.cdt)
         self.c = torch.from_numpy(c).to(self.dev, self.rdt)
@@ -160,13 +164,14 @@ class Trainer:
 
     def forward(self, r: torch.Tensor, ckpt: bool = False):
         cfg = self.cfg
+        sym = 1 if cfg.symmetric else 0
         if not ckpt:
-            return L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=cfg.npol), None
+            return L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=cfg.npol, plan=(0, 0, 0, sym)), None
         S = max(1, min(cfg.ckpt_every, len(self.ntap)))
         nslot = L.num_checkpoints(len(self.ntap), S)
         ck = torch.empty((nslot,) + tuple(r.shape), dtype=r.dtype, device=r.device) if nslot else None
         z = L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=cfg.npol, ckpt=ck, ckpt_every=S if ck is not None else 0,
-                           plan=(S, 0) if ck is None else None)
+                           plan=(S, 0, 0, sym) if ck is None else (0, 0, 0, sym))
         return z, ck
 
     def step(self):
@@ -180,7 +185,7 @@ class Trainer:
         S = max(1, min(cfg.ckpt_every, len(self.ntap)))
         mse, _, gz = TX.rx_mse(z, s, p, cfg.rho_d, cfg.rs, cfg.rolloff, npol=cfg.npol, want_grad=True)
         _, gt, gc = L.ldbp_backward(r, self.taps, self.c, self.ntap, gz, npol=cfg.npol, ckpt=ck, ckpt_every=S,
-                                    need_gx=False)
+                                    need_gx=False, symmetric=cfg.symmetric)
         self.t += 1
         TX.adam_(self.taps, gt, self.m_t, self.v_t, self.t, lr=cfg.lr,
                  mirror=self.mirror() if cfg.symmetric else None)

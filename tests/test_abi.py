@@ -89,6 +89,23 @@ def test_forward_rejects_bad_arguments_before_any_gpu_work():
     assert _fwd(ckpt=4096 + 512, every=1, y=1 << 24) == N.LDBP_EINVAL  # ckpt overlaps x
 
 
+def _bwd(flags=0, x=1 << 20, gy=1 << 24, gx=None, ws=None, ws_bytes=0, ntap=(15, 3), n=64, nwave=2):
+    lib = N.load()
+    pl = N.LdbpPlan(0, 0, 0, flags)
+    nt = N.i32_array(ntap)
+    return lib.ldbp_backward(0, 1, nwave, n, len(ntap), nt, 1 << 12, 1 << 13, x, None, 0, gy, gx, 1 << 14, 1 << 15,
+                             ctypes.byref(pl), ws, ws_bytes, None)
+
+
+def test_backward_rejects_bad_arguments_before_any_gpu_work():
+    # Fake (never dereferenced) addresses: every case fails validation on the host.
+    assert _bwd(flags=2) == N.LDBP_EINVAL                               # undefined plan flag
+    assert _bwd(flags=N.LDBP_PLAN_SYMMETRIC) == N.LDBP_EWORKSPACE       # valid flag, missing workspace
+    assert _bwd(ntap=(15, 4)) == N.LDBP_EINVAL                          # even length
+    assert _bwd(x=(1 << 20) + 8) == N.LDBP_EINVAL                       # misaligned
+    assert _bwd(gx=(1 << 24) + 512, ws=1 << 28, ws_bytes=1 << 30) == N.LDBP_EINVAL   # gx overlaps gy
+
+
 def test_batch_plan_rejects_bad_tables_before_any_gpu_work():
     lib = N.load()
     h = ctypes.c_void_p(0)

@@ -25,7 +25,7 @@ def _t(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
 
 
-def _gpu_grad(x, taps, c, gy, npol=1, dtype=torch.complex128, ckpt_every=0, use_ckpt=False):
+def _gpu_grad(x, taps, c, gy, npol=1, dtype=torch.complex128, ckpt_every=0, use_ckpt=False, symmetric=False):
     tp, ntap = W.pack_taps(taps)
     rd = torch.float32 if dtype == torch.complex64 else torch.float64
     xt, tt, ct, gt = _t(x, dtype), _t(tp, dtype), _t(np.asarray(c, np.float64), rd), _t(gy, dtype)
@@ -34,8 +34,10 @@ def _gpu_grad(x, taps, c, gy, npol=1, dtype=torch.complex128, ckpt_every=0, use_
         ns = G.num_checkpoints(len(ntap), ckpt_every)
         if ns > 0:
             ck = torch.empty((ns,) + tuple(xt.shape), dtype=dtype, device=DEV)
-            G.ldbp_forward(xt, tt, ct, ntap, npol=npol, ckpt=ck, ckpt_every=ckpt_every)
-    gx, gtp, gc = G.ldbp_backward(xt, tt, ct, ntap, gt, npol=npol, ckpt=ck, ckpt_every=ckpt_every)
+            G.ldbp_forward(xt, tt, ct, ntap, npol=npol, ckpt=ck, ckpt_every=ckpt_every,
+                           plan=(0, 0, 0, 1) if symmetric else None)
+    gx, gtp, gc = G.ldbp_backward(xt, tt, ct, ntap, gt, npol=npol, ckpt=ck, ckpt_every=ckpt_every,
+                                  symmetric=symmetric)
     torch.cuda.synchronize()
     off = np.cumsum([0] + ntap)
     gtp = gtp.cpu().numpy().astype(np.complex128)
@@ -67,6 +69,37 @@ def test_backward_mixed_taps_vs_oracle(dtype, tol, S, use_ckpt):
     gy = synth.complex_normal(62, (3, 3001))
     ref = O.ldbp_grad(x, taps, c, gy)
     _cmp(_gpu_grad(x, taps, c, gy, dtype=dtype, ckpt_every=S, use_ckpt=use_ckpt), ref, tol)
+
+
+def _sym_projection(gt):
+    """Oracle tap gradient projected on symmetric filters: (g_k + g_-k) / 2 in both entries."""
+    out = []
+    for g in gt:
+        f = O.fold_symmetric_grad(g)
+        K = len(f) - 1
+        h = np.empty_like(g)
+        h[K] = f[0]
+        for k in range(1, K + 1):
+            h[K + k] = h[K - k] = 0.5 * f[k]
+        out.append(h)
+    return out
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 1e-4), (torch.complex128, 1e-10)])
+@pytest.mark.parametrize("npol,S,use_ckpt", [(1, 3, True), (1, 2, False), (2, 3, True), (1, 0, False)])
+def test_backward_symmetric_folded_vs_oracle(dtype, tol, npol, S, use_ckpt):
+    """Folded evaluation for symmetric filters (incl. T = 1 and the K > 12 direct path): dL/dx and dL/dc as
+    the oracle's, taps as the oracle's gradient projected on symmetric filters."""
+    print("case: bwd symmetric", dtype, npol, S, use_ckpt, flush=True)
+    Ts = [15, 3, 1, 27, 9, 5]
+    taps, c = _model(64, Ts, 0.3)
+    taps = [0.5 * (h + h[::-1]) for h in taps]
+    shape = (3, 2501) if npol == 1 else (2, 2501, 2)
+    x = synth.complex_normal(65, shape) * 0.5
+    gy = synth.complex_normal(66, shape)
+    rx, rt, rc = O.ldbp_grad(x, taps, c, gy, npol=npol)
+    _cmp(_gpu_grad(x, taps, c, gy, npol=npol, dtype=dtype, ckpt_every=S, use_ckpt=use_ckpt, symmetric=True),
+         (rx, _sym_projection(rt), rc), tol)
 
 
 @pytest.mark.parametrize("npol", [1, 2])
