@@ -39,8 +39,9 @@ static int max_chunks(int dtype, int npol, int rb) {
 }
 
 // Splits the l steps into passes.  With a checkpoint interval the passes are
-// exactly the checkpoint blocks; otherwise each pass takes steps while twice
-// its halo stays within 1/8 of the LDS work size (or a fixed S from the plan).
+// exactly the checkpoint blocks (the backward's unit; the forward groups them, see
+// make_block_plan); otherwise each pass takes steps while twice its halo stays within
+// 1/8 of the LDS work size (or a fixed S from the plan).
 struct PassPlan {
   std::vector<PassTable> passes;
   int chunks;
@@ -104,6 +105,71 @@ static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* pl
   return LDBP_OK;
 }
 
+// Passes over steps [0, nrun) made of whole checkpoint blocks of S steps: a pass takes blocks
+// while twice its halo stays within 1/8 of the LDS work size (or up to plan->steps_per_pass steps,
+// at least one block), and writes the state at each inner block boundary to that block's slot
+// (ckpt_mask).  The pass output itself is the next block's slot, or y after the last step.
+static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ldbp_plan* plan, PassPlan& out) {
+  int st = make_plan(m, S, plan, out);  // exact blocks: validates rb, chunks and the per-block halo
+  if (st) return st;
+  const int chunk = fwd_chunk(m.dtype, m.npol, out.rb);
+  const int cmax = max_chunks(m.dtype, m.npol, out.rb);
+  const int want = (plan && plan->steps_per_pass > 0) ? std::max<int>(S, plan->steps_per_pass / S * S) : 0;
+  std::vector<PassTable> blocks;
+  for (const auto& b : out.passes)
+    if (b.c0 < nrun) blocks.push_back(b);
+  std::vector<PassTable> passes;
+  int max_halo = 0;
+  for (size_t i = 0; i < blocks.size();) {
+    PassTable pt = blocks[i];
+    pt.ckpt_mask = 0;
+    pt.ckpt_every = S;
+    size_t j = i + 1;
+    while (j < blocks.size()) {
+      const PassTable& b = blocks[j];
+      if (pt.nstep + b.nstep > LDBP_MAX_STEPS_PER_PASS) break;
+      if (want > 0 ? pt.nstep + b.nstep > want : 2 * (pt.halo + b.halo) * 8 > out.chunks * chunk) break;
+      pt.ckpt_mask |= uint64_t(1) << (pt.nstep - 1);  // the end of the pass so far is an inner boundary
+      for (int k = 0; k < b.nstep; ++k) {
+        pt.K[pt.nstep + k] = b.K[k];
+        pt.tapoff[pt.nstep + k] = b.tapoff[k];
+      }
+      pt.nstep += b.nstep;
+      pt.halo += b.halo;
+      ++j;
+    }
+    pt.wrap_general = (pt.halo >= m.n) ? 1 : 0;
+    max_halo = std::max(max_halo, pt.halo);
+    passes.push_back(pt);
+    i = j;
+  }
+  int chunks = out.chunks;
+  while (chunks * chunk - 2 * max_halo < chunk / 2 && chunks < cmax) ++chunks;
+  if (chunks * chunk - 2 * max_halo < 1)
+    return fail(LDBP_EUNSUPPORTED, "halo %d of a pass does not fit in LDS; use fewer steps per pass", max_halo);
+  out.chunks = chunks;
+  out.passes = passes;
+  return LDBP_OK;
+}
+
+// Runs steps [0, pp's last step] from x, writing every block input b >= 1 to slot b - 1 of ckpt;
+// the output of the final pass goes to `last` (y, or the last slot).
+static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* taps, const void* c, const void* x,
+                          void* last, void* ckpt, int32_t S, hipStream_t s) {
+  const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
+  const void* in = x;
+  for (size_t i = 0; i < pp.passes.size(); ++i) {
+    const PassTable& pt = pp.passes[i];
+    void* out = (i + 1 == pp.passes.size()) ? last
+                                            : static_cast<char*>(ckpt) + ((pt.c0 + pt.nstep) / S - 1) * wave_bytes;
+    int st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, m.nwave, static_cast<int32_t>(m.n), pp.chunks, pt, taps,
+                             c, pp.sym, ckpt, s);
+    if (st) return st;
+    in = out;
+  }
+  return LDBP_OK;
+}
+
 }  // namespace ldbp
 
 using namespace ldbp;
@@ -146,26 +212,29 @@ extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
     if (nslot > 0 && (overlaps(ckpt, nslot * wave_bytes, x, wave_bytes) || overlaps(ckpt, nslot * wave_bytes, y, wave_bytes)))
       return fail(LDBP_EINVAL, "ckpt overlaps x or y");
   }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ckpt) {
+    PassPlan bp;
+    st = make_block_plan(m, ckpt_every, nstep, plan, bp);
+    if (st) return st;
+    return run_block_plan(m, bp, taps, c, x, y, ckpt, ckpt_every, s);
+  }
   PassPlan pp;
-  st = make_plan(m, ckpt ? ckpt_every : 0, plan, pp);
+  st = make_plan(m, 0, plan, pp);
   if (st) return st;
   const size_t np = pp.passes.size();
-  if (!ckpt && np > 1) {
+  if (np > 1) {
     if (!ws || ws_bytes < wave_bytes)
       return fail(LDBP_EWORKSPACE, "workspace of %zu bytes required, %zu given", wave_bytes, ws ? ws_bytes : 0);
     if (!aligned16(ws)) return fail(LDBP_EINVAL, "ws must be 16-byte aligned");
     if (overlaps(ws, wave_bytes, x, wave_bytes) || overlaps(ws, wave_bytes, y, wave_bytes))
       return fail(LDBP_EINVAL, "workspace overlaps x or y");
   }
-  hipStream_t s = static_cast<hipStream_t>(stream);
   const void* in = x;
   for (size_t i = 0; i < np; ++i) {
-    void* out;
-    if (i + 1 == np) out = y;
-    else if (ckpt) out = static_cast<char*>(ckpt) + i * wave_bytes;
-    else out = ((np - 1 - i) % 2 == 0) ? y : ws;
+    void* out = ((np - 1 - i) % 2 == 0) ? y : ws;  // ping-pong that ends in y
     st = launch_fwd_pass(dtype, npol, pp.rb, in, out, nwave, static_cast<int32_t>(n), pp.chunks, pp.passes[i], taps, c,
-                         pp.sym, s);
+                         pp.sym, nullptr, s);
     if (st) return st;
     in = out;
   }
@@ -301,16 +370,15 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
   const size_t nb = L.blocks.passes.size();
   const char* ck = static_cast<const char*>(ckpt);
   if (!ckpt && nb > 1) {
-    // recompute the block inputs with the forward (its output goes to a scratch buffer)
+    // recompute the block inputs 1 .. nb-1 with the forward, passes grouped over whole blocks
     ck = wsb + L.off_ckpt;
-    const void* in = x;
-    for (size_t i = 0; i + 1 < nb; ++i) {
-      void* out = wsb + L.off_ckpt + i * wave_bytes;
-      st = launch_fwd_pass(dtype, npol, L.blocks.rb, in, out, nwave, static_cast<int32_t>(n), L.blocks.chunks,
-                           L.blocks.passes[i], taps, c, sym, s);
-      if (st) return st;
-      in = out;
-    }
+    const int32_t nrun = L.blocks.passes[nb - 1].c0;
+    ldbp_plan fp{0, 0, L.blocks.rb, sym ? LDBP_PLAN_SYMMETRIC : 0};
+    PassPlan bp;
+    st = make_block_plan(m, L.S, nrun, &fp, bp);
+    if (st) return st;
+    st = run_block_plan(m, bp, taps, c, x, wsb + L.off_ckpt + (nb - 2) * wave_bytes, wsb + L.off_ckpt, L.S, s);
+    if (st) return st;
   }
   const void* gcur = gy;
   for (size_t bi = nb; bi-- > 0;) {
@@ -333,7 +401,7 @@ extern "C" int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwav
   if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
     return fail(LDBP_EINVAL, "ckpt_every %d outside [0, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
   PassPlan pp;
-  st = make_plan(m, ckpt_every, plan, pp);
+  st = ckpt_every > 0 ? make_block_plan(m, ckpt_every, nstep, plan, pp) : make_plan(m, 0, plan, pp);
   if (st) return st;
   int maxs = 0, minlen = 1 << 30;
   for (const auto& pt : pp.passes) {

@@ -7,6 +7,8 @@
 // and writes only the L samples whose dependency cone was fully loaded.  After
 // step s the valid region has shrunk by K_s on each side.  Each thread
 // produces RB consecutive outputs from a register window of RB + 2K inputs.
+// A pass may span several checkpoint blocks: at an inner block boundary the tile's own L
+// samples (valid after every step of the pass) are also written to that block's checkpoint slot.
 #include <algorithm>
 #include <vector>
 
@@ -20,7 +22,8 @@ template <typename R, int NPOL, int RB, int THREADS>
 __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __restrict__ x, cx_t<R>* __restrict__ y,
                                                            int32_t n, int32_t tile_len, int32_t ntiles,
                                                            int32_t work, const cx_t<R>* __restrict__ taps,
-                                                           const R* __restrict__ c, PassTable pt, int32_t sym) {
+                                                           const R* __restrict__ c, PassTable pt, int32_t sym,
+                                                           cx_t<R>* __restrict__ ckpt, int64_t slot_elems) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   V* b0 = reinterpret_cast<V*>(smem);
@@ -48,6 +51,15 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
     V* t = b0;
     b0 = b1;
     b1 = t;
+    if ((pt.ckpt_mask >> s) & 1) {
+      // the next step writes the other buffer, so b0 stays intact while it is copied out
+      const int64_t slot = (pt.c0 + s + 1) / pt.ckpt_every - 1;
+      V* cw = ckpt + slot * slot_elems + wave * static_cast<int64_t>(n) * NPOL;
+      for (int j = threadIdx.x; j < Lw; j += THREADS) {
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) cw[static_cast<int64_t>(t0 + j) * NPOL + p] = b0[(H + j) * NPOL + p];
+      }
+    }
   }
 
   for (int j = threadIdx.x; j < Lw; j += THREADS) {
@@ -84,7 +96,9 @@ size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks) {
 
 template <typename R, int NPOL, int RB>
 static int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
-                             const PassTable& pt, const void* taps, const void* c, int sym, hipStream_t stream) {
+                             const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
+                             hipStream_t stream) {
+  if (pt.ckpt_mask && (!ckpt || pt.ckpt_every < 1)) return fail(LDBP_EINVAL, "checkpoint writes without slots");
   const int work = chunks * RB * kThreads;
   const int tile_len = work - 2 * pt.halo;
   if (tile_len < 1) return fail(LDBP_EINVAL, "pass halo %d too large for work size %d", pt.halo, work);
@@ -99,15 +113,16 @@ static int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, i
   hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(nblocks)), dim3(kThreads), lds, stream,
                      static_cast<const cx_t<R>*>(x), static_cast<cx_t<R>*>(y), n, tile_len,
                      static_cast<int32_t>(ntiles), work, static_cast<const cx_t<R>*>(taps),
-                     static_cast<const R*>(c), pt, sym);
+                     static_cast<const R*>(c), pt, sym, static_cast<cx_t<R>*>(ckpt), nwave * n * NPOL);
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }
 
 int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
-                    const PassTable& pt, const void* taps, const void* c, int sym, hipStream_t stream) {
-#define LDBP_FWD_LAUNCH(R, NP, B) \
-  if (npol == NP && rb == B) return launch_fwd_pass_t<R, NP, B>(x, y, nwave, n, chunks, pt, taps, c, sym, stream);
+                    const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream) {
+#define LDBP_FWD_LAUNCH(R, NP, B)                                                                       \
+  if (npol == NP && rb == B)                                                                            \
+    return launch_fwd_pass_t<R, NP, B>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream);
   if (dtype == LDBP_C64) {
     LDBP_FWD_LAUNCH(float, 1, 7) LDBP_FWD_LAUNCH(float, 1, 8) LDBP_FWD_LAUNCH(float, 1, 9)
     LDBP_FWD_LAUNCH(float, 2, 3) LDBP_FWD_LAUNCH(float, 2, 4) LDBP_FWD_LAUNCH(float, 2, 5)

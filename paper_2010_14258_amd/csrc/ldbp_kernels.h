@@ -15,6 +15,9 @@ struct PassTable {
   int32_t halo;          // H = sum of K over the pass
   int32_t c0;            // index of the pass's first step in the global step list
   int32_t wrap_general;  // 1 when H >= n, so tile loads need a full modulo
+  uint64_t ckpt_mask;    // bit s: after local step s write the state to checkpoint slot (c0+s+1)/ckpt_every - 1
+  int32_t ckpt_every;    // checkpoint block length (used with ckpt_mask)
+  int32_t reserved;
   int32_t K[LDBP_MAX_STEPS_PER_PASS];       // half-lengths
   int32_t tapoff[LDBP_MAX_STEPS_PER_PASS];  // offsets into the packed taps
 };
@@ -25,8 +28,9 @@ bool fwd_rb_supported(int dtype, int npol, int rb);
 int fwd_chunk(int dtype, int npol, int rb);
 size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks);
 
+// ckpt: base of the checkpoint slots written inside the pass (pt.ckpt_mask), or NULL when the mask is 0.
 int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
-                    const PassTable& pt, const void* taps, const void* c, int sym, hipStream_t stream);
+                    const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream);
 
 // Backward (adjoint) block kernel and the deterministic gradient reduction.
 size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt);

@@ -121,3 +121,16 @@ def test_batch_plan_rejects_bad_tables_before_any_gpu_work():
                                       ctypes.byref(h)) == N.LDBP_EUNSUPPORTED
     assert h.value in (None, 0)
     assert lib.ldbp_batch_forward(None, 16, 16, 16, 32, None) == N.LDBP_EINVAL
+
+
+def test_checkpointed_forward_groups_whole_blocks():
+    from paper_2010_14258_amd import ldbp as L
+    # 50 steps of 15 taps, checkpoints every 2 steps: passes of whole blocks (halo rule), not 25 passes
+    npass, _, maxs = L.ldbp_forward_plan_query(0, 1, 64, 65536, [15] * 50, ckpt_every=2)
+    assert npass == 4 and maxs == 16 and maxs % 2 == 0
+    # steps_per_pass is rounded down to whole blocks
+    npass, _, maxs = L.ldbp_forward_plan_query(0, 1, 64, 65536, [15] * 50, ckpt_every=2, plan=(7, 0))
+    assert maxs == 6 and npass == 9
+    # a pass never splits a block, whatever the plan asks for
+    npass, _, maxs = L.ldbp_forward_plan_query(0, 1, 64, 65536, [15] * 50, ckpt_every=5, plan=(3, 0))
+    assert maxs == 5 and npass == 10
