@@ -65,6 +65,86 @@ __device__ __forceinline__ double wave_sum_last(double v) { return wave_sum(v); 
 
 constexpr int kLastLane = 63;
 
+// Value of the lane whose index differs in bit B (within a row of 16 lanes, B < 4).
+template <int B>
+__device__ __forceinline__ float lane_xor(float v) {
+  const int x = __builtin_bit_cast(int, v);
+  int r;
+  if constexpr (B == 0) {
+    r = __builtin_amdgcn_mov_dpp(x, 0xB1, 0xf, 0xf, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (B == 1) {
+    r = __builtin_amdgcn_mov_dpp(x, 0x4E, 0xf, 0xf, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (B == 2) {
+    r = __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0x5, false);   // banks 0, 2: row_shl:4 (lane i+4)
+    r = __builtin_amdgcn_update_dpp(r, x, 0x114, 0xf, 0xa, false);   // banks 1, 3: row_shr:4 (lane i-4)
+  } else {
+    r = __builtin_amdgcn_mov_dpp(x, 0x128, 0xf, 0xf, false);  // row_ror:8 = lane i ^ 8 in a 16-lane row
+  }
+  return __builtin_bit_cast(float, r);
+}
+
+// One butterfly level over lane bit B: of the V values a lane holds, it keeps the half selected by
+// its bit B (upper half when set) summed with the partner's same half, sending the other half.
+template <int V, int B>
+__device__ __forceinline__ void butterfly_level(float* a, int lane) {
+  const bool up = (lane >> B) & 1;
+#pragma unroll
+  for (int j = 0; j < V / 2; ++j) {
+    const float keep = up ? a[j + V / 2] : a[j];
+    const float send = up ? a[j] : a[j + V / 2];
+    a[j] = keep + lane_xor<B>(send);
+  }
+}
+
+// Sums NV = 2^m per-lane values (m <= 4) over the 64 lanes of a wave with m butterfly levels over lane
+// bits 0, 1, 3, 2 and plain exchanges over the remaining bits: about 4 NV instructions instead of
+// 16 NV for NV separate reductions.  Returns the lane's total; it is the total of value
+// reduce_index<NV>(lane) in every lane whose remaining bits (2 when m < 4, and 4, 5) are zero.
+template <int NV>
+__device__ __forceinline__ float wave_reduce_multi(float (&a)[NV], int lane) {
+  static_assert(NV == 1 || NV == 2 || NV == 4 || NV == 8 || NV == 16, "NV must be 2^m, m <= 4");
+  if constexpr (NV >= 2) butterfly_level<NV, 0>(a, lane);
+  if constexpr (NV >= 4) butterfly_level<NV / 2, 1>(a, lane);
+  if constexpr (NV >= 8) butterfly_level<NV / 4, 3>(a, lane);
+  if constexpr (NV >= 16) butterfly_level<NV / 8, 2>(a, lane);
+  float v = a[0];
+  if constexpr (NV < 16) v += lane_xor<2>(v);
+  if constexpr (NV < 8) v += lane_xor<3>(v);
+  if constexpr (NV < 4) v += lane_xor<1>(v);
+  if constexpr (NV < 2) v += lane_xor<0>(v);
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// Index of the value whose total wave_reduce_multi<NV> leaves in `lane`, and whether the lane holds
+// a total to store (one lane per value).
+template <int NV>
+__device__ __forceinline__ int reduce_index(int lane) {
+  int idx = 0;
+  if constexpr (NV >= 2) idx += ((lane >> 0) & 1) * (NV / 2);
+  if constexpr (NV >= 4) idx += ((lane >> 1) & 1) * (NV / 4);
+  if constexpr (NV >= 8) idx += ((lane >> 3) & 1) * (NV / 8);
+  if constexpr (NV >= 16) idx += ((lane >> 2) & 1) * (NV / 16);
+  return idx;
+}
+
+template <int NV>
+__device__ __forceinline__ bool reduce_owner(int lane) {
+  int used = 0;
+  if constexpr (NV >= 2) used |= 1;
+  if constexpr (NV >= 4) used |= 2;
+  if constexpr (NV >= 8) used |= 8;
+  if constexpr (NV >= 16) used |= 4;
+  return (lane & ~used) == 0;
+}
+
+__host__ __device__ constexpr int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p *= 2;
+  return p;
+}
+
 // out[j] = sum_k conj(h_k) in[j+k] for j in [lo, hi); reads in[lo-K, hi+RB+K-2].  SYM: folded.
 template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM>
 __device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
@@ -192,18 +272,42 @@ __device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, in
   }
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
+  double* redd = reinterpret_cast<double*>(red);
+  constexpr int NV = pow2_at_least(2 * NA);
+  if constexpr (sizeof(R) == 4 && NV <= 16) {
+    // all 2 NA components reduced together; value 2a + c is component c of accumulator a
+    float vals[NV];
 #pragma unroll
-  for (int k = 0; k < NA; ++k) {
-    const R sx = wave_sum_last(acc[k].x);
-    const R sy = wave_sum_last(acc[k].y);
-    if (lane == kLastLane) {
+    for (int a = 0; a < NV / 2; ++a) {
+      vals[2 * a] = a < NA ? acc[a].x : 0.f;
+      vals[2 * a + 1] = a < NA ? acc[a].y : 0.f;
+    }
+    const float tot = wave_reduce_multi<NV>(vals, lane);
+    const int idx = reduce_index<NV>(lane);
+    if (reduce_owner<NV>(lane) && idx < 2 * NA) {
+      const int a = idx >> 1, comp = idx & 1;
       if constexpr (SYM) {
-        const double f = k == 0 ? 1.0 : 0.5;
-        const double2 v{f * static_cast<double>(sx), f * static_cast<double>(sy)};
-        red[wv * ldr + col0 + K + k] = v;
-        red[wv * ldr + col0 + K - k] = v;
+        const double v = (a == 0 ? 1.0 : 0.5) * static_cast<double>(tot);
+        redd[2 * (wv * ldr + col0 + K + a) + comp] = v;
+        redd[2 * (wv * ldr + col0 + K - a) + comp] = v;
       } else {
-        red[wv * ldr + col0 + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+        redd[2 * (wv * ldr + col0 + a) + comp] = static_cast<double>(tot);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const R sx = wave_sum_last(acc[k].x);
+      const R sy = wave_sum_last(acc[k].y);
+      if (lane == kLastLane) {
+        if constexpr (SYM) {
+          const double f = k == 0 ? 1.0 : 0.5;
+          const double2 v{f * static_cast<double>(sx), f * static_cast<double>(sy)};
+          red[wv * ldr + col0 + K + k] = v;
+          red[wv * ldr + col0 + K - k] = v;
+        } else {
+          red[wv * ldr + col0 + k] = double2{static_cast<double>(sx), static_cast<double>(sy)};
+        }
       }
     }
   }
