@@ -157,3 +157,29 @@ def test_forward_symmetric_folded_evaluation(npol, dtype, tol):
     for rb in rbs:
         y = _run(x, taps, c, npol=npol, dtype=dtype, plan=(0, 0, rb, 1))
         assert _rel(y, ref) <= tol, rb
+
+
+def test_forward_full_size_dual_pol_8x1048576_sampled():
+    """Dual-polarisation configuration at full size: 8 x 1,048,576 samples x 2 polarisations, l = 64
+    (2 steps per 80 km span, 32 spans), 5 taps shared by both polarisations, Manakov phase (8/9), folded
+    symmetric filters, in the plan the bench's autotuner picks ([14, 1, 5, 1]) and the default plan.
+
+    Stand-in model: in-band LS taps scaled to unit peak gain (5-tap LS filters cascaded over 64 steps
+    amplify out-of-band content without bound and make any finite-precision comparison chaotic).
+    Inputs: CN(0, P) per polarisation.  Sampled outputs: each sample's dependency cone (+-128 samples)
+    through the oracle."""
+    print("case: full size dual pol 8x1048576x2", flush=True)
+    nwave, n = 8, 1 << 20
+    p = 10 ** ((2.0 - 30) / 10)
+    x = synth.complex_normal(501, (nwave, n, 2)) * math.sqrt(p)
+    taps, c = W.ldbp_init(32, 2, 5, span_km=80.0, kerr_scale=8.0 / 9.0)
+    taps = [W.unit_peak_gain(0.5 * (h + h[::-1])) for h in taps]
+    H = sum((len(h) - 1) // 2 for h in taps)
+    g = synth.rng(502)
+    for plan in ((14, 1, 5, 1), (0, 0, 0, 1)):
+        y = _run(x, taps, c, npol=2, plan=plan)
+        for b in range(nwave):
+            for m in [0, n - 1, int(g.integers(0, n)), int(g.integers(0, n))]:
+                win = W.cone_sample(x[b], m, H)
+                ref = O.ldbp_forward(win, taps, c, npol=2)[H]
+                assert np.max(np.abs(y[b, m] - ref)) <= 2e-4 * math.sqrt(p), (plan, b, m)

@@ -42,7 +42,8 @@ def _wave(seed, nwave, n, npol, p):
     return synth.complex_normal(seed, shape) * math.sqrt(p)
 
 
-CASES = [(256, 1), (4096, 1), (8192, 1), (65536, 1), (131072, 1), (2048, 2), (4096, 2), (16384, 2), (1 << 20, 2)]
+CASES = [(256, 1), (4096, 1), (8192, 1), (65536, 1), (131072, 1), (2048, 2), (4096, 2), (16384, 2), (1 << 20, 2),
+         (1 << 21, 2)]
 
 
 @pytest.mark.parametrize("n,npol", CASES)
