@@ -40,7 +40,8 @@ LDBP_STPS, TAPS = 5, 15
 P_DBM = 4.0
 RS = 10.7e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ldbp_fwd_traffic.json")
-KERNEL_SOURCES = ["paper_2010_14258_amd/csrc/ldbp_fwd.hip", "paper_2010_14258_amd/csrc/ldbp_fir.h",
+KERNEL_SOURCES = ["paper_2010_14258_amd/csrc/ldbp_fwd.hip", "paper_2010_14258_amd/csrc/ldbp_fwd_impl.h",
+                  "paper_2010_14258_amd/csrc/ldbp_fir.h",
                   "paper_2010_14258_amd/csrc/common.h"]
 
 

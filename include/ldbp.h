@@ -54,6 +54,7 @@ enum ldbp_status {
 enum ldbp_dtype { LDBP_C64 = 0, LDBP_C128 = 1 };
 
 #define LDBP_MAX_TAPS 63 /* largest odd filter length per step */
+#define LDBP_MAX_NL_TAPS 63 /* largest odd power-filter length per step (generalised ESSM) */
 #define LDBP_MAX_STEPS_PER_PASS 64
 
 /* Execution plan of the time-blocked forward.  Zero fields mean "choose".
@@ -119,6 +120,33 @@ int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
 int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
                             const int32_t* ntap, int32_t ckpt_every, const ldbp_plan* plan, int32_t* npasses,
                             int32_t* tile_len, int32_t* max_steps_per_pass);
+
+/* ---------------------------------------------------------------------------
+ * Generalised enhanced SSM (Sec. III-D, eq. nl_filtered with a filter per step): LDBP whose
+ * nonlinear steps filter the power before the phase.  Step i is
+ *   u   = h^(i) * x                                        (as in ldbp_forward)
+ *   F_j = sum_{k=-kappa_i}^{kappa_i} eta^(i)_k |u_{(j-k) mod n}|^2   (summed over polarisations)
+ *   y_j = u_j exp(j c_i F_j)
+ * with real filters eta^(i) of odd length nl_ntap[i] = 2 kappa_i + 1.  eta^(i) = (1) is the LDBP
+ * step.  Arguments as for ldbp_forward, plus
+ *   nl_ntap      host [nstep], odd, 1 <= nl_ntap[i] <= LDBP_MAX_NL_TAPS
+ *   eta          device [sum nl_ntap] real (float for LDBP_C64, double for LDBP_C128), filter i at
+ *                offset sum_{j<i} nl_ntap[j], index kappa_i + k holding eta_k
+ * The halo of a step is K_i + kappa_i; a pass also keeps the power of its tile in LDS.
+ * -------------------------------------------------------------------------*/
+int essm_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                const int32_t* ntap, const int32_t* nl_ntap, const void* ckpt,
+                                int32_t ckpt_every, const ldbp_plan* plan, size_t* bytes);
+
+int essm_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                 const int32_t* ntap, const int32_t* nl_ntap, const void* taps, const void* c,
+                 const void* eta, const void* x, void* y, void* ckpt, int32_t ckpt_every,
+                 const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream);
+
+int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                            const int32_t* ntap, const int32_t* nl_ntap, int32_t ckpt_every,
+                            const ldbp_plan* plan, int32_t* npasses, int32_t* tile_len,
+                            int32_t* max_steps_per_pass);
 
 /* ---------------------------------------------------------------------------
  * LDBP backward: gradients of a real loss L through y = f_theta(x).  The paper

@@ -15,6 +15,10 @@ struct ModelArgs {
   int64_t nwave, n;
   int32_t nstep;
   const int32_t* ntap;
+  const int32_t* nl_ntap = nullptr;  // filtered nonlinear steps (generalised ESSM): real filter lengths
+
+  int kap(int i) const { return nl_ntap ? (nl_ntap[i] - 1) / 2 : 0; }
+  bool filtered() const { return nl_ntap != nullptr; }
 };
 
 static int check_model(const ModelArgs& m) {
@@ -28,13 +32,18 @@ static int check_model(const ModelArgs& m) {
     const int t = m.ntap[i];
     if (t < 1 || t > LDBP_MAX_TAPS || (t % 2) == 0)
       return fail(LDBP_EINVAL, "ntap[%d] = %d must be odd and in [1, %d]", i, t, LDBP_MAX_TAPS);
+    if (m.nl_ntap) {
+      const int e = m.nl_ntap[i];
+      if (e < 1 || e > LDBP_MAX_NL_TAPS || (e % 2) == 0)
+        return fail(LDBP_EINVAL, "nl_ntap[%d] = %d must be odd and in [1, %d]", i, e, LDBP_MAX_NL_TAPS);
+    }
   }
   return LDBP_OK;
 }
 
-static int max_chunks(int dtype, int npol, int rb) {
+static int max_chunks(int dtype, int npol, int rb, bool filtered = false) {
   int c = 1;
-  while (fwd_lds_bytes(dtype, npol, rb, c + 1) <= kMaxLdsBytes) ++c;
+  while (fwd_lds_bytes(dtype, npol, rb, c + 1, filtered) <= kMaxLdsBytes) ++c;
   return c;
 }
 
@@ -57,17 +66,19 @@ static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* pl
   out.sym = (plan && (plan->flags & LDBP_PLAN_SYMMETRIC)) ? 1 : 0;
   const int chunk = fwd_chunk(m.dtype, m.npol, rb);
   int chunks = (plan && plan->chunks > 0) ? plan->chunks : 1;
-  const int cmax = max_chunks(m.dtype, m.npol, rb);
+  const int cmax = max_chunks(m.dtype, m.npol, rb, m.filtered());
   if (chunks > cmax) return fail(LDBP_EINVAL, "plan chunks %d exceeds the LDS limit (%d)", chunks, cmax);
   const int fixed_s = ckpt_every > 0 ? ckpt_every : ((plan && plan->steps_per_pass > 0) ? plan->steps_per_pass : 0);
   if (fixed_s > LDBP_MAX_STEPS_PER_PASS)
     return fail(LDBP_EINVAL, "steps per pass %d exceeds %d", fixed_s, LDBP_MAX_STEPS_PER_PASS);
 
-  std::vector<int32_t> tapoff(m.nstep);
-  int32_t acc = 0;
+  std::vector<int32_t> tapoff(m.nstep), etaoff(m.nstep);
+  int32_t acc = 0, eacc = 0;
   for (int i = 0; i < m.nstep; ++i) {
     tapoff[i] = acc;
     acc += m.ntap[i];
+    etaoff[i] = eacc;
+    eacc += m.nl_ntap ? m.nl_ntap[i] : 1;
   }
   out.passes.clear();
   int s = 0;
@@ -78,14 +89,17 @@ static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* pl
     int h = 0;
     int cnt = 0;
     while (s + cnt < m.nstep && cnt < LDBP_MAX_STEPS_PER_PASS) {
-      const int k = (m.ntap[s + cnt] - 1) / 2;
+      const int kf = (m.ntap[s + cnt] - 1) / 2;
+      const int k = kf + m.kap(s + cnt);  // halo of the step: FIR half-length plus power-filter half-length
       if (fixed_s > 0) {
         if (cnt >= fixed_s) break;
       } else if (cnt > 0 && 2 * (h + k) * 8 > chunks * chunk) {
         break;
       }
-      pt.K[cnt] = k;
+      pt.K[cnt] = kf;
       pt.tapoff[cnt] = tapoff[s + cnt];
+      pt.kap[cnt] = m.kap(s + cnt);
+      pt.etaoff[cnt] = etaoff[s + cnt];
       h += k;
       ++cnt;
     }
@@ -113,7 +127,7 @@ static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ld
   int st = make_plan(m, S, plan, out);  // exact blocks: validates rb, chunks and the per-block halo
   if (st) return st;
   const int chunk = fwd_chunk(m.dtype, m.npol, out.rb);
-  const int cmax = max_chunks(m.dtype, m.npol, out.rb);
+  const int cmax = max_chunks(m.dtype, m.npol, out.rb, m.filtered());
   const int want = (plan && plan->steps_per_pass > 0) ? std::max<int>(S, plan->steps_per_pass / S * S) : 0;
   std::vector<PassTable> blocks;
   for (const auto& b : out.passes)
@@ -133,6 +147,8 @@ static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ld
       for (int k = 0; k < b.nstep; ++k) {
         pt.K[pt.nstep + k] = b.K[k];
         pt.tapoff[pt.nstep + k] = b.tapoff[k];
+        pt.kap[pt.nstep + k] = b.kap[k];
+        pt.etaoff[pt.nstep + k] = b.etaoff[k];
       }
       pt.nstep += b.nstep;
       pt.halo += b.halo;
@@ -155,7 +171,7 @@ static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ld
 // Runs steps [0, pp's last step] from x, writing every block input b >= 1 to slot b - 1 of ckpt;
 // the output of the final pass goes to `last` (y, or the last slot).
 static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* taps, const void* c, const void* x,
-                          void* last, void* ckpt, int32_t S, hipStream_t s) {
+                          void* last, void* ckpt, int32_t S, hipStream_t s, const void* eta = nullptr) {
   const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
   const void* in = x;
   for (size_t i = 0; i < pp.passes.size(); ++i) {
@@ -163,7 +179,7 @@ static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* ta
     void* out = (i + 1 == pp.passes.size()) ? last
                                             : static_cast<char*>(ckpt) + ((pt.c0 + pt.nstep) / S - 1) * wave_bytes;
     int st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, m.nwave, static_cast<int32_t>(m.n), pp.chunks, pt, taps,
-                             c, pp.sym, ckpt, s);
+                             c, pp.sym, ckpt, s, eta);
     if (st) return st;
     in = out;
   }
@@ -174,11 +190,10 @@ static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* ta
 
 using namespace ldbp;
 
-extern "C" int ldbp_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
-                                           const int32_t* ntap, const void* ckpt, int32_t ckpt_every,
-                                           const ldbp_plan* plan, size_t* bytes) {
+namespace ldbp {
+
+static int forward_ws_impl(const ModelArgs& m, const void* ckpt, const ldbp_plan* plan, size_t* bytes) {
   if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
-  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
   int st = check_model(m);
   if (st) return st;
   if (ckpt) {
@@ -188,36 +203,39 @@ extern "C" int ldbp_forward_workspace_size(int32_t dtype, int32_t npol, int64_t 
   PassPlan pp;
   st = make_plan(m, 0, plan, pp);
   if (st) return st;
-  *bytes = pp.passes.size() > 1 ? static_cast<size_t>(nwave) * n * npol * cx_size(dtype) : 0;
+  *bytes = pp.passes.size() > 1 ? static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype) : 0;
   return LDBP_OK;
 }
 
-extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
-                            const int32_t* ntap, const void* taps, const void* c, const void* x, void* y,
-                            void* ckpt, int32_t ckpt_every, const ldbp_plan* plan, void* ws, size_t ws_bytes,
-                            void* stream) {
-  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+// The forward of LDBP (eta == NULL) and of the generalised ESSM (eta: packed real filters, m.nl_ntap).
+static int forward_impl(const ModelArgs& m, const void* taps, const void* c, const void* eta, const void* x, void* y,
+                        void* ckpt, int32_t ckpt_every, const ldbp_plan* plan, void* ws, size_t ws_bytes,
+                        void* stream) {
   int st = check_model(m);
   if (st) return st;
   if (!taps || !c || !x || !y) return fail(LDBP_EINVAL, "taps, c, x and y must be non-NULL");
+  if (m.filtered() && !eta) return fail(LDBP_EINVAL, "eta must be non-NULL");
   if (!aligned16(taps) || !aligned16(x) || !aligned16(y)) return fail(LDBP_EINVAL, "taps, x and y must be 16-byte aligned");
-  if (reinterpret_cast<uintptr_t>(c) % real_size(dtype)) return fail(LDBP_EINVAL, "c is not aligned to its real type");
-  const size_t wave_bytes = static_cast<size_t>(nwave) * n * npol * cx_size(dtype);
+  if (reinterpret_cast<uintptr_t>(c) % real_size(m.dtype)) return fail(LDBP_EINVAL, "c is not aligned to its real type");
+  if (eta && reinterpret_cast<uintptr_t>(eta) % real_size(m.dtype))
+    return fail(LDBP_EINVAL, "eta is not aligned to its real type");
+  const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
   if (overlaps(x, wave_bytes, y, wave_bytes)) return fail(LDBP_EINVAL, "x and y overlap");
   if (ckpt) {
     if (ckpt_every < 1 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
       return fail(LDBP_EINVAL, "ckpt_every %d outside [1, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
     if (!aligned16(ckpt)) return fail(LDBP_EINVAL, "ckpt must be 16-byte aligned");
-    const int64_t nslot = (nstep + ckpt_every - 1) / ckpt_every - 1;
+    const int64_t nslot = (m.nstep + ckpt_every - 1) / ckpt_every - 1;
     if (nslot > 0 && (overlaps(ckpt, nslot * wave_bytes, x, wave_bytes) || overlaps(ckpt, nslot * wave_bytes, y, wave_bytes)))
       return fail(LDBP_EINVAL, "ckpt overlaps x or y");
   }
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* e = m.filtered() ? eta : nullptr;
   if (ckpt) {
     PassPlan bp;
-    st = make_block_plan(m, ckpt_every, nstep, plan, bp);
+    st = make_block_plan(m, ckpt_every, m.nstep, plan, bp);
     if (st) return st;
-    return run_block_plan(m, bp, taps, c, x, y, ckpt, ckpt_every, s);
+    return run_block_plan(m, bp, taps, c, x, y, ckpt, ckpt_every, s, e);
   }
   PassPlan pp;
   st = make_plan(m, 0, plan, pp);
@@ -233,12 +251,75 @@ extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
   const void* in = x;
   for (size_t i = 0; i < np; ++i) {
     void* out = ((np - 1 - i) % 2 == 0) ? y : ws;  // ping-pong that ends in y
-    st = launch_fwd_pass(dtype, npol, pp.rb, in, out, nwave, static_cast<int32_t>(n), pp.chunks, pp.passes[i], taps, c,
-                         pp.sym, nullptr, s);
+    st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, m.nwave, static_cast<int32_t>(m.n), pp.chunks, pp.passes[i],
+                         taps, c, pp.sym, nullptr, s, e);
     if (st) return st;
     in = out;
   }
   return LDBP_OK;
+}
+
+static int plan_query_impl(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* plan, int32_t* npasses,
+                           int32_t* tile_len, int32_t* max_steps_per_pass) {
+  int st = check_model(m);
+  if (st) return st;
+  if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
+    return fail(LDBP_EINVAL, "ckpt_every %d outside [0, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
+  PassPlan pp;
+  st = ckpt_every > 0 ? make_block_plan(m, ckpt_every, m.nstep, plan, pp) : make_plan(m, 0, plan, pp);
+  if (st) return st;
+  int maxs = 0, minlen = 1 << 30;
+  for (const auto& pt : pp.passes) {
+    maxs = std::max(maxs, pt.nstep);
+    minlen = std::min(minlen, pp.chunks * fwd_chunk(m.dtype, m.npol, pp.rb) - 2 * pt.halo);
+  }
+  if (npasses) *npasses = static_cast<int32_t>(pp.passes.size());
+  if (tile_len) *tile_len = minlen;
+  if (max_steps_per_pass) *max_steps_per_pass = maxs;
+  return LDBP_OK;
+}
+
+}  // namespace ldbp
+
+extern "C" int ldbp_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                           const int32_t* ntap, const void* ckpt, int32_t ckpt_every,
+                                           const ldbp_plan* plan, size_t* bytes) {
+  (void)ckpt_every;
+  return forward_ws_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap}, ckpt, plan, bytes);
+}
+
+extern "C" int ldbp_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                            const int32_t* ntap, const void* taps, const void* c, const void* x, void* y,
+                            void* ckpt, int32_t ckpt_every, const ldbp_plan* plan, void* ws, size_t ws_bytes,
+                            void* stream) {
+  return forward_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap}, taps, c, nullptr, x, y, ckpt, ckpt_every, plan,
+                      ws, ws_bytes, stream);
+}
+
+extern "C" int essm_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                           const int32_t* ntap, const int32_t* nl_ntap, const void* ckpt,
+                                           int32_t ckpt_every, const ldbp_plan* plan, size_t* bytes) {
+  (void)ckpt_every;
+  if (!nl_ntap) return fail(LDBP_EINVAL, "nl_ntap is NULL");
+  return forward_ws_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap, nl_ntap}, ckpt, plan, bytes);
+}
+
+extern "C" int essm_forward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                            const int32_t* ntap, const int32_t* nl_ntap, const void* taps, const void* c,
+                            const void* eta, const void* x, void* y, void* ckpt, int32_t ckpt_every,
+                            const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  if (!nl_ntap) return fail(LDBP_EINVAL, "nl_ntap is NULL");
+  return forward_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap, nl_ntap}, taps, c, eta, x, y, ckpt, ckpt_every,
+                      plan, ws, ws_bytes, stream);
+}
+
+extern "C" int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                       const int32_t* ntap, const int32_t* nl_ntap, int32_t ckpt_every,
+                                       const ldbp_plan* plan, int32_t* npasses, int32_t* tile_len,
+                                       int32_t* max_steps_per_pass) {
+  if (!nl_ntap) return fail(LDBP_EINVAL, "nl_ntap is NULL");
+  return plan_query_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap, nl_ntap}, ckpt_every, plan, npasses, tile_len,
+                         max_steps_per_pass);
 }
 
 // ---------------------------------------------------------------- backward
@@ -395,21 +476,6 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
 extern "C" int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
                                        const int32_t* ntap, int32_t ckpt_every, const ldbp_plan* plan,
                                        int32_t* npasses, int32_t* tile_len, int32_t* max_steps_per_pass) {
-  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
-  int st = check_model(m);
-  if (st) return st;
-  if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
-    return fail(LDBP_EINVAL, "ckpt_every %d outside [0, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
-  PassPlan pp;
-  st = ckpt_every > 0 ? make_block_plan(m, ckpt_every, nstep, plan, pp) : make_plan(m, 0, plan, pp);
-  if (st) return st;
-  int maxs = 0, minlen = 1 << 30;
-  for (const auto& pt : pp.passes) {
-    maxs = std::max(maxs, pt.nstep);
-    minlen = std::min(minlen, pp.chunks * fwd_chunk(dtype, npol, pp.rb) - 2 * pt.halo);
-  }
-  if (npasses) *npasses = static_cast<int32_t>(pp.passes.size());
-  if (tile_len) *tile_len = minlen;
-  if (max_steps_per_pass) *max_steps_per_pass = maxs;
-  return LDBP_OK;
+  return plan_query_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap}, ckpt_every, plan, npasses, tile_len,
+                         max_steps_per_pass);
 }

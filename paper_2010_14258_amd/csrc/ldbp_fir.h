@@ -12,9 +12,12 @@ namespace ldbp {
 // h_0 x_m + sum_{k>=1} h_k (x_{m-k} + x_{m+k}) (the folded structure of Sec. III-B), which
 // needs K + 1 complex multiplies instead of 2K + 1.
 // An odd RB keeps the lanes' window starts on distinct LDS banks (stride RB * 8 bytes).
-template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM>
+// LIN: no phase; out receives u and pw[j] = |u_j|^2 (summed over polarisations), the input of a
+// filtered nonlinear step (nl_filter below).
+template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM, bool LIN = false>
 __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out,
-                                               int lo, int hi, const cx_t<R>* __restrict__ h, R coef) {
+                                               int lo, int hi, const cx_t<R>* __restrict__ h, R coef,
+                                               R* __restrict__ pw = nullptr) {
   using V = cx_t<R>;
   constexpr int W = RB + 2 * K;
   for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
@@ -60,18 +63,26 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      R pw = 0;
+      R pwr = 0;
 #pragma unroll
-      for (int p = 0; p < NPOL; ++p) pw += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
-      R s, co;
-      phase_sincos(coef, pw, s, co);
-      if (base + r < hi) {
+      for (int p = 0; p < NPOL; ++p) pwr += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
+      if constexpr (LIN) {
+        if (base + r < hi) {
+          pw[base + r] = pwr;
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) {
-          V o;
-          o.x = acc[r][p].x * co - acc[r][p].y * s;
-          o.y = acc[r][p].x * s + acc[r][p].y * co;
-          out[(base + r) * NPOL + p] = o;
+          for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+        }
+      } else {
+        R s, co;
+        phase_sincos(coef, pwr, s, co);
+        if (base + r < hi) {
+#pragma unroll
+          for (int p = 0; p < NPOL; ++p) {
+            V o;
+            o.x = acc[r][p].x * co - acc[r][p].y * s;
+            o.y = acc[r][p].x * s + acc[r][p].y * co;
+            out[(base + r) * NPOL + p] = o;
+          }
         }
       }
     }
@@ -79,9 +90,10 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
 }
 
 // Filters longer than the unrolled range: taps streamed, inputs read from LDS per tap.
-template <typename R, int NPOL, int RB, int THREADS>
+template <typename R, int NPOL, int RB, int THREADS, bool LIN = false>
 __device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out,
-                                                 int lo, int hi, int K, const cx_t<R>* __restrict__ h, R coef) {
+                                                 int lo, int hi, int K, const cx_t<R>* __restrict__ h, R coef,
+                                                 R* __restrict__ pw = nullptr) {
   using V = cx_t<R>;
   for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
     V acc[RB][NPOL];
@@ -98,36 +110,118 @@ __device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in,
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      R pw = 0;
+      R pwr = 0;
 #pragma unroll
-      for (int p = 0; p < NPOL; ++p) pw += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
-      R s, co;
-      phase_sincos(coef, pw, s, co);
-      if (base + r < hi) {
+      for (int p = 0; p < NPOL; ++p) pwr += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
+      if constexpr (LIN) {
+        if (base + r < hi) {
+          pw[base + r] = pwr;
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) {
-          V o;
-          o.x = acc[r][p].x * co - acc[r][p].y * s;
-          o.y = acc[r][p].x * s + acc[r][p].y * co;
-          out[(base + r) * NPOL + p] = o;
+          for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+        }
+      } else {
+        R s, co;
+        phase_sincos(coef, pwr, s, co);
+        if (base + r < hi) {
+#pragma unroll
+          for (int p = 0; p < NPOL; ++p) {
+            V o;
+            o.x = acc[r][p].x * co - acc[r][p].y * s;
+            o.y = acc[r][p].x * s + acc[r][p].y * co;
+            out[(base + r) * NPOL + p] = o;
+          }
         }
       }
     }
   }
 }
 
-template <typename R, int NPOL, int RB, int THREADS, bool SYM>
+template <typename R, int NPOL, int RB, int THREADS, bool SYM, bool LIN = false>
 __device__ __forceinline__ void fir_kerr_dispatch_t(const cx_t<R>* in, cx_t<R>* out, int lo, int hi, int K,
-                                                    const cx_t<R>* h, R coef) {
+                                                    const cx_t<R>* h, R coef, R* pw = nullptr) {
   switch (K) {
 #define LDBP_FWD_CASE(k) \
-  case k: fir_kerr_fixed<R, NPOL, RB, THREADS, k, SYM>(in, out, lo, hi, h, coef); break;
+  case k: fir_kerr_fixed<R, NPOL, RB, THREADS, k, SYM, LIN>(in, out, lo, hi, h, coef, pw); break;
     LDBP_FWD_CASE(0) LDBP_FWD_CASE(1) LDBP_FWD_CASE(2) LDBP_FWD_CASE(3)
     LDBP_FWD_CASE(4) LDBP_FWD_CASE(5) LDBP_FWD_CASE(6) LDBP_FWD_CASE(7)
     LDBP_FWD_CASE(8) LDBP_FWD_CASE(9) LDBP_FWD_CASE(10) LDBP_FWD_CASE(11)
     LDBP_FWD_CASE(12)
 #undef LDBP_FWD_CASE
-    default: fir_kerr_generic<R, NPOL, RB, THREADS>(in, out, lo, hi, K, h, coef); break;
+    default: fir_kerr_generic<R, NPOL, RB, THREADS, LIN>(in, out, lo, hi, K, h, coef, pw); break;
+  }
+}
+
+// The linear part of a filtered step: out = h * in over [lo, hi) and pw = |out|^2 there.
+template <typename R, int NPOL, int RB, int THREADS>
+__device__ __forceinline__ void fir_lin_dispatch(const cx_t<R>* in, cx_t<R>* out, R* pw, int lo, int hi, int K,
+                                                 const cx_t<R>* h, bool sym) {
+  if (sym) fir_kerr_dispatch_t<R, NPOL, RB, THREADS, true, true>(in, out, lo, hi, K, h, R(0), pw);
+  else fir_kerr_dispatch_t<R, NPOL, RB, THREADS, false, true>(in, out, lo, hi, K, h, R(0), pw);
+}
+
+// Filtered nonlinear step (generalised ESSM, eq. nl_filtered with a filter per step), in place:
+// u_m <- u_m exp(j coef F_m), F_m = sum_{k=-KAP}^{KAP} eta_k pw_{m-k}, for m in [lo, hi).  RB outputs
+// per thread from a register window of RB + 2 KAP powers; reads pw[lo-KAP, hi+RB+KAP-2].
+template <typename R, int NPOL, int RB, int THREADS, int KAP>
+__device__ __forceinline__ void nl_filter_fixed(cx_t<R>* __restrict__ u, const R* __restrict__ pw, int lo, int hi,
+                                                const R* __restrict__ eta, R coef) {
+  using V = cx_t<R>;
+  constexpr int W = RB + 2 * KAP;
+  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
+    R win[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) win[j] = pw[base - KAP + j];
+    R F[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) F[r] = 0;
+#pragma unroll
+    for (int k = -KAP; k <= KAP; ++k) {
+      const R e = eta[KAP + k];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) F[r] = fma(e, win[r - k + KAP], F[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (base + r < hi) {
+        R s, co;
+        phase_sincos(coef, F[r], s, co);
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+          const V a = u[(base + r) * NPOL + p];
+          u[(base + r) * NPOL + p] = V{a.x * co - a.y * s, a.x * s + a.y * co};
+        }
+      }
+    }
+  }
+}
+
+template <typename R, int NPOL, int RB, int THREADS>
+__device__ __forceinline__ void nl_filter_generic(cx_t<R>* __restrict__ u, const R* __restrict__ pw, int lo, int hi,
+                                                  int kap, const R* __restrict__ eta, R coef) {
+  using V = cx_t<R>;
+  for (int m = lo + static_cast<int>(threadIdx.x); m < hi; m += THREADS) {
+    R F = 0;
+    for (int k = -kap; k <= kap; ++k) F = fma(eta[kap + k], pw[m - k], F);
+    R s, co;
+    phase_sincos(coef, F, s, co);
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) {
+      const V a = u[m * NPOL + p];
+      u[m * NPOL + p] = V{a.x * co - a.y * s, a.x * s + a.y * co};
+    }
+  }
+}
+
+template <typename R, int NPOL, int RB, int THREADS>
+__device__ __forceinline__ void nl_filter_dispatch(cx_t<R>* u, const R* pw, int lo, int hi, int kap, const R* eta,
+                                                   R coef) {
+  switch (kap) {
+#define LDBP_NL_CASE(k) \
+  case k: nl_filter_fixed<R, NPOL, RB, THREADS, k>(u, pw, lo, hi, eta, coef); break;
+    LDBP_NL_CASE(0) LDBP_NL_CASE(1) LDBP_NL_CASE(2) LDBP_NL_CASE(3) LDBP_NL_CASE(4) LDBP_NL_CASE(5)
+    LDBP_NL_CASE(6) LDBP_NL_CASE(8) LDBP_NL_CASE(10) LDBP_NL_CASE(12) LDBP_NL_CASE(16) LDBP_NL_CASE(20)
+#undef LDBP_NL_CASE
+    default: nl_filter_generic<R, NPOL, RB, THREADS>(u, pw, lo, hi, kap, eta, coef); break;
   }
 }
 

@@ -1,0 +1,117 @@
+// LDBP forward kernel (included by the files that instantiate it): time-blocked fused FIR + Kerr
+// passes (eq. model, Sec. III-B).
+//
+// One pass applies S consecutive steps u = h * x (circular, centred, T = 2K+1
+// taps), y = u exp(j c |u|^2) to a tile of L output samples.  The workgroup
+// loads the tile plus a halo of H = sum K over the S steps (wrapping around the
+// circular waveform), keeps the signal in LDS between steps (ping-pong buffers),
+// and writes only the L samples whose dependency cone was fully loaded.  After
+// step s the valid region has shrunk by K_s on each side.  Each thread
+// produces RB consecutive outputs from a register window of RB + 2K inputs.
+// A pass may span several checkpoint blocks: at an inner block boundary the tile's own L
+// samples (valid after every step of the pass) are also written to that block's checkpoint slot.
+#pragma once
+
+#include "common.h"
+#include "ldbp_fir.h"
+#include "ldbp_kernels.h"
+
+namespace ldbp {
+
+constexpr int kFwdThreads = 256;
+
+
+// FILT: the steps are filtered nonlinear steps (eta != NULL); CKPT: the pass writes inner checkpoints.
+// Separate instantiations keep the plain LDBP kernel's registers (and occupancy) unchanged.
+template <typename R, int NPOL, int RB, int THREADS, bool FILT, bool CKPT>
+__global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __restrict__ x, cx_t<R>* __restrict__ y,
+                                                           int32_t n, int32_t tile_len, int32_t ntiles,
+                                                           int32_t work, const cx_t<R>* __restrict__ taps,
+                                                           const R* __restrict__ c, PassTable pt, int32_t sym,
+                                                           cx_t<R>* __restrict__ ckpt, int64_t slot_elems,
+                                                           const R* __restrict__ eta) {
+  using V = cx_t<R>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  V* b0 = reinterpret_cast<V*>(smem);
+  V* b1 = b0 + static_cast<size_t>(work + RB) * NPOL;
+  R* pwb = reinterpret_cast<R*>(b1 + static_cast<size_t>(work + RB) * NPOL);  // filtered steps only
+
+  const int tile = static_cast<int>(blockIdx.x % static_cast<uint32_t>(ntiles));
+  const int64_t wave = blockIdx.x / static_cast<uint32_t>(ntiles);
+  const int t0 = tile * tile_len;
+  const int Lw = min(tile_len, n - t0);
+  const int H = pt.halo;
+  const int W0 = Lw + 2 * H;
+  const V* xw = x + wave * static_cast<int64_t>(n) * NPOL;
+  V* yw = y + wave * static_cast<int64_t>(n) * NPOL;
+
+  load_tile<R, NPOL, THREADS>(xw, b0, n, t0, H, W0, pt.wrap_general);
+  __syncthreads();
+
+  int lo = 0;
+  for (int s = 0; s < pt.nstep; ++s) {
+    const int K = pt.K[s];
+    lo += K;
+    const R coef = c[pt.c0 + s] * phase_coef_scale<R>();
+    if constexpr (FILT) {
+      // filtered step: linear part and power, then the phase from the filtered power (the valid
+      // region shrinks by K, then by kappa)
+      const int kap = pt.kap[s];
+      fir_lin_dispatch<R, NPOL, RB, THREADS>(b0, b1, pwb, lo, W0 - lo, K, taps + pt.tapoff[s], sym != 0);
+      __syncthreads();
+      lo += kap;
+      nl_filter_dispatch<R, NPOL, RB, THREADS>(b1, pwb, lo, W0 - lo, kap, eta + pt.etaoff[s], coef);
+    } else {
+      fir_kerr_dispatch<R, NPOL, RB, THREADS>(b0, b1, lo, W0 - lo, K, taps + pt.tapoff[s], coef, sym != 0);
+    }
+    __syncthreads();
+    V* t = b0;
+    b0 = b1;
+    b1 = t;
+    if (CKPT && ((pt.ckpt_mask >> s) & 1)) {
+      // the next step writes the other buffer, so b0 stays intact while it is copied out
+      const int64_t slot = (pt.c0 + s + 1) / pt.ckpt_every - 1;
+      V* cw = ckpt + slot * slot_elems + wave * static_cast<int64_t>(n) * NPOL;
+      for (int j = threadIdx.x; j < Lw; j += THREADS) {
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) cw[static_cast<int64_t>(t0 + j) * NPOL + p] = b0[(H + j) * NPOL + p];
+      }
+    }
+  }
+
+  for (int j = threadIdx.x; j < Lw; j += THREADS) {
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) yw[static_cast<int64_t>(t0 + j) * NPOL + p] = b0[(H + j) * NPOL + p];
+  }
+}
+
+template <typename R, int NPOL, int RB>
+inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                             const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
+                             hipStream_t stream, const void* eta) {
+  if (pt.ckpt_mask && (!ckpt || pt.ckpt_every < 1)) return fail(LDBP_EINVAL, "checkpoint writes without slots");
+  const int work = chunks * RB * kFwdThreads;
+  const int tile_len = work - 2 * pt.halo;
+  if (tile_len < 1) return fail(LDBP_EINVAL, "pass halo %d too large for work size %d", pt.halo, work);
+  const int64_t ntiles = (n + tile_len - 1) / tile_len;
+  const int64_t nblocks = ntiles * nwave;
+  if (nblocks > 0x7fffffffLL) return fail(LDBP_EUNSUPPORTED, "grid too large (%lld blocks)", (long long)nblocks);
+  const size_t lds = 2 * static_cast<size_t>(work + RB) * NPOL * sizeof(cx_t<R>) +
+                     (eta ? static_cast<size_t>(work + RB) * sizeof(R) : 0);
+  auto kern = eta ? (pt.ckpt_mask ? ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, true, true>
+                                  : ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, true, false>)
+                  : (pt.ckpt_mask ? ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, false, true>
+                                  : ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, false, false>);
+  if (lds > 65536) LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                      static_cast<int>(lds)));
+  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(nblocks)), dim3(kFwdThreads), lds, stream,
+                     static_cast<const cx_t<R>*>(x), static_cast<cx_t<R>*>(y), n, tile_len,
+                     static_cast<int32_t>(ntiles), work, static_cast<const cx_t<R>*>(taps),
+                     static_cast<const R*>(c), pt, sym, static_cast<cx_t<R>*>(ckpt), nwave * n * NPOL,
+                     static_cast<const R*>(eta));
+  LDBP_HIP_CHECK(hipGetLastError());
+  return LDBP_OK;
+}
+
+}  // namespace ldbp

@@ -20,17 +20,31 @@ struct PassTable {
   int32_t reserved;
   int32_t K[LDBP_MAX_STEPS_PER_PASS];       // half-lengths
   int32_t tapoff[LDBP_MAX_STEPS_PER_PASS];  // offsets into the packed taps
+  // filtered nonlinear steps (generalised ESSM; used only when a filter array is passed):
+  int32_t kap[LDBP_MAX_STEPS_PER_PASS];     // half-lengths of the real power filters
+  int32_t etaoff[LDBP_MAX_STEPS_PER_PASS];  // offsets into the packed filters
 };
 
 // Forward pass kernel geometry: rb = outputs per thread, chunk = 256 * rb samples.
 int fwd_rb_default(int dtype, int npol);
 bool fwd_rb_supported(int dtype, int npol, int rb);
 int fwd_chunk(int dtype, int npol, int rb);
-size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks);
+// filtered: the pass also holds the power of the signal (a real per sample) for filtered steps.
+size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks, bool filtered = false);
 
 // ckpt: base of the checkpoint slots written inside the pass (pt.ckpt_mask), or NULL when the mask is 0.
+// eta: packed real filters of the nonlinear steps (pt.kap / pt.etaoff), or NULL for plain Kerr steps.
 int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
-                    const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream);
+                    const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream,
+                    const void* eta = nullptr);
+
+// Instantiation groups of launch_fwd_pass (separate translation units).
+int launch_fwd_pass_c64p2(int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                          const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
+                          hipStream_t stream, const void* eta);
+int launch_fwd_pass_c128(int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
+                         const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
+                         hipStream_t stream, const void* eta);
 
 // Backward (adjoint) block kernel and the deterministic gradient reduction.
 size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt);

@@ -1,0 +1,76 @@
+"""Python binding of the generalised ESSM entry points (argument marshalling only).
+
+The generalised enhanced SSM is LDBP whose nonlinear steps filter the power before the phase
+(Sec. III-D, eq. nl_filtered with a real filter per step): y_j = u_j exp(j c_i sum_k eta_k |u_{j-k}|^2).
+Layouts as in ``ldbp``; ``eta`` is a real tensor (float32 for complex64, float64 for complex128)
+holding the filters back to back, ``nl_ntap`` their odd lengths.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as N
+from .ldbp import _check_dev, _code, _plan, _ptr, _real_dtype, _shape, stream_handle
+
+
+def _check_model(ntap, nl_ntap, taps, c, eta):
+    if len(nl_ntap) != len(ntap):
+        raise ValueError("nl_ntap must have one entry per step")
+    if taps.numel() != sum(int(t) for t in ntap) or c.numel() != len(ntap) or eta.numel() != sum(int(t) for t in nl_ntap):
+        raise ValueError("taps/c/eta sizes do not match ntap/nl_ntap")
+
+
+def essm_forward_workspace_size(x: torch.Tensor, ntap: Sequence[int], nl_ntap: Sequence[int], npol: int = 1,
+                                ckpt=None, ckpt_every: int = 0, plan=None) -> int:
+    lib = N.load()
+    nwave, n = _shape(x, npol)
+    out = ctypes.c_size_t(0)
+    pl = _plan(plan)
+    N.check(lib.essm_forward_workspace_size(_code(x), npol, nwave, n, len(ntap), N.i32_array(ntap),
+                                            N.i32_array(nl_ntap), _ptr(ckpt), int(ckpt_every),
+                                            ctypes.byref(pl) if pl is not None else None, ctypes.byref(out)))
+    return int(out.value)
+
+
+def essm_forward_plan_query(dtype: int, npol: int, nwave: int, n: int, ntap: Sequence[int], nl_ntap: Sequence[int],
+                            ckpt_every: int = 0, plan=None):
+    """(passes, shortest tile length, most steps fused in a pass) of the forward's execution plan."""
+    lib = N.load()
+    a, b, c = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    pl = _plan(plan)
+    N.check(lib.essm_forward_plan_query(dtype, npol, nwave, n, len(ntap), N.i32_array(ntap), N.i32_array(nl_ntap),
+                                        int(ckpt_every), ctypes.byref(pl) if pl is not None else None,
+                                        ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def essm_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, eta: torch.Tensor, ntap: Sequence[int],
+                 nl_ntap: Sequence[int], npol: int = 1, y: Optional[torch.Tensor] = None,
+                 ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0, plan=None,
+                 ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """y = f_theta(x) with filtered nonlinear steps.  Returns y."""
+    lib = N.load()
+    code = _code(x)
+    nwave, n = _shape(x, npol)
+    _check_dev("x", x)
+    _check_dev("taps", taps, x.dtype)
+    _check_dev("c", c, _real_dtype(code))
+    _check_dev("eta", eta, _real_dtype(code))
+    _check_model(ntap, nl_ntap, taps, c, eta)
+    if y is None:
+        y = torch.empty_like(x)
+    _check_dev("y", y, x.dtype)
+    if ckpt is not None:
+        _check_dev("ckpt", ckpt, x.dtype)
+    pl = _plan(plan)
+    if ws is None:
+        need = essm_forward_workspace_size(x, ntap, nl_ntap, npol, ckpt, ckpt_every, plan)
+        ws = torch.empty(need, dtype=torch.uint8, device=x.device) if need > 0 else None
+    N.check(lib.essm_forward(code, npol, nwave, n, len(ntap), N.i32_array(ntap), N.i32_array(nl_ntap), _ptr(taps),
+                             _ptr(c), _ptr(eta), _ptr(x), _ptr(y), _ptr(ckpt), int(ckpt_every),
+                             ctypes.byref(pl) if pl is not None else None, _ptr(ws),
+                             ws.numel() if ws is not None else 0, stream_handle(stream, x.device)))
+    return y
