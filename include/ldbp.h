@@ -187,6 +187,27 @@ int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t
                   void* gc, const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Generalised ESSM backward: gradients of a real loss through essm_forward (the chain rule of
+ * eq. nl_filtered with a filter per step; the paper trains with standard tools).  For a step with
+ * phi = c F, F = eta * P, P = |u|^2 and q = Im(G_y conj(y)) = dL/dphi:
+ *   dL/dc = sum_j q_j F_j,  dL/deta_k = c sum_j q_j P_{j-k},  r_m = c sum_k eta_k q_{m+k},
+ *   G_u = G_y e^{-j phi} + 2 r u,
+ * and the FIR step as in ldbp_backward.  Arguments as for ldbp_backward, plus nl_ntap and eta as for
+ * essm_forward and
+ *   geta         device [sum nl_ntap] real output, overwritten
+ * Sums over samples are reduced in FP64 in a fixed order (deterministic).
+ * -------------------------------------------------------------------------*/
+int essm_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                 const int32_t* ntap, const int32_t* nl_ntap, const void* ckpt,
+                                 int32_t ckpt_every, size_t* bytes);
+
+int essm_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                  const int32_t* ntap, const int32_t* nl_ntap, const void* taps, const void* c,
+                  const void* eta, const void* x, const void* ckpt, int32_t ckpt_every, const void* gy,
+                  void* gx, void* gtaps, void* gc, void* geta, const ldbp_plan* plan, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched LDBP inference over uneven waveforms (eq. model for each waveform of the batch).
  * Waveform b has wave_len[b] samples, wave_nstep[b] steps with tap counts
  * step_ntap[sum_{j<b} wave_nstep[j] + s], its own taps and Kerr coefficients.  Packed layouts:

@@ -65,6 +65,11 @@ SIGNATURES = {
                                c_void_p]),
     "essm_forward_plan_query": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32, c_int32,
                                           P_plan, P_i32, P_i32, P_i32]),
+    "essm_backward_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32,
+                                               c_void_p, c_int32, P_size]),
+    "essm_backward": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32, c_void_p, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, P_plan, c_void_p, c_size_t, c_void_p]),
     "ldbp_backward_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p,
                                                c_int32, P_size]),
     "ldbp_backward": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p, c_void_p, c_void_p,

@@ -346,8 +346,9 @@ struct BwdLayout {
   int32_t S;
   int32_t tile_len;
   int64_t ntiles;    // total over the batch
-  int32_t ncols;     // sum T + l
+  int32_t ncols;     // sum T + sum(power-filter lengths) + l
   int32_t ntaps;     // sum T
+  int32_t neta;      // sum of the power-filter lengths (0 for LDBP)
   size_t off_ckpt, off_g0, off_g1, off_part, total;
 };
 
@@ -364,7 +365,7 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
     for (int Lw = 4096; Lw >= 64; Lw -= 64) {
       bool ok = true;
       for (const auto& pt : L.blocks.passes)
-        if (bwd_lds_bytes(m.dtype, m.npol, Lw, pt) > budget) { ok = false; break; }
+        if (bwd_lds_bytes(m.dtype, m.npol, Lw, pt, m.filtered()) > budget) { ok = false; break; }
       if (ok) { best = Lw; break; }
     }
   }
@@ -374,8 +375,12 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
   L.tile_len = best;
   L.ntiles = m.nwave * ((m.n + best - 1) / best);
   L.ntaps = 0;
-  for (int i = 0; i < m.nstep; ++i) L.ntaps += m.ntap[i];
-  L.ncols = L.ntaps + m.nstep;
+  L.neta = 0;
+  for (int i = 0; i < m.nstep; ++i) {
+    L.ntaps += m.ntap[i];
+    if (m.nl_ntap) L.neta += m.nl_ntap[i];
+  }
+  L.ncols = L.ntaps + L.neta + m.nstep;
   const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
   const size_t nb = L.blocks.passes.size();
   size_t off = 0;
@@ -393,11 +398,10 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
 
 }  // namespace ldbp
 
-extern "C" int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
-                                            const int32_t* ntap, const void* ckpt, int32_t ckpt_every,
-                                            size_t* bytes) {
+namespace ldbp {
+
+static int backward_ws_impl(const ModelArgs& m, const void* ckpt, int32_t ckpt_every, size_t* bytes) {
   if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
-  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
   int st = check_model(m);
   if (st) return st;
   if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
@@ -410,11 +414,12 @@ extern "C" int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t
   return LDBP_OK;
 }
 
-extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
-                             const int32_t* ntap, const void* taps, const void* c, const void* x, const void* ckpt,
-                             int32_t ckpt_every, const void* gy, void* gx, void* gtaps, void* gc,
-                             const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream) {
-  ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+// The backward of LDBP (eta == NULL) and of the generalised ESSM (eta, geta: filters and their gradient).
+static int backward_impl(const ModelArgs& m, const void* taps, const void* c, const void* eta, const void* x,
+                         const void* ckpt, int32_t ckpt_every, const void* gy, void* gx, void* gtaps, void* gc,
+                         void* geta, const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  const int32_t dtype = m.dtype, npol = m.npol;
+  const int64_t nwave = m.nwave, n = m.n;
   int st = check_model(m);
   if (st) return st;
   if (plan && (plan->flags & ~LDBP_PLAN_SYMMETRIC))
@@ -422,11 +427,14 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
   const int sym = (plan && (plan->flags & LDBP_PLAN_SYMMETRIC)) ? 1 : 0;
   if (!taps || !c || !x || !gy || !gtaps || !gc)
     return fail(LDBP_EINVAL, "taps, c, x, gy, gtaps and gc must be non-NULL");
+  if (m.filtered() && (!eta || !geta)) return fail(LDBP_EINVAL, "eta and geta must be non-NULL");
   if (!aligned16(taps) || !aligned16(x) || !aligned16(gy) || !aligned16(gtaps) || (gx && !aligned16(gx)) ||
       (ckpt && !aligned16(ckpt)))
     return fail(LDBP_EINVAL, "complex arrays must be 16-byte aligned");
-  if (reinterpret_cast<uintptr_t>(c) % real_size(dtype) || reinterpret_cast<uintptr_t>(gc) % real_size(dtype))
-    return fail(LDBP_EINVAL, "c and gc must be aligned to their real type");
+  if (reinterpret_cast<uintptr_t>(c) % real_size(dtype) || reinterpret_cast<uintptr_t>(gc) % real_size(dtype) ||
+      (eta && reinterpret_cast<uintptr_t>(eta) % real_size(dtype)) ||
+      (geta && reinterpret_cast<uintptr_t>(geta) % real_size(dtype)))
+    return fail(LDBP_EINVAL, "c, gc, eta and geta must be aligned to their real type");
   if (ckpt_every < 0 || ckpt_every > LDBP_MAX_STEPS_PER_PASS)
     return fail(LDBP_EINVAL, "ckpt_every %d outside [0, %d]", ckpt_every, LDBP_MAX_STEPS_PER_PASS);
   if (ckpt && ckpt_every == 0) return fail(LDBP_EINVAL, "ckpt given without ckpt_every");
@@ -444,6 +452,7 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
     return fail(LDBP_EINVAL, "workspace overlaps an argument");
 
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* e = m.filtered() ? eta : nullptr;
   char* wsb = static_cast<char*>(ws);
   void* g0 = wsb + L.off_g0;
   void* g1 = wsb + L.off_g1;
@@ -458,7 +467,7 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
     PassPlan bp;
     st = make_block_plan(m, L.S, nrun, &fp, bp);
     if (st) return st;
-    st = run_block_plan(m, bp, taps, c, x, wsb + L.off_ckpt + (nb - 2) * wave_bytes, wsb + L.off_ckpt, L.S, s);
+    st = run_block_plan(m, bp, taps, c, x, wsb + L.off_ckpt + (nb - 2) * wave_bytes, wsb + L.off_ckpt, L.S, s, e);
     if (st) return st;
   }
   const void* gcur = gy;
@@ -466,11 +475,44 @@ extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t
     const void* xb = bi == 0 ? x : static_cast<const void*>(ck + (bi - 1) * wave_bytes);
     void* gin = (bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0);
     st = launch_bwd_block(dtype, npol, xb, gcur, gin, nwave, static_cast<int32_t>(n), L.tile_len,
-                          L.blocks.passes[bi], taps, c, part, L.ncols, L.ntaps, sym, s);
+                          L.blocks.passes[bi], taps, c, part, L.ncols, L.ntaps + L.neta, sym, s, e, L.ntaps);
     if (st) return st;
     gcur = gin;
   }
-  return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s);
+  return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s, L.neta, geta);
+}
+
+}  // namespace ldbp
+
+extern "C" int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                            const int32_t* ntap, const void* ckpt, int32_t ckpt_every,
+                                            size_t* bytes) {
+  return backward_ws_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap}, ckpt, ckpt_every, bytes);
+}
+
+extern "C" int ldbp_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                             const int32_t* ntap, const void* taps, const void* c, const void* x, const void* ckpt,
+                             int32_t ckpt_every, const void* gy, void* gx, void* gtaps, void* gc,
+                             const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  return backward_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap}, taps, c, nullptr, x, ckpt, ckpt_every, gy, gx,
+                       gtaps, gc, nullptr, plan, ws, ws_bytes, stream);
+}
+
+extern "C" int essm_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                            const int32_t* ntap, const int32_t* nl_ntap, const void* ckpt,
+                                            int32_t ckpt_every, size_t* bytes) {
+  if (!nl_ntap) return fail(LDBP_EINVAL, "nl_ntap is NULL");
+  return backward_ws_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap, nl_ntap}, ckpt, ckpt_every, bytes);
+}
+
+extern "C" int essm_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                             const int32_t* ntap, const int32_t* nl_ntap, const void* taps, const void* c,
+                             const void* eta, const void* x, const void* ckpt, int32_t ckpt_every, const void* gy,
+                             void* gx, void* gtaps, void* gc, void* geta, const ldbp_plan* plan, void* ws,
+                             size_t ws_bytes, void* stream) {
+  if (!nl_ntap) return fail(LDBP_EINVAL, "nl_ntap is NULL");
+  return backward_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap, nl_ntap}, taps, c, eta, x, ckpt, ckpt_every, gy,
+                       gx, gtaps, gc, geta, plan, ws, ws_bytes, stream);
 }
 
 extern "C" int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,

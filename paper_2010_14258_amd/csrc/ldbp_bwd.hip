@@ -380,15 +380,35 @@ __device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga
                                                           col0);
 }
 
-// LDS footprint (in complex elements) of one tile of length Lw for a block with halo H and
-// cumulative halves h_1..h_S; mirrored exactly by bwd_lds_bytes() on the host.
-__host__ __device__ inline int bwd_y_width(int Lw, int H, int hs) { return Lw + 4 * H - 2 * hs; }
+// Buffer margin of Y_s (block output of step s within the tile's recompute): the forward starts from
+// a margin of 2H and each step shrinks the valid margin by K_s + kappa_s; a filtered step keeps its
+// FIR output (margin V_{s-1} - K_s) in place and rotates only the inner part, so the buffer margin of
+// Y_s is 2H - h_s + kappa_s with h_s = sum_{i<=s} (K_i + kappa_i).  Mirrored by bwd_lds_bytes().
+__host__ __device__ inline int bwd_y_width(int Lw, int H, int hs, int kap = 0) { return Lw + 4 * H - 2 * hs + 2 * kap; }
 
-template <typename R, int NPOL, int RB, int RB2, int THREADS>
+// Sum over the tile's own positions of q_i P_{i-k} for every k in [-kap, kap] (the power-filter tap
+// correlation of a filtered step), one wave reduction per tap into red columns col0 + kap + k.
+template <typename R>
+__device__ __forceinline__ void eta_grad(const R* __restrict__ Q, const R* __restrict__ PP, int own_lo, int Lw,
+                                         int kap, double2* __restrict__ red, int ldr, int col0, int threads) {
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  for (int k = -kap; k <= kap; ++k) {
+    R acc = 0;
+    for (int i = own_lo + static_cast<int>(threadIdx.x); i < own_lo + Lw; i += threads) acc = fma(Q[i], PP[i - k], acc);
+    acc = wave_sum_last(acc);
+    if (lane == kLastLane) red[wv * ldr + col0 + kap + k] = double2{static_cast<double>(acc), 0.0};
+  }
+}
+
+// FILT: the block's nonlinear steps filter the power (generalised ESSM, eta != NULL); a separate
+// instantiation keeps the plain LDBP kernel unchanged.
+template <typename R, int NPOL, int RB, int RB2, int THREADS, bool FILT>
 __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const cx_t<R>* __restrict__ xb, const cx_t<R>* __restrict__ gout, cx_t<R>* __restrict__ gin, int32_t n,
     int32_t tile_len, int32_t ntiles, const cx_t<R>* __restrict__ taps, const R* __restrict__ c, PassTable pt,
-    int32_t pad, double2* __restrict__ part, int32_t ncols, int32_t ccol_base, int32_t sym) {
+    int32_t pad, double2* __restrict__ part, int32_t ncols, int32_t ccol_base, int32_t sym,
+    const R* __restrict__ eta, int32_t ecol_base) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = THREADS / 64;
@@ -400,21 +420,28 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
   const int H = pt.halo;
   const int S = pt.nstep;
   const int ntap_blk = pt.tapoff[S - 1] + 2 * pt.K[S - 1] + 1 - pt.tapoff[0];
-  const int ldr = ntap_blk + S;
+  const int neta_blk = FILT ? pt.etaoff[S - 1] + 2 * pt.kap[S - 1] + 1 - pt.etaoff[0] : 0;
+  const int ldr = ntap_blk + neta_blk + S;
+  auto kapp = [&](int s) { return FILT ? pt.kap[s - 1] : 0; };  // kappa of step s (1-based)
 
-  // LDS carve-up: red (FP64 partials) | Y_0 .. Y_S | GA | GB; Y_s has width bwd_y_width(Lw, H, h_s) + pad.
+  // LDS carve-up: red (FP64 partials) | Y_0 .. Y_S | GA | GB [| Q | PP]; Y_s has width
+  // bwd_y_width(Lw, H, h_s, kappa_s) + pad.
   double2* red = reinterpret_cast<double2*>(smem);
   V* Y0 = reinterpret_cast<V*>(smem + static_cast<size_t>(NW) * ldr * sizeof(double2));
   size_t ytot = 0;
   {
     int h = 0;
     for (int s = 0; s <= S; ++s) {
-      if (s > 0) h += pt.K[s - 1];
-      ytot += static_cast<size_t>(bwd_y_width(Lw, H, h) + pad) * NPOL;
+      const int kp = s > 0 ? kapp(s) : 0;
+      if (s > 0) h += pt.K[s - 1] + kp;
+      ytot += static_cast<size_t>(bwd_y_width(Lw, H, h, kp) + pad) * NPOL;
     }
   }
   V* GA = Y0 + ytot;
   V* GB = GA + static_cast<size_t>(Lw + 2 * H + pad) * NPOL;
+  // filtered steps only: Q over the G range, PP over the recompute range (a Y buffer plus a window)
+  R* Q = reinterpret_cast<R*>(GB + static_cast<size_t>(Lw + 2 * H + pad) * NPOL);
+  R* PP = Q + (Lw + 2 * H + pad);
   int hs;
 
   const V* xw = xb + wave * static_cast<int64_t>(n) * NPOL;
@@ -425,14 +452,27 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
   __syncthreads();
   hs = 0;
   V* ycur = Y0;
+  int kprev = 0;  // kappa of the step that produced ycur (its buffer extends kprev beyond the valid part)
   for (int s = 1; s <= S; ++s) {
     const int K = pt.K[s - 1];
-    V* ynext = ycur + static_cast<size_t>(bwd_y_width(Lw, H, hs) + pad) * NPOL;
-    hs += K;
+    const int kp = kapp(s);
+    V* ynext = ycur + static_cast<size_t>(bwd_y_width(Lw, H, hs, kprev) + pad) * NPOL;
     const R coef = c[pt.c0 + s - 1] * phase_coef_scale<R>();
-    fir_kerr_dispatch<R, NPOL, RB, THREADS>(ycur + K * NPOL, ynext, 0, bwd_y_width(Lw, H, hs), K,
-                                            taps + pt.tapoff[s - 1], coef, sym != 0);
+    if constexpr (FILT) {
+      // FIR output over the buffer of Y_s (valid margin of Y_{s-1} minus K), power into PP, then the
+      // filtered phase on the inner part
+      const int wout = bwd_y_width(Lw, H, hs + K, 0);
+      fir_lin_dispatch<R, NPOL, RB, THREADS>(ycur + (kprev + K) * NPOL, ynext, PP, 0, wout, K,
+                                             taps + pt.tapoff[s - 1], sym != 0);
+      __syncthreads();
+      nl_filter_dispatch<R, NPOL, RB, THREADS>(ynext, PP, kp, wout - kp, kp, eta + pt.etaoff[s - 1], coef);
+    } else {
+      fir_kerr_dispatch<R, NPOL, RB, THREADS>(ycur + K * NPOL, ynext, 0, bwd_y_width(Lw, H, hs + K), K,
+                                              taps + pt.tapoff[s - 1], coef, sym != 0);
+    }
     __syncthreads();
+    hs += K + kp;
+    kprev = kp;
     ycur = ynext;
   }
   // 2. block-output gradient
@@ -445,40 +485,84 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
   hs = H;
   for (int s = S; s >= 1; --s) {
     const int K = pt.K[s - 1];
+    const int kp = kapp(s);
+    const int kpp = s > 1 ? kapp(s - 1) : 0;
     const R cr = c[pt.c0 + s - 1];
     const R coef = cr * phase_coef_scale<R>();
-    // Kerr adjoint over GA indices [H - h_s, H + Lw + h_s); Y_s index = i - H + (2H - h_s)
-    const int lo = H - hs, hi = H + Lw + hs, yoff = H - hs;
-    V* yprev = ycur - static_cast<size_t>(bwd_y_width(Lw, H, hs - K) + pad) * NPOL;
+    // G_y,s is held over GA indices [H - h_s, H + Lw + h_s); Y_s index = i + yoff with the buffer
+    // margin 2H - h_s + kappa_s, so yoff = H - h_s + kappa_s
+    const int lo = H - hs, hi = H + Lw + hs, yoff = H - hs + kp;
+    const int hprev = hs - K - kp;
+    V* yprev = ycur - static_cast<size_t>(bwd_y_width(Lw, H, hprev, kpp) + pad) * NPOL;
     R accc = 0;
-    for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += THREADS) {
-      V yv[NPOL], gv[NPOL];
-      R pw = 0, q = 0;
+    if constexpr (FILT) {
+      // q = dL/dphi and P = |y|^2 over the whole G_y range, then the adjoint of the filtered phase over
+      // the range shrunk by kappa: G_u = G_y e^{-j phi} + 2 r u, r_i = c sum_k eta_k q_{i+k}
+      for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += THREADS) {
+        R pw = 0, q = 0;
 #pragma unroll
-      for (int pp = 0; pp < NPOL; ++pp) {
-        yv[pp] = ycur[(i + yoff) * NPOL + pp];
-        gv[pp] = GA[i * NPOL + pp];
-        pw += yv[pp].x * yv[pp].x + yv[pp].y * yv[pp].y;
-        q += gv[pp].y * yv[pp].x - gv[pp].x * yv[pp].y;
+        for (int pp = 0; pp < NPOL; ++pp) {
+          const V yv = ycur[(i + yoff) * NPOL + pp];
+          const V gv = GA[i * NPOL + pp];
+          pw += yv.x * yv.x + yv.y * yv.y;
+          q += gv.y * yv.x - gv.x * yv.y;
+        }
+        Q[i] = q;
+        PP[i] = pw;
       }
-      R sn, co;
-      phase_sincos(coef, pw, sn, co);
-      const R tq = 2 * cr * q;
+      __syncthreads();
+      const R* e = eta + pt.etaoff[s - 1];
+      for (int i = lo + kp + static_cast<int>(threadIdx.x); i < hi - kp; i += THREADS) {
+        R F = 0, r = 0;
+        for (int k = -kp; k <= kp; ++k) {
+          F = fma(e[kp + k], PP[i - k], F);
+          r = fma(e[kp + k], Q[i + k], r);
+        }
+        R sn, co;
+        phase_sincos(coef, F, sn, co);
+        const R tr = 2 * cr * r;
 #pragma unroll
-      for (int pp = 0; pp < NPOL; ++pp) {
-        const R tx = gv[pp].x + tq * yv[pp].x;
-        const R ty = gv[pp].y + tq * yv[pp].y;
-        GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
+        for (int pp = 0; pp < NPOL; ++pp) {
+          const V yv = ycur[(i + yoff) * NPOL + pp];
+          const V gv = GA[i * NPOL + pp];
+          // G_y e^{-j phi} + 2 r u with u = y e^{-j phi}: (G_y + 2 r y) e^{-j phi}
+          const R tx = gv.x + tr * yv.x;
+          const R ty = gv.y + tr * yv.y;
+          GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
+        }
+        if (i >= H && i < H + Lw) accc += Q[i] * F;
       }
-      if (i >= H && i < H + Lw) accc += q * pw;
+      eta_grad<R>(Q, PP, H, Lw, kp, red, ldr, ntap_blk + pt.etaoff[s - 1] - pt.etaoff[0], THREADS);
+    } else {
+      for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += THREADS) {
+        V yv[NPOL], gv[NPOL];
+        R pw = 0, q = 0;
+#pragma unroll
+        for (int pp = 0; pp < NPOL; ++pp) {
+          yv[pp] = ycur[(i + yoff) * NPOL + pp];
+          gv[pp] = GA[i * NPOL + pp];
+          pw += yv[pp].x * yv[pp].x + yv[pp].y * yv[pp].y;
+          q += gv[pp].y * yv[pp].x - gv[pp].x * yv[pp].y;
+        }
+        R sn, co;
+        phase_sincos(coef, pw, sn, co);
+        const R tq = 2 * cr * q;
+#pragma unroll
+        for (int pp = 0; pp < NPOL; ++pp) {
+          const R tx = gv[pp].x + tq * yv[pp].x;
+          const R ty = gv[pp].y + tq * yv[pp].y;
+          GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
+        }
+        if (i >= H && i < H + Lw) accc += q * pw;
+      }
     }
     accc = wave_sum_last(accc);
-    if (lane == kLastLane) red[wv * ldr + ntap_blk + (s - 1)] = double2{static_cast<double>(accc), 0.0};
+    if (lane == kLastLane) red[wv * ldr + ntap_blk + neta_blk + (s - 1)] = double2{static_cast<double>(accc), 0.0};
     __syncthreads();
-    // FIR adjoint into GA over [H - h_{s-1}, H + Lw + h_{s-1}); tap gradient over the owned range
-    const int hprev = hs - K;
+    // FIR adjoint into GA over [H - h_{s-1}, H + Lw + h_{s-1}); tap gradient over the owned range.  Y_{s-1}
+    // index = GA index + (H - h_{s-1} + kappa_{s-1})
     adj_step_dispatch<R, NPOL, RB, RB2, THREADS>(GB, GA, H - hprev, H + Lw + hprev, K, taps + pt.tapoff[s - 1], H,
-                                                 Lw, yprev, H - hprev, red, ldr,
+                                                 Lw, yprev, H - hprev + kpp, red, ldr,
                                                  pt.tapoff[s - 1] - pt.tapoff[0], sym != 0);
     __syncthreads();
     hs = hprev;
@@ -499,7 +583,19 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
       sx += red[w * ldr + col].x;
       sy += red[w * ldr + col].y;
     }
-    const int g = col < ntap_blk ? pt.tapoff[0] + col : ccol_base + pt.c0 + (col - ntap_blk);
+    int g;
+    if (col < ntap_blk) {
+      g = pt.tapoff[0] + col;
+    } else if (col < ntap_blk + neta_blk) {
+      // eta_k gradient: the sums above times c of the step
+      const int ec = col - ntap_blk;
+      int st = 0;
+      while (st + 1 < S && pt.etaoff[st + 1] - pt.etaoff[0] <= ec) ++st;
+      sx *= static_cast<double>(c[pt.c0 + st]);
+      g = ecol_base + pt.etaoff[0] + ec;
+    } else {
+      g = ccol_base + pt.c0 + (col - ntap_blk - neta_blk);
+    }
     prow[g] = double2{sx, sy};
   }
 }
@@ -508,7 +604,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
 template <typename R>
 __global__ __launch_bounds__(256) void ldbp_grad_reduce(const double2* __restrict__ part, int64_t ntiles,
                                                         int32_t ncols, int32_t ntaps, cx_t<R>* __restrict__ gtaps,
-                                                        R* __restrict__ gc) {
+                                                        R* __restrict__ gc, int32_t neta, R* __restrict__ geta) {
   __shared__ double sx[256], sy[256];
   const int col = blockIdx.x;
   double ax = 0, ay = 0;
@@ -529,7 +625,8 @@ __global__ __launch_bounds__(256) void ldbp_grad_reduce(const double2* __restric
   }
   if (threadIdx.x == 0) {
     if (col < ntaps) gtaps[col] = cx_t<R>{static_cast<R>(sx[0]), static_cast<R>(sy[0])};
-    else gc[col - ntaps] = static_cast<R>(sx[0]);
+    else if (col < ntaps + neta) geta[col - ntaps] = static_cast<R>(sx[0]);
+    else gc[col - ntaps - neta] = static_cast<R>(sx[0]);
   }
 }
 
@@ -547,30 +644,37 @@ static int bwd_pad(int dtype, int npol) {
   return dtype == LDBP_C64 ? 8 : 4;
 }
 
-size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt) {
+size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt, bool filtered) {
   const int pad = bwd_pad(dtype, npol);
   const int S = pt.nstep;
   const int ntap_blk = pt.tapoff[S - 1] + 2 * pt.K[S - 1] + 1 - pt.tapoff[0];
+  const int neta_blk = filtered ? pt.etaoff[S - 1] + 2 * pt.kap[S - 1] + 1 - pt.etaoff[0] : 0;
   size_t elems = 0;
   int hs = 0;
   for (int s = 0; s <= S; ++s) {
-    if (s > 0) hs += pt.K[s - 1];
-    elems += static_cast<size_t>(Lw + 4 * pt.halo - 2 * hs + pad);
+    const int kp = (s > 0 && filtered) ? pt.kap[s - 1] : 0;
+    if (s > 0) hs += pt.K[s - 1] + kp;
+    elems += static_cast<size_t>(bwd_y_width(Lw, pt.halo, hs, kp) + pad);
   }
   elems += 2 * static_cast<size_t>(Lw + 2 * pt.halo + pad);
-  return static_cast<size_t>(4) * (ntap_blk + S) * sizeof(double2) + elems * npol * cx_size(dtype);
+  size_t reals = 0;
+  if (filtered) reals = static_cast<size_t>(Lw + 2 * pt.halo + pad) + static_cast<size_t>(Lw + 4 * pt.halo + pad + 8);
+  return static_cast<size_t>(4) * (ntap_blk + neta_blk + S) * sizeof(double2) + elems * npol * cx_size(dtype) +
+         reals * real_size(dtype);
 }
 
 template <typename R, int NPOL>
 static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                               int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
-                              int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream) {
+                              int32_t ncols, int32_t ccol_base, int sym, const void* eta, int32_t ecol_base,
+                              hipStream_t stream) {
   using Cfg = BwdCfg<R, NPOL>;
   const int64_t ntiles = (n + tile_len - 1) / tile_len;
   const int64_t nblocks = ntiles * nwave;
   if (nblocks > 0x7fffffffLL) return fail(LDBP_EUNSUPPORTED, "grid too large");
-  const size_t lds = bwd_lds_bytes(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL, tile_len, pt);
-  auto kern = ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS>;
+  const size_t lds = bwd_lds_bytes(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL, tile_len, pt, eta != nullptr);
+  auto kern = eta ? ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS, true>
+                  : ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS, false>;
   if (lds > 65536)
     LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
@@ -578,35 +682,32 @@ static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64
                      static_cast<const cx_t<R>*>(xb), static_cast<const cx_t<R>*>(gout), static_cast<cx_t<R>*>(gin),
                      n, tile_len, static_cast<int32_t>(ntiles), static_cast<const cx_t<R>*>(taps),
                      static_cast<const R*>(c), pt, bwd_pad(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL),
-                     static_cast<double2*>(part), ncols, ccol_base, sym);
+                     static_cast<double2*>(part), ncols, ccol_base, sym, static_cast<const R*>(eta), ecol_base);
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }
 
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
-                     int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream) {
+                     int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream, const void* eta,
+                     int32_t ecol_base) {
+#define LDBP_BWD_ARGS xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols, ccol_base, sym, eta, ecol_base, stream
   if (dtype == LDBP_C64)
-    return npol == 1 ? launch_bwd_block_t<float, 1>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                    ccol_base, sym, stream)
-                     : launch_bwd_block_t<float, 2>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                    ccol_base, sym, stream);
-  return npol == 1 ? launch_bwd_block_t<double, 1>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                   ccol_base, sym, stream)
-                   : launch_bwd_block_t<double, 2>(xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols,
-                                                   ccol_base, sym, stream);
+    return npol == 1 ? launch_bwd_block_t<float, 1>(LDBP_BWD_ARGS) : launch_bwd_block_t<float, 2>(LDBP_BWD_ARGS);
+  return npol == 1 ? launch_bwd_block_t<double, 1>(LDBP_BWD_ARGS) : launch_bwd_block_t<double, 2>(LDBP_BWD_ARGS);
+#undef LDBP_BWD_ARGS
 }
 
 int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,
-                       void* gc, hipStream_t stream) {
+                       void* gc, hipStream_t stream, int32_t neta, void* geta) {
   if (dtype == LDBP_C64)
     hipLaunchKernelGGL(ldbp_grad_reduce<float>, dim3(ncols), dim3(256), 0, stream,
                        static_cast<const double2*>(part), ntiles, ncols, ntaps, static_cast<float2*>(gtaps),
-                       static_cast<float*>(gc));
+                       static_cast<float*>(gc), neta, static_cast<float*>(geta));
   else
     hipLaunchKernelGGL(ldbp_grad_reduce<double>, dim3(ncols), dim3(256), 0, stream,
                        static_cast<const double2*>(part), ntiles, ncols, ntaps, static_cast<double2*>(gtaps),
-                       static_cast<double*>(gc));
+                       static_cast<double*>(gc), neta, static_cast<double*>(geta));
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }

@@ -47,11 +47,14 @@ int launch_fwd_pass_c128(int npol, int rb, const void* x, void* y, int64_t nwave
                          hipStream_t stream, const void* eta);
 
 // Backward (adjoint) block kernel and the deterministic gradient reduction.
-size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt);
+// Partial-sum columns: [taps (ntaps)] [power filters (neta), ecol_base = ntaps] [c (l), ccol_base].
+// eta: packed power filters of filtered steps (generalised ESSM), or NULL.
+size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt, bool filtered = false);
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
-                     int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream);
+                     int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream, const void* eta = nullptr,
+                     int32_t ecol_base = 0);
 int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,
-                       void* gc, hipStream_t stream);
+                       void* gc, hipStream_t stream, int32_t neta = 0, void* geta = nullptr);
 
 }  // namespace ldbp

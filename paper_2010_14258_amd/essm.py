@@ -74,3 +74,44 @@ def essm_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, eta: torc
                              ctypes.byref(pl) if pl is not None else None, _ptr(ws),
                              ws.numel() if ws is not None else 0, stream_handle(stream, x.device)))
     return y
+
+
+def essm_backward_workspace_size(x: torch.Tensor, ntap: Sequence[int], nl_ntap: Sequence[int], npol: int = 1,
+                                 ckpt=None, ckpt_every: int = 0) -> int:
+    lib = N.load()
+    nwave, n = _shape(x, npol)
+    out = ctypes.c_size_t(0)
+    N.check(lib.essm_backward_workspace_size(_code(x), npol, nwave, n, len(ntap), N.i32_array(ntap),
+                                             N.i32_array(nl_ntap), _ptr(ckpt), int(ckpt_every), ctypes.byref(out)))
+    return int(out.value)
+
+
+def essm_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, eta: torch.Tensor, ntap: Sequence[int],
+                  nl_ntap: Sequence[int], gy: torch.Tensor, npol: int = 1, ckpt: Optional[torch.Tensor] = None,
+                  ckpt_every: int = 0, need_gx: bool = True, symmetric: bool = False,
+                  ws: Optional[torch.Tensor] = None, stream=None):
+    """Adjoint of ``essm_forward``: returns (gx or None, gtaps, gc, geta) for dL/dy = gy.
+
+    symmetric: the FIR taps satisfy h_{-k} = h_k (folded evaluation; gtaps projected on symmetric filters)."""
+    lib = N.load()
+    code = _code(x)
+    nwave, n = _shape(x, npol)
+    for name, t in (("x", x), ("gy", gy)):
+        _check_dev(name, t, x.dtype)
+    _check_dev("taps", taps, x.dtype)
+    _check_dev("c", c, _real_dtype(code))
+    _check_dev("eta", eta, _real_dtype(code))
+    _check_model(ntap, nl_ntap, taps, c, eta)
+    if ckpt is not None:
+        _check_dev("ckpt", ckpt, x.dtype)
+    gx = torch.empty_like(x) if need_gx else None
+    gtaps, gc, geta = torch.empty_like(taps), torch.empty_like(c), torch.empty_like(eta)
+    if ws is None:
+        ws = torch.empty(essm_backward_workspace_size(x, ntap, nl_ntap, npol, ckpt, ckpt_every), dtype=torch.uint8,
+                         device=x.device)
+    pl = N.LdbpPlan(0, 0, 0, N.LDBP_PLAN_SYMMETRIC if symmetric else 0)
+    N.check(lib.essm_backward(code, npol, nwave, n, len(ntap), N.i32_array(ntap), N.i32_array(nl_ntap), _ptr(taps),
+                              _ptr(c), _ptr(eta), _ptr(x), _ptr(ckpt), int(ckpt_every), _ptr(gy), _ptr(gx),
+                              _ptr(gtaps), _ptr(gc), _ptr(geta), ctypes.byref(pl), _ptr(ws), ws.numel(),
+                              stream_handle(stream, x.device)))
+    return gx, gtaps, gc, geta

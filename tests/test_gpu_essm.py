@@ -117,3 +117,97 @@ def test_essm_tiny_waveforms_wrap(npol):
         ref = OE.essm_forward(x, taps, c, eta, npol=npol)
         y = _run(x, taps, c, eta, npol=npol, dtype=torch.complex128)
         assert _rel(y, ref) <= 1e-12, n
+
+
+def _gpu_grad(x, taps, c, eta, gy, npol=1, dtype=torch.complex128, ckpt_every=0, use_ckpt=False, symmetric=False):
+    tp, ntap = W.pack_taps(taps)
+    nl = [len(e) for e in eta]
+    rd = torch.float32 if dtype == torch.complex64 else torch.float64
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(DEV, dtype)
+    tt = torch.from_numpy(tp).to(DEV, dtype)
+    ct = torch.from_numpy(np.asarray(c, np.float64)).to(DEV, rd)
+    et = torch.from_numpy(np.concatenate(eta)).to(DEV, rd)
+    gt = torch.from_numpy(np.ascontiguousarray(gy)).to(DEV, dtype)
+    ck = None
+    if use_ckpt:
+        ns = G.num_checkpoints(len(ntap), ckpt_every)
+        if ns > 0:
+            ck = torch.empty((ns,) + tuple(xt.shape), dtype=dtype, device=DEV)
+            GE.essm_forward(xt, tt, ct, et, ntap, nl, npol=npol, ckpt=ck, ckpt_every=ckpt_every,
+                            plan=(0, 0, 0, 1) if symmetric else None)
+    gx, gtp, gc, ge = GE.essm_backward(xt, tt, ct, et, ntap, nl, gt, npol=npol, ckpt=ck, ckpt_every=ckpt_every,
+                                       symmetric=symmetric)
+    torch.cuda.synchronize()
+    off = np.cumsum([0] + ntap)
+    eoff = np.cumsum([0] + nl)
+    gtp = gtp.cpu().numpy().astype(np.complex128)
+    ge = ge.cpu().numpy().astype(np.float64)
+    return (gx.cpu().numpy().astype(np.complex128), [gtp[off[i]:off[i + 1]] for i in range(len(ntap))],
+            gc.cpu().numpy().astype(np.float64), [ge[eoff[i]:eoff[i + 1]] for i in range(len(nl))])
+
+
+def _sym(gt):
+    out = []
+    for g in gt:
+        f = O.fold_symmetric_grad(g)
+        K = len(f) - 1
+        h = np.empty_like(g)
+        h[K] = f[0]
+        for k in range(1, K + 1):
+            h[K + k] = h[K - k] = 0.5 * f[k]
+        out.append(h)
+    return out
+
+
+def _cmp(got, ref, tol):
+    for name, a, b in zip(("gx", "gtaps", "gc", "geta"), got, ref):
+        if isinstance(a, list):
+            a, b = np.concatenate(a), np.concatenate(b)
+        assert _rel(a, b) <= tol, (name, _rel(a, b))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 1e-4), (torch.complex128, 1e-10)])
+@pytest.mark.parametrize("npol,S,use_ckpt", [(1, 1, True), (1, 3, True), (1, 3, False), (2, 2, True), (1, 0, False)])
+def test_essm_backward_vs_oracle(dtype, tol, npol, S, use_ckpt):
+    """dL/dx, dL/dtaps, dL/dc and dL/deta of the filtered model (kappa 0, 1, 2, 20 unrolled; 7, 25 direct)."""
+    print("case: essm bwd", dtype, npol, S, use_ckpt, flush=True)
+    Ts = [15, 3, 5, 9, 1, 7]
+    kappas = [2, 0, 20, 7, 1, 25]
+    taps, c, eta = _model(80, Ts, kappas)
+    shape = (3, 3001) if npol == 1 else (2, 2501, 2)
+    x = synth.complex_normal(81, shape) * 0.5
+    gy = synth.complex_normal(82, shape)
+    ref = OE.essm_grad(x, taps, c, eta, gy, npol=npol)
+    _cmp(_gpu_grad(x, taps, c, eta, gy, npol=npol, dtype=dtype, ckpt_every=S, use_ckpt=use_ckpt), ref, tol)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 1e-4), (torch.complex128, 1e-10)])
+def test_essm_backward_symmetric_and_tiny(dtype, tol):
+    """Folded symmetric FIR taps (projected tap gradient), and waveforms shorter than the halo."""
+    print("case: essm bwd sym tiny", dtype, flush=True)
+    Ts = [9, 5, 7, 3]
+    taps, c, eta = _model(90, Ts, [3, 20, 1, 4], symmetric=True)
+    x = synth.complex_normal(91, (2, 4001)) * 0.5
+    gy = synth.complex_normal(92, (2, 4001))
+    rx, rt, rc, re = OE.essm_grad(x, taps, c, eta, gy)
+    _cmp(_gpu_grad(x, taps, c, eta, gy, dtype=dtype, ckpt_every=2, use_ckpt=True, symmetric=True),
+         (rx, _sym(rt), rc, re), tol)
+    for n in (1, 3, 17, 40):
+        x = synth.complex_normal(93 + n, (2, n))
+        gy = synth.complex_normal(94 + n, (2, n))
+        ref = OE.essm_grad(x, taps, c, eta, gy)
+        _cmp(_gpu_grad(x, taps, c, eta, gy, dtype=torch.complex128, ckpt_every=2, use_ckpt=True), ref, 1e-10)
+
+
+def test_essm_unit_filters_backward_equals_ldbp():
+    """eta = (1): the filtered backward gives the LDBP backward's gradients (and dL/deta_0 = c dL/dc)."""
+    print("case: essm bwd unit", flush=True)
+    Ts = [15, 7, 3, 11]
+    taps, c, _ = _model(95, Ts, [0] * 4)
+    eta = [np.ones(1)] * 4
+    x = synth.complex_normal(96, (2, 3000)) * 0.6
+    gy = synth.complex_normal(97, (2, 3000))
+    gx, gt, gc, ge = _gpu_grad(x, taps, c, eta, gy, ckpt_every=2, use_ckpt=True)
+    rx, rt, rc = O.ldbp_grad(x, taps, c, gy)
+    _cmp((gx, gt, gc), (rx, rt, rc), 1e-10)
+    np.testing.assert_allclose([g[0] for g in ge], np.asarray(c) * rc, rtol=1e-9, atol=1e-12)
