@@ -14,8 +14,9 @@ distribution, forward + backward (block checkpoints every 2 steps), FFT-DBP on t
 at the smallest steps/span whose effective SNR is within 0.1 dB of LDBP's, one training iteration of
 the 32 x 16,384 training configuration, the same forward on 1,024 waveforms (512 MiB per buffer,
 beyond the 256 MB last-level cache), the dual-polarisation 8 x 2^20 x 2 configuration (32 x 80 km,
-l = 64, 5 shared taps), the 256-waveform uneven batch, the roofline position of the forward kernel
-and the FP64 oracle on the host (one core and all cores of the process's CPU set).
+l = 64, 5 shared taps), the 256-waveform uneven batch, the generalised ESSM (every nonlinear step
+filtering the power with 41 real taps) forward and forward + backward, the roofline position of the
+forward kernel and the FP64 oracle on the host (one core and all cores of the process's CPU set).
 """
 from __future__ import annotations
 
@@ -341,6 +342,123 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
             "train_iterations": iters, "models": out_models, "by_power": rows}
 
 
+def essm_timing(torch, dev, W, reps: int, kappa: int = 20):
+    """The generalised ESSM on the inference workload: the same l = 50 steps of 15 folded taps, every
+    nonlinear step filtering the power with 2 kappa + 1 real taps.  Forward (autotuned plan) and forward
+    with checkpoints every 2 steps + backward.  The filters are unit filters padded with zeros (the
+    time does not depend on the values), so the output must equal the LDBP forward's."""
+    from paper_2010_14258_amd import autotune as AT
+    from paper_2010_14258_amd import essm as E
+    from paper_2010_14258_amd import ldbp as L
+    from paper_2010_14258_amd import txrx as TX
+
+    r, taps, c, ntap = W["r"], W["taps"], W["c"], W["ntap"]
+    nwave, n = r.shape
+    ell, ne = len(ntap), 2 * kappa + 1
+    eta_np = np.zeros((ell, ne), dtype=np.float32)
+    eta_np[:, kappa] = 1.0
+    eta = torch.from_numpy(eta_np.reshape(-1)).to(dev)
+    nl = [ne] * ell
+    stream = torch.cuda.current_stream(dev)
+    plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=3, eta=eta, nl_ntap=nl)
+    y = torch.empty_like(r)
+    ws = torch.empty(max(E.essm_forward_workspace_size(r, ntap, nl, plan=plan), 1), dtype=torch.uint8, device=dev)
+    ms = event_time(torch, stream,
+                    lambda: E.essm_forward(r, taps, c, eta, ntap, nl, y=y, plan=plan, ws=ws, stream=stream), reps, 2)
+    npass, tile_len, spp = E.essm_forward_plan_query(0, 1, nwave, n, ntap, nl, plan=plan)
+    z = L.ldbp_forward(r, taps, c, ntap, plan=(0, 0, 0, 1))
+    unit_diff = float((y - z).abs().max().item())
+    ss = nwave * n * ell
+    flops = nwave * n * sum(fwd_flops_per_sample_step(t, True) + 4 * kappa + 1 for t in ntap)
+    S = 2
+    ck = torch.empty((L.num_checkpoints(ell, S),) + tuple(r.shape), dtype=r.dtype, device=dev)
+    _, _, gy = TX.rx_mse(z, W["s"], W["p"], RHO_D, RS, want_grad=True)
+    bws = torch.empty(E.essm_backward_workspace_size(r, ntap, nl, ckpt=ck, ckpt_every=S), dtype=torch.uint8,
+                      device=dev)
+
+    def fwd_bwd():
+        E.essm_forward(r, taps, c, eta, ntap, nl, y=y, ckpt=ck, ckpt_every=S, plan=(0, 0, 0, 1), stream=stream)
+        E.essm_backward(r, taps, c, eta, ntap, nl, gy, ckpt=ck, ckpt_every=S, need_gx=False, symmetric=True,
+                        ws=bws, stream=stream)
+
+    ms_fb = event_time(torch, stream, fwd_bwd, max(5, reps // 5), 2)
+    return {"workload": f"64 waveforms x 65,536 c64 samples, l = 50, 15 folded taps, filters of {ne} real taps",
+            "kappa": kappa, "plan": list(plan), "passes": npass, "tile_len": tile_len, "steps_per_pass": spp,
+            "fwd_ms": ms, "fwd_value": ss / (ms * 1e-3), "unit": "samples*steps/s",
+            "fwd_flops_per_sample_step": flops / (nwave * n * ell),
+            "fwd_achieved_tflops": flops / (ms * 1e-3) / 1e12,
+            "fwd_alu_frac": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+            "unit_filter_max_abs_diff_vs_ldbp": unit_diff,
+            "fwd_bwd_ms": ms_fb, "fwd_bwd_value": ss / (ms_fb * 1e-3), "ckpt_every": S}
+
+
+def essm_trained(torch, dev, iters: int, powers, kappa: int = 20, ntaps: int = 15, stps: int = 1):
+    """Conventional vs generalised ESSM (Sec. III-D, V-C) on the 10 x 100 km link with few steps: l = 10
+    (one step per span, log step sizes), least-squares FIR linear steps of `ntaps` taps, filters of
+    2 kappa + 1 real taps starting as unit filters.  Conventional: one filter shared by all nonlinear
+    steps, the only trained parameters.  Generalised: a filter per step, trained jointly with the
+    linear steps and the Kerr coefficients.  LDBP with the same steps and taps (no filters) trained the
+    same way, and the least-squares initialisation (= every model before training), for reference.
+    Training as the training recipe (32 x 16,384 waveforms per batch, launch powers {2, 3, 4} dBm,
+    Adam lr 1e-3), evaluated on the 64 x 65,536 inference batch at each launch power, with FFT-DBP."""
+    from paper_2010_14258_amd import essm as E
+    from paper_2010_14258_amd import ldbp as L
+    from paper_2010_14258_amd import ssm as SS
+    from paper_2010_14258_amd import train as TRN
+    from paper_2010_14258_amd import txrx as TX
+
+    variants = [("ldbp", dict()),
+                ("essm_conventional", dict(essm_kappa=kappa, essm_shared=True, train_taps=False, train_c=False)),
+                ("essm_generalised", dict(essm_kappa=kappa))]
+    models = []
+    init = None
+    for name, kw in variants:
+        trn = TRN.Trainer(TRN.TrainConfig(iters=iters, t_init=ntaps, t_final=ntaps, ldbp_steps=stps, **kw),
+                          device=dev)
+        if init is None:
+            init = (trn.taps.clone(), trn.c.clone(), list(trn.ntap))
+        t0 = time.perf_counter()
+        curve = []
+        for it in range(iters):
+            loss = trn.step()
+            if (it + 1) % 250 == 0:
+                curve.append([it + 1, loss])
+                print(f"train {name} {it + 1}/{iters} loss {loss:.4e} {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        m = {"name": name, "train_seconds": time.perf_counter() - t0, "loss_curve": curve,
+             "taps": trn.taps.contiguous(), "c": trn.c.contiguous(), "ntap": list(trn.ntap)}
+        if trn.essm:
+            m["eta"] = trn.eta_per_step().contiguous()
+            m["nl_ntap"] = list(trn.nl_ntap)
+            m["filters"] = trn.eta.view(-1, 2 * kappa + 1).cpu().numpy().round(5).tolist()
+        models.append(m)
+        del trn
+    rows = []
+    for p_dbm in powers:
+        W = build_workload(torch, dev, p_dbm=p_dbm)
+        r = W["r"]
+        row = {"launch_dbm": p_dbm,
+               "ls_init_snr_db": snr_db(TX, L.ldbp_forward(r, init[0], init[1], init[2], plan=(0, 0, 0, 1)), W["s"],
+                                        W["p"])}
+        for m in models:
+            if "eta" in m:
+                z = E.essm_forward(r, m["taps"], m["c"], m["eta"], m["ntap"], m["nl_ntap"], plan=(0, 0, 0, 1))
+            else:
+                z = L.ldbp_forward(r, m["taps"], m["c"], m["ntap"], plan=(0, 0, 0, 1))
+            row[m["name"] + "_snr_db"] = snr_db(TX, z, W["s"], W["p"])
+        row["fft_dbp_snr_db_by_steps_per_span"] = {k: snr_db(TX, SS.fft_dbp(r, W["dbp_link"](k)), W["s"], W["p"])
+                                                   for k in (1, 2, 5)}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        del W, r
+        torch.cuda.empty_cache()
+    out_models = [{k: v for k, v in m.items() if k not in ("taps", "c", "ntap", "eta", "nl_ntap")} for m in models]
+    return {"workload": f"10 x 100 km, l = {10 * stps} ({stps} step per span), {ntaps} taps, kappa = {kappa}; "
+                        "evaluated on 64 waveforms x 65,536 c64 samples",
+            "train_iterations": iters, "models": out_models, "by_power": rows}
+
+
 def snr_db(TX, z, s, p):
     mse, _, _ = TX.rx_mse(z, s, p, RHO_D, RS)
     return 10.0 * math.log10(1.0 / float(mse.mean().item()))
@@ -353,10 +471,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
-    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp", "snr"], default="full",
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp", "snr", "essm"], default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "dbp: FFT-DBP at one step per span only (for kernel traces of the split-step passes); "
-                         "snr: train LDBP, then the equal-SNR comparison with FFT-DBP over launch powers")
+                         "snr: train LDBP, then the equal-SNR comparison with FFT-DBP over launch powers; "
+                         "essm: train conventional and generalised ESSM (and LDBP) with one step per span")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--train-taps", default="25:3",
@@ -390,6 +509,10 @@ def main():
         variants = [tuple(int(t) for t in v.split(":")) for v in args.train_taps.split(",")]
         out = equal_snr_trained(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")], 20,
                                 variants)
+        print(json.dumps(out), flush=True)
+        return
+    if args.mode == "essm":
+        out = essm_trained(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")])
         print(json.dumps(out), flush=True)
         return
     if args.mode == "dbp":
@@ -542,6 +665,7 @@ def main():
         out["uneven_batch"] = uneven_batch(torch, dev, max(5, args.steps // 5))
         out["big_batch"] = big_batch(torch, dev, W, max(5, args.steps // 5))
         out["manakov"] = manakov(torch, dev, max(5, args.steps // 5))
+        out["essm"] = essm_timing(torch, dev, W, args.steps)
 
     if cpu is not None:
         out["cpu_baseline"] = cpu

@@ -1,4 +1,4 @@
-"""Plan autotuner for the time-blocked LDBP forward.
+"""Plan autotuner for the time-blocked LDBP (and filtered-step ESSM) forward.
 
 For a problem signature (device, dtype, npol, nwave, n, tap profile, symmetric) it times every
 plan in a candidate set -- outputs per thread x steps per pass x LDS chunks -- with HIP events on
@@ -17,6 +17,7 @@ from typing import Dict, Iterable, List, Optional, Sequence, Tuple
 import torch
 
 from . import _native as N
+from . import essm as E
 from . import ldbp as L
 
 _MEM: Dict[str, dict] = {}
@@ -25,12 +26,16 @@ RB_CHOICES = {(N.LDBP_C64, 1): (7, 8, 9), (N.LDBP_C64, 2): (3, 4, 5),
               (N.LDBP_C128, 1): (3, 4), (N.LDBP_C128, 2): (1, 2)}
 
 
-def signature(x: torch.Tensor, ntap: Sequence[int], npol: int, symmetric: bool) -> str:
+def signature(x: torch.Tensor, ntap: Sequence[int], npol: int, symmetric: bool,
+              nl_ntap: Optional[Sequence[int]] = None) -> str:
     code = L._code(x)
     nwave, n = L._shape(x, npol)
     name = torch.cuda.get_device_name(x.device)
     prof = ",".join(str(int(t)) for t in ntap)
-    return f"{name}|{code}|{npol}|{nwave}|{n}|{prof}|{int(bool(symmetric))}"
+    key = f"{name}|{code}|{npol}|{nwave}|{n}|{prof}|{int(bool(symmetric))}"
+    if nl_ntap is not None:
+        key += "|essm:" + ",".join(str(int(t)) for t in nl_ntap)
+    return key
 
 
 def _load(path: Optional[str]) -> dict:
@@ -90,10 +95,14 @@ def _time(fn, stream, reps: int) -> float:
 
 def tune_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], npol: int = 1,
                  symmetric: bool = False, reps: int = 5, cache_path: Optional[str] = None,
-                 plans: Optional[Iterable[Tuple[int, int, int, int]]] = None, stream=None):
-    """Returns (best plan tuple, best ms, list of (plan, ms)) for y = ldbp_forward(x, ...)."""
+                 plans: Optional[Iterable[Tuple[int, int, int, int]]] = None, stream=None,
+                 eta: Optional[torch.Tensor] = None, nl_ntap: Optional[Sequence[int]] = None):
+    """Returns (best plan tuple, best ms, list of (plan, ms)) for y = ldbp_forward(x, ...), or for
+    y = essm_forward(x, ..., eta, ...) when the filters of the nonlinear steps (eta, nl_ntap) are given."""
+    if (eta is None) != (nl_ntap is None):
+        raise ValueError("eta and nl_ntap go together")
     cache_path = cache_path or os.environ.get("LDBP_AUTOTUNE_CACHE")
-    key = signature(x, ntap, npol, symmetric)
+    key = signature(x, ntap, npol, symmetric, nl_ntap)
     if key in _MEM:
         e = _MEM[key]
         return tuple(e["plan"]), e["ms"], e.get("table", [])
@@ -108,13 +117,20 @@ def tune_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Seq
     ws_cache = {}
     for plan in (plans or candidates(code, npol, len(ntap), symmetric)):
         try:
-            need = L.ldbp_forward_workspace_size(x, ntap, npol, plan=plan)
+            if eta is None:
+                need = L.ldbp_forward_workspace_size(x, ntap, npol, plan=plan)
+            else:
+                need = E.essm_forward_workspace_size(x, ntap, nl_ntap, npol, plan=plan)
         except N.LdbpError:
             continue
         if need not in ws_cache:
             ws_cache[need] = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
         ws = ws_cache[need]
-        fn = lambda: L.ldbp_forward(x, taps, c, ntap, npol=npol, y=y, plan=plan, ws=ws, stream=stream)
+        if eta is None:
+            fn = lambda: L.ldbp_forward(x, taps, c, ntap, npol=npol, y=y, plan=plan, ws=ws, stream=stream)
+        else:
+            fn = lambda: E.essm_forward(x, taps, c, eta, ntap, nl_ntap, npol=npol, y=y, plan=plan, ws=ws,
+                                        stream=stream)
         try:
             ms = _time(fn, stream, reps)
         except N.LdbpError:

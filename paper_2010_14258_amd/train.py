@@ -12,6 +12,12 @@ the layers; event e of E fires at iteration floor(prune_frac * iters * (e/E)^2),
 early.  A pruned pair is removed from the packed filters (equivalent to a zero mask on it) so the
 kernels stop paying for it.
 
+With ``essm_kappa >= 0`` the model is the generalised enhanced SSM (Sec. III-D): every nonlinear
+step filters the power with a real filter of 2 kappa + 1 taps before the phase, the filters start as
+unit filters and train with the rest; ``essm_shared`` ties them to one filter applied in every step
+(the conventional ESSM, whose gradient is the sum of the per-step filter gradients), and
+``train_taps = False`` keeps the linear steps at their initialisation.
+
 Batches are a pure function of (seed, iteration): a run resumed from a checkpoint continues
 bit for bit like an uninterrupted one.
 """
@@ -25,6 +31,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 import torch
 
+from . import essm as E
 from . import init as I
 from . import ldbp as L
 from . import ssm as SS
@@ -60,6 +67,9 @@ class TrainConfig:
     seed: int = 301
     complex128: bool = False
     unit_init: bool = False
+    train_taps: bool = True
+    essm_kappa: int = -1              # >= 0: filtered nonlinear steps with 2 kappa + 1 real taps
+    essm_shared: bool = False         # one filter in every nonlinear step (conventional ESSM)
 
 
 def pruning_plan(t_init: Sequence[int], t_final: Sequence[int], iters: int, frac: float):
@@ -108,6 +118,15 @@ class Trainer:
         self.v_t = torch.zeros_like(self.m_t)
         self.m_c = torch.zeros_like(self.c)
         self.v_c = torch.zeros_like(self.c)
+        self.essm = cfg.essm_kappa >= 0
+        if self.essm:
+            ne = 2 * cfg.essm_kappa + 1
+            self.nl_ntap = [ne] * len(self.ntap)
+            unit = torch.zeros(ne, dtype=self.rdt, device=self.dev)
+            unit[cfg.essm_kappa] = 1.0
+            self.eta = unit if cfg.essm_shared else unit.repeat(len(self.ntap))
+            self.m_e = torch.zeros_like(self.eta)
+            self.v_e = torch.zeros_like(self.eta)
         self.t = 0
         self.it = 0
         self.plan = pruning_plan(self.ntap, [cfg.t_final] * len(self.ntap), cfg.iters, cfg.prune_frac) \
@@ -162,16 +181,26 @@ class Trainer:
         self.ntap[layer] -= 2
         self._mirror = None
 
+    def eta_per_step(self) -> torch.Tensor:
+        """The filters of the nonlinear steps back to back (the shared one repeated in every step)."""
+        return self.eta.repeat(len(self.ntap)) if self.cfg.essm_shared else self.eta
+
+    def _fwd(self, r, **kw):
+        if self.essm:
+            return E.essm_forward(r, self.taps, self.c, self.eta_per_step(), self.ntap, self.nl_ntap,
+                                  npol=self.cfg.npol, **kw)
+        return L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=self.cfg.npol, **kw)
+
     def forward(self, r: torch.Tensor, ckpt: bool = False):
         cfg = self.cfg
         sym = 1 if cfg.symmetric else 0
         if not ckpt:
-            return L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=cfg.npol, plan=(0, 0, 0, sym)), None
+            return self._fwd(r, plan=(0, 0, 0, sym)), None
         S = max(1, min(cfg.ckpt_every, len(self.ntap)))
         nslot = L.num_checkpoints(len(self.ntap), S)
         ck = torch.empty((nslot,) + tuple(r.shape), dtype=r.dtype, device=r.device) if nslot else None
-        z = L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=cfg.npol, ckpt=ck, ckpt_every=S if ck is not None else 0,
-                           plan=(S, 0, 0, sym) if ck is None else (0, 0, 0, sym))
+        z = self._fwd(r, ckpt=ck, ckpt_every=S if ck is not None else 0,
+                      plan=(S, 0, 0, sym) if ck is None else (0, 0, 0, sym))
         return z, ck
 
     def step(self):
@@ -184,13 +213,23 @@ class Trainer:
         z, ck = self.forward(r, ckpt=True)
         S = max(1, min(cfg.ckpt_every, len(self.ntap)))
         mse, _, gz = TX.rx_mse(z, s, p, cfg.rho_d, cfg.rs, cfg.rolloff, npol=cfg.npol, want_grad=True)
-        _, gt, gc = L.ldbp_backward(r, self.taps, self.c, self.ntap, gz, npol=cfg.npol, ckpt=ck, ckpt_every=S,
-                                    need_gx=False, symmetric=cfg.symmetric)
+        if self.essm:
+            _, gt, gc, ge = E.essm_backward(r, self.taps, self.c, self.eta_per_step(), self.ntap, self.nl_ntap, gz,
+                                            npol=cfg.npol, ckpt=ck, ckpt_every=S, need_gx=False,
+                                            symmetric=cfg.symmetric)
+            if cfg.essm_shared:
+                ge = ge.view(len(self.ntap), -1).sum(0)
+        else:
+            _, gt, gc = L.ldbp_backward(r, self.taps, self.c, self.ntap, gz, npol=cfg.npol, ckpt=ck, ckpt_every=S,
+                                        need_gx=False, symmetric=cfg.symmetric)
         self.t += 1
-        TX.adam_(self.taps, gt, self.m_t, self.v_t, self.t, lr=cfg.lr,
-                 mirror=self.mirror() if cfg.symmetric else None)
+        if cfg.train_taps:
+            TX.adam_(self.taps, gt, self.m_t, self.v_t, self.t, lr=cfg.lr,
+                     mirror=self.mirror() if cfg.symmetric else None)
         if cfg.train_c:
             TX.adam_(self.c, gc, self.m_c, self.v_c, self.t, lr=cfg.lr)
+        if self.essm:
+            TX.adam_(self.eta, ge, self.m_e, self.v_e, self.t, lr=cfg.lr)
         loss = float(mse.mean().item())
         self.history.append({"it": self.it, "loss": loss, "taps": int(sum(self.ntap))})
         self.it += 1
@@ -242,9 +281,12 @@ class Trainer:
 
     # ------------------------------------------------------------------ checkpoints
     def state_dict(self):
-        return {"cfg": asdict(self.cfg), "taps": self.taps.cpu(), "c": self.c.cpu(), "ntap": list(self.ntap),
-                "m_t": self.m_t.cpu(), "v_t": self.v_t.cpu(), "m_c": self.m_c.cpu(), "v_c": self.v_c.cpu(),
-                "t": self.t, "it": self.it, "events_done": self.events_done}
+        st = {"cfg": asdict(self.cfg), "taps": self.taps.cpu(), "c": self.c.cpu(), "ntap": list(self.ntap),
+              "m_t": self.m_t.cpu(), "v_t": self.v_t.cpu(), "m_c": self.m_c.cpu(), "v_c": self.v_c.cpu(),
+              "t": self.t, "it": self.it, "events_done": self.events_done}
+        if self.essm:
+            st.update(eta=self.eta.cpu(), m_e=self.m_e.cpu(), v_e=self.v_e.cpu())
+        return st
 
     def load_state_dict(self, st):
         self.taps = st["taps"].to(self.dev)
@@ -253,6 +295,8 @@ class Trainer:
         self.m_t, self.v_t = st["m_t"].to(self.dev), st["v_t"].to(self.dev)
         self.m_c, self.v_c = st["m_c"].to(self.dev), st["v_c"].to(self.dev)
         self.t, self.it, self.events_done = int(st["t"]), int(st["it"]), int(st["events_done"])
+        if self.essm:
+            self.eta, self.m_e, self.v_e = st["eta"].to(self.dev), st["m_e"].to(self.dev), st["v_e"].to(self.dev)
         self._mirror = None
 
     def save(self, path: str):

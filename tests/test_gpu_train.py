@@ -137,3 +137,82 @@ def test_learned_ldbp_gains_over_its_initialisation():
           flush=True)
     assert snr1 >= snr0 + 1.0
     assert snr1 >= dbp1
+
+
+@pytest.mark.parametrize("shared", [False, True])
+def test_essm_training_gradient_matches_oracle(shared):
+    """Generalised (per-step filters) and conventional (one shared filter) ESSM training gradients of the
+    receiver MSE against the oracle adjoint; the shared filter's gradient is the sum over the steps."""
+    print("case: essm training gradient", shared, flush=True)
+    tr = T.Trainer(_small(t_init=11, t_final=11, ldbp_steps=2, complex128=True, essm_kappa=3, essm_shared=shared))
+    g = np.random.default_rng(5)
+    tr.eta += torch.from_numpy(g.uniform(-0.2, 0.2, tr.eta.numel())).to(tr.eta)
+    r, s, p = tr.batch(4)
+    z, ck = tr.forward(r, ckpt=True)
+    from paper_2010_14258_amd import essm as E, txrx as TX
+    from oracle import essm as OE
+    mse, _, gz = TX.rx_mse(z, s, p, 2, tr.cfg.rs, want_grad=True)
+    S = min(tr.cfg.ckpt_every, len(tr.ntap))
+    _, gt, gc, ge = E.essm_backward(r, tr.taps, tr.c, tr.eta_per_step(), tr.ntap, tr.nl_ntap, gz, ckpt=ck,
+                                    ckpt_every=S, need_gx=False, symmetric=True)
+    torch.cuda.synchronize()
+    rn, sn, pn = r.cpu().numpy(), s.cpu().numpy(), p.cpu().numpy()
+    tp = tr.taps.cpu().numpy()
+    off = np.cumsum([0] + tr.ntap)
+    taps = [tp[off[i]:off[i + 1]] for i in range(len(tr.ntap))]
+    ev = tr.eta_per_step().cpu().numpy()
+    eta = [ev[7 * i:7 * i + 7] for i in range(len(tr.ntap))]
+    c = tr.c.cpu().numpy()
+    y = OE.essm_forward(rn, taps, c, eta)
+    loss, gy = X.rx_loss_and_grad(y, sn, 2, pn, tr.cfg.rs)
+    _, gtr, gcr, ger = OE.essm_grad(rn, taps, c, eta, gy)
+    assert abs(float(mse.mean()) - loss) <= 1e-9 * loss
+    assert _rel(gc.cpu().numpy(), gcr) <= 1e-9
+    assert _rel(ge.cpu().numpy(), np.concatenate(ger)) <= 1e-9
+    if shared:
+        assert _rel(ge.view(len(tr.ntap), -1).sum(0).cpu().numpy(), np.sum(ger, axis=0)) <= 1e-9
+    # symmetric taps: the projected tap gradient
+    proj = [0.5 * (h + h[::-1]) for h in gtr]
+    assert _rel(gt.cpu().numpy(), np.concatenate(proj)) <= 1e-9
+
+
+def test_essm_resume_is_bitwise_identical(tmp_path):
+    print("case: essm resume", flush=True)
+    cfg = _small(t_init=9, t_final=7, iters=10, essm_kappa=4)
+    a = T.Trainer(cfg)
+    a.train(10)
+    b = T.Trainer(cfg)
+    b.train(4)
+    path = os.path.join(tmp_path, "ck.pt")
+    b.save(path)
+    c = T.Trainer(cfg)
+    c.load(path)
+    c.train(6)
+    np.testing.assert_array_equal(a.taps.cpu().numpy(), c.taps.cpu().numpy())
+    np.testing.assert_array_equal(a.eta.cpu().numpy(), c.eta.cpu().numpy())
+    assert not np.array_equal(a.eta.cpu().numpy(), T.Trainer(cfg).eta.cpu().numpy())
+
+
+def test_conventional_essm_trains_only_its_filter():
+    print("case: conventional essm", flush=True)
+    cfg = _small(essm_kappa=5, essm_shared=True, train_taps=False, train_c=False, iters=5)
+    tr = T.Trainer(cfg)
+    t0, c0 = tr.taps.clone(), tr.c.clone()
+    tr.train(5)
+    assert torch.equal(tr.taps, t0) and torch.equal(tr.c, c0)
+    assert tr.eta.numel() == 11 and tr.eta_per_step().numel() == 11 * len(tr.ntap)
+    assert not torch.equal(tr.eta, torch.nn.functional.one_hot(torch.tensor(5), 11).to(tr.eta))
+
+
+def test_learned_essm_gains_over_its_initialisation():
+    """10 x 100 km, 4 dBm, 1 step per span, 9 taps and 2 x 10 + 1 filter taps per step: the generalised
+    ESSM starts as the least-squares LDBP (unit filters) and gains after 400 Adam iterations."""
+    print("case: learned essm", flush=True)
+    cfg = T.TrainConfig(nwave=8, nsym=1024, rho_a=4, rho_d=2, nspan=10, span_km=100, channel_steps=20,
+                        ldbp_steps=1, t_init=9, t_final=9, iters=400, powers_dbm=(4.0,), seed=7, essm_kappa=10)
+    tr = T.Trainer(cfg)
+    snr0 = tr.evaluate(nbatch=4, p_dbm=4.0)
+    tr.train(400)
+    snr1 = tr.evaluate(nbatch=4, p_dbm=4.0)
+    print(f"ESSM LS init {snr0:.2f} dB, trained {snr1:.2f} dB", flush=True)
+    assert snr1 >= snr0 + 1.0
