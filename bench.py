@@ -480,6 +480,8 @@ def main():
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--train-taps", default="25:3",
                     help="models of --mode snr: initial:final taps per step, comma separated (pruned in training)")
+    ap.add_argument("--one-stream", action="store_true",
+                    help="fwd/pmc modes: keep every launch on one stream (the kernel's own per-launch time)")
     ap.add_argument("--plan", default=None,
                     help="forward plan S,chunks,outputs_per_thread,symmetric (default: autotuned, folded)")
     args = ap.parse_args()
@@ -535,8 +537,13 @@ def main():
     folded = bool(plan[3])
     ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, plan=plan), 1), dtype=torch.uint8, device=dev)
 
+    plan1 = tuple(plan[:4]) + (1,)   # the same plan with every launch on the caller's stream
+
     def fwd():
-        L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan, ws=ws, stream=stream)
+        L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan1 if args.one_stream else plan, ws=ws, stream=stream)
+
+    def fwd_one():
+        L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan1, ws=ws, stream=stream)
 
     if args.mode == "pmc":
         for _ in range(3):
@@ -558,8 +565,12 @@ def main():
     npass, tile_len, spp = L.ldbp_forward_plan_query(0, 1, nwave, n, ntap, plan=plan)
     ss = nwave * n * ell
     value = ss / (ms_fwd * 1e-3)
-    launch_ms = ms_fwd / npass
-    flops_launch = nwave * n * sum(fwd_flops_per_sample_step(t, folded) for t in ntap) / npass
+    # the kernel's own per-launch time: the same plan with every launch on the caller's stream (the
+    # default call runs the two halves of the batch on two streams, whose launches overlap)
+    ms_one = event_time(torch, stream, fwd_one, args.steps, args.warmup)
+    launch_ms = ms_one / npass
+    flops_fwd = nwave * n * sum(fwd_flops_per_sample_step(t, folded) for t in ntap)
+    flops_launch = flops_fwd / npass
     achieved_tflops = flops_launch / (launch_ms * 1e-3) / 1e12
     bytes_launch = nwave * n * 8 * 2
     achieved_gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
@@ -593,9 +604,11 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / FP32_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": f"ldbp_fwd_kernel<float,1,{plan[2]},256>" + (" folded" if folded else ""),
-                     "launch_ms": launch_ms,
+                     "launch_ms": launch_ms, "one_stream_ms_per_step": ms_one,
                      "flops_per_launch": flops_launch, "algorithmic_bytes_per_launch": bytes_launch,
-                     "hbm_achieved_gbs": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS},
+                     "hbm_achieved_gbs": achieved_gbs, "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
+                     "split_batch_achieved": flops_fwd / (ms_fwd * 1e-3) / 1e12,
+                     "split_batch_frac": flops_fwd / (ms_fwd * 1e-3) / 1e12 / FP32_PEAK_TFLOPS},
     }
 
     if plan_gen is not None:

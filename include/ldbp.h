@@ -25,6 +25,12 @@
  *     caller.  Inputs and outputs must not overlap unless stated.
  *   - stream is a hipStream_t passed as void* (NULL = the null stream).  Calls
  *     enqueue work and return without synchronising the host, except where noted.
+ *     The multi-pass forward and the backward may run the second half of the batch
+ *     on a second stream the library keeps per host thread, device and caller stream
+ *     (default priority; at most 16 per thread), forked from `stream` by an event
+ *     before its first launch and joined back into it after its last; work enqueued
+ *     on `stream` afterwards is ordered after the whole call.  Not while `stream` is
+ *     being captured into a graph, and not with LDBP_PLAN_ONE_STREAM.
  *   - Every function returns LDBP_OK (0) or a negative ldbp_status.  Argument
  *     checks run before any GPU work is enqueued; on failure nothing is
  *     enqueued.  ldbp_last_error() returns a thread-local message for the last
@@ -68,9 +74,12 @@ enum ldbp_dtype { LDBP_C64 = 0, LDBP_C128 = 1 };
  *   flags               LDBP_PLAN_SYMMETRIC: the caller guarantees h_{-k} = h_k for every
  *                       filter; the forward then evaluates the folded form
  *                       h_0 x_m + sum_{k>=1} h_k (x_{m-k} + x_{m+k}) (Sec. III-B).
+ *                       LDBP_PLAN_ONE_STREAM: every launch goes to `stream` (no split of
+ *                       the batch over a second stream).
  * Results are bit-identical for any steps_per_pass and chunks at fixed
- * outputs_per_thread and flags. */
+ * outputs_per_thread and LDBP_PLAN_SYMMETRIC, with or without LDBP_PLAN_ONE_STREAM. */
 #define LDBP_PLAN_SYMMETRIC 1
+#define LDBP_PLAN_ONE_STREAM 2
 typedef struct ldbp_plan {
   int32_t steps_per_pass;
   int32_t chunks;
@@ -175,7 +184,8 @@ int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
  *                correlation) are evaluated folded, and gtaps holds the gradient projected on
  *                symmetric filters: entries k and -k both hold (dL/dh_k + dL/dh_{-k}) / 2, the
  *                centre dL/dh_0 (so their sum over a mirrored pair is the gradient of the shared
- *                parameter).  Other flag bits: LDBP_EINVAL.
+ *                parameter).  LDBP_PLAN_ONE_STREAM as for the forward.  Other flag bits:
+ *                LDBP_EINVAL.
  *   ws           device workspace of ldbp_backward_workspace_size() bytes
  * -------------------------------------------------------------------------*/
 int ldbp_backward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,

@@ -33,6 +33,7 @@ class LdbpPlan(ctypes.Structure):
 
 
 LDBP_PLAN_SYMMETRIC = 1
+LDBP_PLAN_ONE_STREAM = 2
 
 
 P_plan = ctypes.POINTER(LdbpPlan)

@@ -41,6 +41,81 @@ static int check_model(const ModelArgs& m) {
   return LDBP_OK;
 }
 
+// A second stream per host thread, device and caller stream, with the two events that fork it from
+// the caller's stream and join it back.  Created on first use and kept until the process ends.
+// Keyed by the caller's stream so that calls on different streams stay independent of each other.
+struct SideStream {
+  int dev = -1;
+  hipStream_t caller = nullptr;
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr size_t kMaxSideStreams = 16;  // per host thread; further caller streams run on one stream
+
+// The side stream for work forked from `caller`, or NULL when the call should stay on one stream:
+// the caller's stream is being captured, belongs to another device than the current one, the
+// thread already keeps kMaxSideStreams of them, or a runtime call fails (its error is cleared; the
+// work then simply runs on one stream).
+static SideStream* side_stream(hipStream_t caller) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(caller, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  if (caller) {
+    hipDevice_t sd = -1;
+    if (hipStreamGetDevice(caller, &sd) != hipSuccess || sd != cur) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  thread_local std::vector<SideStream> sides;
+  for (auto& x : sides)
+    if (x.dev == cur && x.caller == caller) return x.s ? &x : nullptr;
+  if (sides.size() >= kMaxSideStreams) return nullptr;
+  SideStream x;
+  x.dev = cur;
+  x.caller = caller;
+  if (hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&x.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&x.join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    x.s = nullptr;  // remembered: this caller stream keeps to one stream
+  }
+  sides.push_back(x);
+  return x.s ? &sides.back() : nullptr;
+}
+
+// Runs run(w0, w1, stream) over the waveforms of the batch: with split, waveforms [h, nwave) on the
+// side stream (forked from s, joined back into s) and [0, h) on s, h = ceil(nwave / 2); otherwise all
+// of them on s.  The two halves touch disjoint waveforms, so the kernels of one fill the other's
+// ramp-up and drain at every launch boundary.
+template <typename F>
+static int over_halves(hipStream_t s, int64_t nwave, bool split, F&& run) {
+  SideStream* side = (split && nwave >= 2) ? side_stream(s) : nullptr;
+  if (!side) return run(0, nwave, s);
+  const int64_t h = (nwave + 1) / 2;
+  LDBP_HIP_CHECK(hipEventRecord(side->fork, s));
+  LDBP_HIP_CHECK(hipStreamWaitEvent(side->s, side->fork, 0));
+  int st = run(0, h, s);
+  const int st2 = st ? LDBP_OK : run(h, nwave, side->s);
+  // join even after a failed launch, so that later work on s stays ordered after everything enqueued
+  LDBP_HIP_CHECK(hipEventRecord(side->join, side->s));
+  LDBP_HIP_CHECK(hipStreamWaitEvent(s, side->join, 0));
+  return st ? st : st2;
+}
+
+// The split pays when a call has several launches of at least two workgroups per compute unit.
+static bool worth_splitting(const ldbp_plan* plan, size_t launches, int64_t blocks_per_launch) {
+  if (plan && (plan->flags & LDBP_PLAN_ONE_STREAM)) return false;
+  return launches >= 2 && blocks_per_launch >= 512;
+}
+
 static int max_chunks(int dtype, int npol, int rb, bool filtered = false) {
   int c = 1;
   while (fwd_lds_bytes(dtype, npol, rb, c + 1, filtered) <= kMaxLdsBytes) ++c;
@@ -169,21 +244,35 @@ static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ld
 }
 
 // Runs steps [0, pp's last step] from x, writing every block input b >= 1 to slot b - 1 of ckpt;
-// the output of the final pass goes to `last` (y, or the last slot).
+// the output of the final pass goes to `last` (y, or the last slot).  Pointers are those of the whole
+// batch; the launches cover waveforms [w0, w1).
 static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* taps, const void* c, const void* x,
-                          void* last, void* ckpt, int32_t S, hipStream_t s, const void* eta = nullptr) {
+                          void* last, void* ckpt, int32_t S, hipStream_t s, const void* eta = nullptr,
+                          int64_t w0 = 0, int64_t w1 = -1) {
+  if (w1 < 0) w1 = m.nwave;
   const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
-  const void* in = x;
+  const size_t w_off = static_cast<size_t>(w0) * m.n * m.npol * cx_size(m.dtype);
+  const int64_t slot_elems = m.nwave * m.n * m.npol;
+  const void* in = static_cast<const char*>(x) + w_off;
   for (size_t i = 0; i < pp.passes.size(); ++i) {
     const PassTable& pt = pp.passes[i];
-    void* out = (i + 1 == pp.passes.size()) ? last
-                                            : static_cast<char*>(ckpt) + ((pt.c0 + pt.nstep) / S - 1) * wave_bytes;
-    int st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, m.nwave, static_cast<int32_t>(m.n), pp.chunks, pt, taps,
-                             c, pp.sym, ckpt, s, eta);
+    char* base = (i + 1 == pp.passes.size()) ? static_cast<char*>(last)
+                                             : static_cast<char*>(ckpt) + ((pt.c0 + pt.nstep) / S - 1) * wave_bytes;
+    void* out = base + w_off;
+    int st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0, static_cast<int32_t>(m.n), pp.chunks, pt,
+                             taps, c, pp.sym, ckpt ? static_cast<char*>(ckpt) + w_off : nullptr, s, eta, slot_elems);
     if (st) return st;
     in = out;
   }
   return LDBP_OK;
+}
+
+// Workgroups of one forward launch over the batch (the pass with the largest halo has the most tiles).
+static int64_t fwd_blocks(const ModelArgs& m, const PassPlan& pp) {
+  int32_t halo = 0;
+  for (const auto& pt : pp.passes) halo = std::max(halo, pt.halo);
+  const int64_t tile = std::max<int64_t>(1, int64_t(pp.chunks) * fwd_chunk(m.dtype, m.npol, pp.rb) - 2 * halo);
+  return m.nwave * ((m.n + tile - 1) / tile);
 }
 
 }  // namespace ldbp
@@ -229,13 +318,18 @@ static int forward_impl(const ModelArgs& m, const void* taps, const void* c, con
     if (nslot > 0 && (overlaps(ckpt, nslot * wave_bytes, x, wave_bytes) || overlaps(ckpt, nslot * wave_bytes, y, wave_bytes)))
       return fail(LDBP_EINVAL, "ckpt overlaps x or y");
   }
+  if (plan && (plan->flags & ~(LDBP_PLAN_SYMMETRIC | LDBP_PLAN_ONE_STREAM)))
+    return fail(LDBP_EINVAL, "plan flags 0x%x: unknown bits", plan->flags);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const void* e = m.filtered() ? eta : nullptr;
   if (ckpt) {
     PassPlan bp;
     st = make_block_plan(m, ckpt_every, m.nstep, plan, bp);
     if (st) return st;
-    return run_block_plan(m, bp, taps, c, x, y, ckpt, ckpt_every, s, e);
+    return over_halves(s, m.nwave, worth_splitting(plan, bp.passes.size(), fwd_blocks(m, bp)),
+                       [&](int64_t w0, int64_t w1, hipStream_t ss) {
+                         return run_block_plan(m, bp, taps, c, x, y, ckpt, ckpt_every, ss, e, w0, w1);
+                       });
   }
   PassPlan pp;
   st = make_plan(m, 0, plan, pp);
@@ -248,15 +342,22 @@ static int forward_impl(const ModelArgs& m, const void* taps, const void* c, con
     if (overlaps(ws, wave_bytes, x, wave_bytes) || overlaps(ws, wave_bytes, y, wave_bytes))
       return fail(LDBP_EINVAL, "workspace overlaps x or y");
   }
-  const void* in = x;
-  for (size_t i = 0; i < np; ++i) {
-    void* out = ((np - 1 - i) % 2 == 0) ? y : ws;  // ping-pong that ends in y
-    st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, m.nwave, static_cast<int32_t>(m.n), pp.chunks, pp.passes[i],
-                         taps, c, pp.sym, nullptr, s, e);
-    if (st) return st;
-    in = out;
-  }
-  return LDBP_OK;
+  const size_t wave_elem_bytes = static_cast<size_t>(m.n) * m.npol * cx_size(m.dtype);
+  return over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)),
+                     [&](int64_t w0, int64_t w1, hipStream_t ss) {
+                       const size_t off = static_cast<size_t>(w0) * wave_elem_bytes;
+                       const void* in = static_cast<const char*>(x) + off;
+                       for (size_t i = 0; i < np; ++i) {
+                         // ping-pong that ends in y
+                         void* out = static_cast<char*>(((np - 1 - i) % 2 == 0) ? y : ws) + off;
+                         const int r = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0,
+                                                       static_cast<int32_t>(m.n), pp.chunks, pp.passes[i], taps, c,
+                                                       pp.sym, nullptr, ss, e);
+                         if (r) return r;
+                         in = out;
+                       }
+                       return static_cast<int>(LDBP_OK);
+                     });
 }
 
 static int plan_query_impl(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* plan, int32_t* npasses,
@@ -327,16 +428,19 @@ extern "C" int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwav
 namespace ldbp {
 
 constexpr size_t kBwdLdsBudget = 53 * 1024;   // three workgroups per CU
+// Filtered steps: the kernel's registers allow two workgroups per CU, so each may take half the LDS
+// (longer tiles, less halo recompute; measured 1.5x faster than 53 KiB at kappa = 20).
+constexpr size_t kBwdLdsBudgetFiltered = 80 * 1024;
 
 // LDS budget of one backward workgroup; LDBP_BWD_LDS_KIB overrides it (a tuning knob: a smaller
 // budget gives more workgroups per CU, a larger one longer tiles and less halo recompute).
-static size_t bwd_lds_budget() {
+static size_t bwd_lds_budget(bool filtered) {
   const char* e = std::getenv("LDBP_BWD_LDS_KIB");
   if (e) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 16 && v <= 160) return static_cast<size_t>(v) * 1024;
   }
-  return kBwdLdsBudget;
+  return filtered ? kBwdLdsBudgetFiltered : kBwdLdsBudget;
 }
 
 static size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
@@ -359,7 +463,7 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
   int st = make_plan(m, L.S, nullptr, L.blocks);
   if (st) return st;
   // tile length: the largest multiple of 64 whose LDS footprint fits the budget for every block
-  size_t budget = bwd_lds_budget();
+  size_t budget = bwd_lds_budget(m.filtered());
   int best = 0;
   for (; budget <= kMaxLdsBytes && best == 0; budget += 32 * 1024) {
     for (int Lw = 4096; Lw >= 64; Lw -= 64) {
@@ -422,8 +526,9 @@ static int backward_impl(const ModelArgs& m, const void* taps, const void* c, co
   const int64_t nwave = m.nwave, n = m.n;
   int st = check_model(m);
   if (st) return st;
-  if (plan && (plan->flags & ~LDBP_PLAN_SYMMETRIC))
-    return fail(LDBP_EINVAL, "plan flags 0x%x: only LDBP_PLAN_SYMMETRIC is defined", plan->flags);
+  if (plan && (plan->flags & ~(LDBP_PLAN_SYMMETRIC | LDBP_PLAN_ONE_STREAM)))
+    return fail(LDBP_EINVAL, "plan flags 0x%x: only LDBP_PLAN_SYMMETRIC and LDBP_PLAN_ONE_STREAM are defined",
+                plan->flags);
   const int sym = (plan && (plan->flags & LDBP_PLAN_SYMMETRIC)) ? 1 : 0;
   if (!taps || !c || !x || !gy || !gtaps || !gc)
     return fail(LDBP_EINVAL, "taps, c, x, gy, gtaps and gc must be non-NULL");
@@ -459,26 +564,38 @@ static int backward_impl(const ModelArgs& m, const void* taps, const void* c, co
   void* part = wsb + L.off_part;
   const size_t nb = L.blocks.passes.size();
   const char* ck = static_cast<const char*>(ckpt);
+  PassPlan bp;  // forward passes that recompute the block inputs 1 .. nb-1 when no checkpoints are given
   if (!ckpt && nb > 1) {
-    // recompute the block inputs 1 .. nb-1 with the forward, passes grouped over whole blocks
     ck = wsb + L.off_ckpt;
     const int32_t nrun = L.blocks.passes[nb - 1].c0;
     ldbp_plan fp{0, 0, L.blocks.rb, sym ? LDBP_PLAN_SYMMETRIC : 0};
-    PassPlan bp;
     st = make_block_plan(m, L.S, nrun, &fp, bp);
     if (st) return st;
-    st = run_block_plan(m, bp, taps, c, x, wsb + L.off_ckpt + (nb - 2) * wave_bytes, wsb + L.off_ckpt, L.S, s, e);
-    if (st) return st;
   }
-  const void* gcur = gy;
-  for (size_t bi = nb; bi-- > 0;) {
-    const void* xb = bi == 0 ? x : static_cast<const void*>(ck + (bi - 1) * wave_bytes);
-    void* gin = (bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0);
-    st = launch_bwd_block(dtype, npol, xb, gcur, gin, nwave, static_cast<int32_t>(n), L.tile_len,
-                          L.blocks.passes[bi], taps, c, part, L.ncols, L.ntaps + L.neta, sym, s, e, L.ntaps);
-    if (st) return st;
-    gcur = gin;
-  }
+  const size_t wave_elem_bytes = static_cast<size_t>(n) * npol * cx_size(dtype);
+  const int64_t tiles_per_wave = L.ntiles / nwave;
+  st = over_halves(s, nwave, worth_splitting(plan, nb, L.ntiles), [&](int64_t w0, int64_t w1, hipStream_t ss) {
+    const size_t off = static_cast<size_t>(w0) * wave_elem_bytes;
+    if (!ckpt && nb > 1) {
+      const int r = run_block_plan(m, bp, taps, c, x, wsb + L.off_ckpt + (nb - 2) * wave_bytes, wsb + L.off_ckpt,
+                                   L.S, ss, e, w0, w1);
+      if (r) return r;
+    }
+    // this range's rows of the partial sums: the tiles of waveforms [w0, w1)
+    void* prt = static_cast<double*>(part) + static_cast<size_t>(w0 * tiles_per_wave) * L.ncols * 2;
+    const char* gcur = static_cast<const char*>(gy) + off;
+    for (size_t bi = nb; bi-- > 0;) {
+      const char* xb = (bi == 0 ? static_cast<const char*>(x) : ck + (bi - 1) * wave_bytes) + off;
+      char* gin = static_cast<char*>((bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0)) + off;
+      const int r = launch_bwd_block(dtype, npol, xb, gcur, gin, w1 - w0, static_cast<int32_t>(n), L.tile_len,
+                                     L.blocks.passes[bi], taps, c, prt, L.ncols, L.ntaps + L.neta, sym, ss, e,
+                                     L.ntaps);
+      if (r) return r;
+      gcur = gin;
+    }
+    return static_cast<int>(LDBP_OK);
+  });
+  if (st) return st;
   return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s, L.neta, geta);
 }
 

@@ -401,6 +401,188 @@ __device__ __forceinline__ void eta_grad(const R* __restrict__ Q, const R* __res
   }
 }
 
+// Adjoint of the filtered phase of one step over G indices [lo + kap, hi - kap), with q = dL/dphi in Q
+// and P = |y|^2 in PP, both filled on [lo, hi):
+//   F_i = sum_k eta_k P_{i-k},  r_i = c sum_k eta_k q_{i+k},  G_u,i = (G_y,i + 2 r_i y_i) e^{-j c F_i};
+// y_i is ycur[(i + yoff) * NPOL + p].  Returns this thread's share of sum_{owned i} q_i F_i (dL/dc).
+// Generic kappa: one sample per thread and iteration.
+template <typename R, int NPOL, int THREADS>
+__device__ __forceinline__ R nl_adjoint_generic(const cx_t<R>* __restrict__ ycur, int yoff, const cx_t<R>* __restrict__ GA,
+                                                cx_t<R>* __restrict__ GB, const R* __restrict__ Q,
+                                                const R* __restrict__ PP, int lo, int hi, int kap,
+                                                const R* __restrict__ e, R cr, R coef, int own_lo, int own_hi) {
+  using V = cx_t<R>;
+  R accc = 0;
+  for (int i = lo + kap + static_cast<int>(threadIdx.x); i < hi - kap; i += THREADS) {
+    R F = 0, r = 0;
+    for (int k = -kap; k <= kap; ++k) {
+      F = fma(e[kap + k], PP[i - k], F);
+      r = fma(e[kap + k], Q[i + k], r);
+    }
+    R sn, co;
+    phase_sincos(coef, F, sn, co);
+    const R tr = 2 * cr * r;
+#pragma unroll
+    for (int pp = 0; pp < NPOL; ++pp) {
+      const V yv = ycur[(i + yoff) * NPOL + pp];
+      const V gv = GA[i * NPOL + pp];
+      // G_y e^{-j phi} + 2 r u with u = y e^{-j phi}: (G_y + 2 r y) e^{-j phi}
+      const R tx = gv.x + tr * yv.x;
+      const R ty = gv.y + tr * yv.y;
+      GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
+    }
+    if (i >= own_lo && i < own_hi) accc += Q[i] * F;
+  }
+  return accc;
+}
+
+// Fixed kappa: RBF (odd) consecutive samples per thread from register windows of P and q (2 (RBF + 2 kappa)
+// LDS reads for RBF samples instead of 2 (2 kappa + 1) each), the filter taps uniform (scalar
+// registers).  Window entries outside [lo, hi) are read as zero, so LDS left over from other data
+// never enters a sum.
+template <typename R, int NPOL, int THREADS, int KAP>
+__device__ __forceinline__ R nl_adjoint_fixed(const cx_t<R>* __restrict__ ycur, int yoff, const cx_t<R>* __restrict__ GA,
+                                              cx_t<R>* __restrict__ GB, const R* __restrict__ Q,
+                                              const R* __restrict__ PP, int lo, int hi, const R* __restrict__ e,
+                                              R cr, R coef, int own_lo, int own_hi) {
+  using V = cx_t<R>;
+  constexpr int RBF = 7;  // odd: lanes RBF words apart fall on distinct LDS banks
+  constexpr int W = RBF + 2 * KAP;
+  R accc = 0;
+  const int lo2 = lo + KAP, hi2 = hi - KAP;
+  for (int base = lo2 + static_cast<int>(threadIdx.x) * RBF; base < hi2; base += THREADS * RBF) {
+    // F from a window of P, then r from a window of q (one window live at a time)
+    R F[RBF], rr[RBF], qo[RBF];
+    {
+      R w[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int m = base - KAP + j;
+        w[j] = m < hi ? PP[m] : R(0);
+      }
+#pragma unroll
+      for (int r = 0; r < RBF; ++r) F[r] = 0;
+#pragma unroll
+      for (int k = -KAP; k <= KAP; ++k) {
+        const R ek = e[KAP + k];
+#pragma unroll
+        for (int r = 0; r < RBF; ++r) F[r] = fma(ek, w[r - k + KAP], F[r]);
+      }
+    }
+    {
+      R w[W];
+#pragma unroll
+      for (int j = 0; j < W; ++j) {
+        const int m = base - KAP + j;
+        w[j] = m < hi ? Q[m] : R(0);
+      }
+#pragma unroll
+      for (int r = 0; r < RBF; ++r) {
+        rr[r] = 0;
+        qo[r] = w[r + KAP];
+      }
+#pragma unroll
+      for (int k = -KAP; k <= KAP; ++k) {
+        const R ek = e[KAP + k];
+#pragma unroll
+        for (int r = 0; r < RBF; ++r) rr[r] = fma(ek, w[r + k + KAP], rr[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RBF; ++r) {
+      const int i = base + r;
+      if (i < hi2) {
+        R sn, co;
+        phase_sincos(coef, F[r], sn, co);
+        const R tr = 2 * cr * rr[r];
+#pragma unroll
+        for (int pp = 0; pp < NPOL; ++pp) {
+          const V yv = ycur[(i + yoff) * NPOL + pp];
+          const V gv = GA[i * NPOL + pp];
+          const R tx = gv.x + tr * yv.x;
+          const R ty = gv.y + tr * yv.y;
+          GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
+        }
+        if (i >= own_lo && i < own_hi) accc += qo[r] * F[r];
+      }
+    }
+  }
+  return accc;
+}
+
+template <typename R, int NPOL, int THREADS>
+__device__ __forceinline__ R nl_adjoint_dispatch(const cx_t<R>* ycur, int yoff, const cx_t<R>* GA, cx_t<R>* GB,
+                                                 const R* Q, const R* PP, int lo, int hi, int kap, const R* e, R cr,
+                                                 R coef, int own_lo, int own_hi) {
+  if constexpr (sizeof(R) == 4) {
+    switch (kap) {
+#define LDBP_NLA_CASE(k) \
+  case k: return nl_adjoint_fixed<R, NPOL, THREADS, k>(ycur, yoff, GA, GB, Q, PP, lo, hi, e, cr, coef, own_lo, own_hi);
+      LDBP_NLA_CASE(1) LDBP_NLA_CASE(2) LDBP_NLA_CASE(3) LDBP_NLA_CASE(4) LDBP_NLA_CASE(5) LDBP_NLA_CASE(6)
+      LDBP_NLA_CASE(8) LDBP_NLA_CASE(10) LDBP_NLA_CASE(12) LDBP_NLA_CASE(16) LDBP_NLA_CASE(20)
+#undef LDBP_NLA_CASE
+      default: break;
+    }
+  }
+  return nl_adjoint_generic<R, NPOL, THREADS>(ycur, yoff, GA, GB, Q, PP, lo, hi, kap, e, cr, coef, own_lo, own_hi);
+}
+
+// Filter-tap gradient sums g_k = sum_{owned i} q_i P_{i-k}, k = -kap..kap, for fixed kappa: RBF owned
+// samples per thread against a register window of P, the 2 kappa + 1 sums reduced over the wave in
+// groups of 16 by the butterfly (wave_reduce_multi) and stored as wave partials red[wv][col0 + k + kap].
+template <typename R, int THREADS, int KAP>
+__device__ __forceinline__ void eta_grad_fixed(const R* __restrict__ Q, const R* __restrict__ PP, int own_lo, int Lw,
+                                               double2* __restrict__ red, int ldr, int col0) {
+  constexpr int RBF = 7;  // odd: lanes RBF words apart fall on distinct LDS banks
+  constexpr int NE = 2 * KAP + 1;
+  constexpr int W = RBF + 2 * KAP;
+  const int own_hi = own_lo + Lw;
+  R g[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) g[k] = 0;
+  for (int base = own_lo + static_cast<int>(threadIdx.x) * RBF; base < own_hi; base += THREADS * RBF) {
+    R wp[W], q[RBF];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int m = base - KAP + j;
+      wp[j] = m < own_hi + KAP ? PP[m] : R(0);
+    }
+#pragma unroll
+    for (int r = 0; r < RBF; ++r) q[r] = base + r < own_hi ? Q[base + r] : R(0);
+#pragma unroll
+    for (int k = -KAP; k <= KAP; ++k)
+#pragma unroll
+      for (int r = 0; r < RBF; ++r) g[KAP + k] = fma(q[r], wp[r - k + KAP], g[KAP + k]);
+  }
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int g0 = 0; g0 < NE; g0 += 16) {
+    float vals[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) vals[j] = g0 + j < NE ? g[g0 + j] : 0.f;
+    const float tot = wave_reduce_multi<16>(vals, lane);
+    const int idx = g0 + reduce_index<16>(lane);
+    if (reduce_owner<16>(lane) && idx < NE) red[wv * ldr + col0 + idx] = double2{static_cast<double>(tot), 0.0};
+  }
+}
+
+template <typename R, int THREADS>
+__device__ __forceinline__ void eta_grad_dispatch(const R* Q, const R* PP, int own_lo, int Lw, int kap,
+                                                  double2* red, int ldr, int col0) {
+  if constexpr (sizeof(R) == 4) {
+    switch (kap) {
+#define LDBP_EG_CASE(k) \
+  case k: eta_grad_fixed<R, THREADS, k>(Q, PP, own_lo, Lw, red, ldr, col0); return;
+      LDBP_EG_CASE(1) LDBP_EG_CASE(2) LDBP_EG_CASE(3) LDBP_EG_CASE(4) LDBP_EG_CASE(5) LDBP_EG_CASE(6)
+      LDBP_EG_CASE(8) LDBP_EG_CASE(10) LDBP_EG_CASE(12) LDBP_EG_CASE(16) LDBP_EG_CASE(20)
+#undef LDBP_EG_CASE
+      default: break;
+    }
+  }
+  eta_grad<R>(Q, PP, own_lo, Lw, kap, red, ldr, col0, THREADS);
+}
+
 // FILT: the block's nonlinear steps filter the power (generalised ESSM, eta != NULL); a separate
 // instantiation keeps the plain LDBP kernel unchanged.
 template <typename R, int NPOL, int RB, int RB2, int THREADS, bool FILT>
@@ -511,28 +693,9 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
         PP[i] = pw;
       }
       __syncthreads();
-      const R* e = eta + pt.etaoff[s - 1];
-      for (int i = lo + kp + static_cast<int>(threadIdx.x); i < hi - kp; i += THREADS) {
-        R F = 0, r = 0;
-        for (int k = -kp; k <= kp; ++k) {
-          F = fma(e[kp + k], PP[i - k], F);
-          r = fma(e[kp + k], Q[i + k], r);
-        }
-        R sn, co;
-        phase_sincos(coef, F, sn, co);
-        const R tr = 2 * cr * r;
-#pragma unroll
-        for (int pp = 0; pp < NPOL; ++pp) {
-          const V yv = ycur[(i + yoff) * NPOL + pp];
-          const V gv = GA[i * NPOL + pp];
-          // G_y e^{-j phi} + 2 r u with u = y e^{-j phi}: (G_y + 2 r y) e^{-j phi}
-          const R tx = gv.x + tr * yv.x;
-          const R ty = gv.y + tr * yv.y;
-          GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
-        }
-        if (i >= H && i < H + Lw) accc += Q[i] * F;
-      }
-      eta_grad<R>(Q, PP, H, Lw, kp, red, ldr, ntap_blk + pt.etaoff[s - 1] - pt.etaoff[0], THREADS);
+      accc = nl_adjoint_dispatch<R, NPOL, THREADS>(ycur, yoff, GA, GB, Q, PP, lo, hi, kp, eta + pt.etaoff[s - 1], cr,
+                                                   coef, H, H + Lw);
+      eta_grad_dispatch<R, THREADS>(Q, PP, H, Lw, kp, red, ldr, ntap_blk + pt.etaoff[s - 1] - pt.etaoff[0]);
     } else {
       for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += THREADS) {
         V yv[NPOL], gv[NPOL];

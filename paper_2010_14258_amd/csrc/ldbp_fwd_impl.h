@@ -88,7 +88,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
 template <typename R, int NPOL, int RB>
 inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                              const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                             hipStream_t stream, const void* eta) {
+                             hipStream_t stream, const void* eta, int64_t slot_elems) {
   if (pt.ckpt_mask && (!ckpt || pt.ckpt_every < 1)) return fail(LDBP_EINVAL, "checkpoint writes without slots");
   const int work = chunks * RB * kFwdThreads;
   const int tile_len = work - 2 * pt.halo;
@@ -108,7 +108,8 @@ inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, i
   hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(nblocks)), dim3(kFwdThreads), lds, stream,
                      static_cast<const cx_t<R>*>(x), static_cast<cx_t<R>*>(y), n, tile_len,
                      static_cast<int32_t>(ntiles), work, static_cast<const cx_t<R>*>(taps),
-                     static_cast<const R*>(c), pt, sym, static_cast<cx_t<R>*>(ckpt), nwave * n * NPOL,
+                     static_cast<const R*>(c), pt, sym, static_cast<cx_t<R>*>(ckpt),
+                     slot_elems > 0 ? slot_elems : nwave * n * NPOL,
                      static_cast<const R*>(eta));
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;

@@ -32,19 +32,21 @@ int fwd_chunk(int dtype, int npol, int rb);
 // filtered: the pass also holds the power of the signal (a real per sample) for filtered steps.
 size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks, bool filtered = false);
 
-// ckpt: base of the checkpoint slots written inside the pass (pt.ckpt_mask), or NULL when the mask is 0.
+// ckpt: base of the checkpoint slots written inside the pass (pt.ckpt_mask), or NULL when the mask is 0;
+// wave w's state for slot j goes to ckpt + j * slot_elems + w * n * npol (slot_elems 0: nwave * n * npol,
+// a larger one when the launch covers a sub-range of a batch whose slots hold every waveform).
 // eta: packed real filters of the nonlinear steps (pt.kap / pt.etaoff), or NULL for plain Kerr steps.
 int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                     const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream,
-                    const void* eta = nullptr);
+                    const void* eta = nullptr, int64_t slot_elems = 0);
 
 // Instantiation groups of launch_fwd_pass (separate translation units).
 int launch_fwd_pass_c64p2(int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                           const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                          hipStream_t stream, const void* eta);
+                          hipStream_t stream, const void* eta, int64_t slot_elems);
 int launch_fwd_pass_c128(int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                          const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                         hipStream_t stream, const void* eta);
+                         hipStream_t stream, const void* eta, int64_t slot_elems);
 
 // Backward (adjoint) block kernel and the deterministic gradient reduction.
 // Partial-sum columns: [taps (ntaps)] [power filters (neta), ecol_base = ntaps] [c (l), ccol_base].

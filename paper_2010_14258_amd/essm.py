@@ -89,7 +89,7 @@ def essm_backward_workspace_size(x: torch.Tensor, ntap: Sequence[int], nl_ntap: 
 def essm_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, eta: torch.Tensor, ntap: Sequence[int],
                   nl_ntap: Sequence[int], gy: torch.Tensor, npol: int = 1, ckpt: Optional[torch.Tensor] = None,
                   ckpt_every: int = 0, need_gx: bool = True, symmetric: bool = False,
-                  ws: Optional[torch.Tensor] = None, stream=None):
+                  ws: Optional[torch.Tensor] = None, stream=None, one_stream: bool = False):
     """Adjoint of ``essm_forward``: returns (gx or None, gtaps, gc, geta) for dL/dy = gy.
 
     symmetric: the FIR taps satisfy h_{-k} = h_k (folded evaluation; gtaps projected on symmetric filters)."""
@@ -109,7 +109,8 @@ def essm_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, eta: tor
     if ws is None:
         ws = torch.empty(essm_backward_workspace_size(x, ntap, nl_ntap, npol, ckpt, ckpt_every), dtype=torch.uint8,
                          device=x.device)
-    pl = N.LdbpPlan(0, 0, 0, N.LDBP_PLAN_SYMMETRIC if symmetric else 0)
+    pl = N.LdbpPlan(0, 0, 0, (N.LDBP_PLAN_SYMMETRIC if symmetric else 0) |
+                    (N.LDBP_PLAN_ONE_STREAM if one_stream else 0))
     N.check(lib.essm_backward(code, npol, nwave, n, len(ntap), N.i32_array(ntap), N.i32_array(nl_ntap), _ptr(taps),
                               _ptr(c), _ptr(eta), _ptr(x), _ptr(ckpt), int(ckpt_every), _ptr(gy), _ptr(gx),
                               _ptr(gtaps), _ptr(gc), _ptr(geta), ctypes.byref(pl), _ptr(ws), ws.numel(),

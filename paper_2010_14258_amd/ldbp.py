@@ -48,14 +48,15 @@ def _check_dev(name: str, t: torch.Tensor, dtype=None):
 
 
 def _plan(plan) -> Optional[N.LdbpPlan]:
-    """None, an LdbpPlan, or a tuple (steps_per_pass, chunks[, outputs_per_thread[, symmetric]])."""
+    """None, an LdbpPlan, or a tuple (steps_per_pass, chunks[, outputs_per_thread[, symmetric[, one_stream]]])."""
     if plan is None:
         return None
     if isinstance(plan, N.LdbpPlan):
         return plan
-    vals = list(plan) + [0] * (4 - len(plan))
-    s, ch, rb, sym = vals[:4]
-    return N.LdbpPlan(int(s), int(ch), int(rb), N.LDBP_PLAN_SYMMETRIC if sym else 0)
+    vals = list(plan) + [0] * (5 - len(plan))
+    s, ch, rb, sym, one = vals[:5]
+    flags = (N.LDBP_PLAN_SYMMETRIC if sym else 0) | (N.LDBP_PLAN_ONE_STREAM if one else 0)
+    return N.LdbpPlan(int(s), int(ch), int(rb), flags)
 
 
 def _shape(x: torch.Tensor, npol: int):
@@ -134,11 +135,14 @@ def ldbp_backward_workspace_size(x: torch.Tensor, ntap: Sequence[int], npol: int
 
 def ldbp_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], gy: torch.Tensor,
                   npol: int = 1, ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0, need_gx: bool = True,
-                  symmetric: bool = False, ws: Optional[torch.Tensor] = None, stream=None):
+                  symmetric: bool = False, ws: Optional[torch.Tensor] = None, stream=None,
+                  one_stream: bool = False):
     """Adjoint of ``ldbp_forward``: returns (gx or None, gtaps, gc) for dL/dy = gy (G = dL/dRe + j dL/dIm).
 
     symmetric: the taps satisfy h_{-k} = h_k; the FIR products are evaluated folded and gtaps is the
-    gradient projected on symmetric filters ((dL/dh_k + dL/dh_{-k}) / 2 in both entries)."""
+    gradient projected on symmetric filters ((dL/dh_k + dL/dh_{-k}) / 2 in both entries).
+    one_stream: keep every launch on `stream` (by default the library may run half the batch on a
+    second stream of its own, forked from and joined back into `stream`)."""
     lib = N.load()
     code = _code(x)
     nwave, n = _shape(x, npol)
@@ -154,7 +158,8 @@ def ldbp_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Se
     if ws is None:
         need = ldbp_backward_workspace_size(x, ntap, npol, ckpt, ckpt_every)
         ws = torch.empty(need, dtype=torch.uint8, device=x.device)
-    pl = N.LdbpPlan(0, 0, 0, N.LDBP_PLAN_SYMMETRIC if symmetric else 0)
+    pl = N.LdbpPlan(0, 0, 0, (N.LDBP_PLAN_SYMMETRIC if symmetric else 0) |
+                    (N.LDBP_PLAN_ONE_STREAM if one_stream else 0))
     st = lib.ldbp_backward(code, npol, nwave, n, len(ntap), N.i32_array(ntap), _ptr(taps), _ptr(c), _ptr(x),
                            _ptr(ckpt), int(ckpt_every), _ptr(gy), _ptr(gx), _ptr(gtaps), _ptr(gc), ctypes.byref(pl),
                            _ptr(ws), ws.numel(), stream_handle(stream, x.device))

@@ -99,7 +99,7 @@ def _bwd(flags=0, x=1 << 20, gy=1 << 24, gx=None, ws=None, ws_bytes=0, ntap=(15,
 
 def test_backward_rejects_bad_arguments_before_any_gpu_work():
     # Fake (never dereferenced) addresses: every case fails validation on the host.
-    assert _bwd(flags=2) == N.LDBP_EINVAL                               # undefined plan flag
+    assert _bwd(flags=4) == N.LDBP_EINVAL                               # undefined plan flag
     assert _bwd(flags=N.LDBP_PLAN_SYMMETRIC) == N.LDBP_EWORKSPACE       # valid flag, missing workspace
     assert _bwd(ntap=(15, 4)) == N.LDBP_EINVAL                          # even length
     assert _bwd(x=(1 << 20) + 8) == N.LDBP_EINVAL                       # misaligned

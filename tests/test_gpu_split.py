@@ -1,0 +1,114 @@
+"""The batch split over a second stream: every result equals the one-stream result bit for bit.
+
+The multi-pass forward, the checkpointed forward and the backward run the second half of a large
+batch on a library-owned stream forked from and joined back into the caller's stream; the kernels and
+the per-waveform arithmetic are the same, and the backward's partial sums are reduced in the same
+order, so the outputs must be identical.  Sizes are above the split threshold (at least 512
+workgroups per launch); the half-batch boundary is odd-sized (ceil(nwave / 2) waveforms first).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2010_14258_amd import essm as GE  # noqa: E402
+from paper_2010_14258_amd import ldbp as G  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _model(seed, Ts, dtype, symmetric=True):
+    taps = synth.random_taps(seed, Ts)
+    taps = [h / np.linalg.norm(h) for h in taps]
+    if symmetric:
+        taps = [0.5 * (h + h[::-1]) for h in taps]
+    rd = torch.float32 if dtype == torch.complex64 else torch.float64
+    c = synth.random_real(seed + 1, len(Ts), -0.3, 0.3)
+    return (torch.from_numpy(np.concatenate(taps)).to(DEV, dtype), torch.from_numpy(c).to(DEV, rd),
+            [len(h) for h in taps])
+
+
+def _x(seed, shape, dtype):
+    return torch.from_numpy(synth.complex_normal(seed, shape) * 0.5).to(DEV, dtype)
+
+
+CASES = [(torch.complex64, 1, (5, 1 << 18)), (torch.complex64, 2, (3, 1 << 17, 2)),
+         (torch.complex128, 1, (3, 1 << 17))]
+
+
+@pytest.mark.parametrize("dtype,npol,shape", CASES)
+def test_forward_split_equals_one_stream(dtype, npol, shape):
+    print("case: split forward", dtype, npol, shape, flush=True)
+    Ts = [15, 9, 7, 11, 5, 13, 3, 9, 15, 7, 5, 11]
+    taps, c, ntap = _model(1, Ts, dtype)
+    x = _x(2, shape, dtype)
+    for plan in ((4, 0, 0, 1), (3, 0, 0, 0)):
+        a = G.ldbp_forward(x, taps, c, ntap, npol=npol, plan=plan)
+        b = G.ldbp_forward(x, taps, c, ntap, npol=npol, plan=plan + (1,))
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), plan
+    S = 2
+    ns = G.num_checkpoints(len(Ts), S)
+    cka = torch.empty((ns,) + shape, dtype=dtype, device=DEV)
+    ckb = torch.empty_like(cka)
+    a = G.ldbp_forward(x, taps, c, ntap, npol=npol, ckpt=cka, ckpt_every=S, plan=(4, 0, 0, 1))
+    b = G.ldbp_forward(x, taps, c, ntap, npol=npol, ckpt=ckb, ckpt_every=S, plan=(4, 0, 0, 1, 1))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(cka, ckb)
+
+
+BWD_CASES = [(torch.complex64, 1, (5, 1 << 19)), (torch.complex64, 2, (3, 1 << 20, 2)),
+             (torch.complex128, 1, (3, 1 << 20))]
+
+
+@pytest.mark.parametrize("dtype,npol,shape", BWD_CASES)
+def test_backward_split_equals_one_stream(dtype, npol, shape):
+    print("case: split backward", dtype, npol, shape, flush=True)
+    Ts = [15, 9, 7, 11, 5, 13, 3, 9]
+    taps, c, ntap = _model(3, Ts, dtype)
+    x = _x(4, shape, dtype)
+    gy = _x(5, shape, dtype)
+    S = 2
+    ck = torch.empty((G.num_checkpoints(len(Ts), S),) + shape, dtype=dtype, device=DEV)
+    G.ldbp_forward(x, taps, c, ntap, npol=npol, ckpt=ck, ckpt_every=S, plan=(0, 0, 0, 1, 1))
+    for kw in (dict(ckpt=ck, ckpt_every=S), dict()):
+        ra = G.ldbp_backward(x, taps, c, ntap, gy, npol=npol, symmetric=True, **kw)
+        rb = G.ldbp_backward(x, taps, c, ntap, gy, npol=npol, symmetric=True, one_stream=True, **kw)
+        torch.cuda.synchronize()
+        for u, v in zip(ra, rb):
+            assert torch.equal(u, v)
+
+
+def test_essm_split_equals_one_stream_on_a_side_torch_stream():
+    """Generalised ESSM forward and backward, called on a non-default torch stream."""
+    print("case: split essm", flush=True)
+    dtype, shape = torch.complex64, (4, 1 << 18)
+    Ts = [9, 7, 5, 11, 3, 9]
+    taps, c, ntap = _model(6, Ts, dtype)
+    g = synth.rng(7)
+    nl = [41, 1, 7, 21, 3, 41]
+    eta = torch.from_numpy(np.concatenate([g.uniform(-0.1, 0.1, e) + np.eye(1, e, e // 2)[0] for e in nl])).to(
+        DEV, torch.float32)
+    x = _x(8, shape, dtype)
+    gy = _x(9, shape, dtype)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        ya = GE.essm_forward(x, taps, c, eta, ntap, nl, plan=(2, 0, 0, 1), stream=st)
+        yb = GE.essm_forward(x, taps, c, eta, ntap, nl, plan=(2, 0, 0, 1, 1), stream=st)
+        ra = GE.essm_backward(x, taps, c, eta, ntap, nl, gy, symmetric=True, stream=st)
+        rb = GE.essm_backward(x, taps, c, eta, ntap, nl, gy, symmetric=True, one_stream=True, stream=st)
+    st.synchronize()
+    assert torch.equal(ya, yb)
+    for u, v in zip(ra, rb):
+        assert torch.equal(u, v)
+
+
+def test_unknown_plan_flags_are_rejected():
+    x = _x(10, (2, 1000), torch.complex64)
+    taps, c, ntap = _model(11, [5, 3], torch.complex64)
+    from paper_2010_14258_amd import _native as N
+    with pytest.raises(N.LdbpError):
+        G.ldbp_forward(x, taps, c, ntap, plan=N.LdbpPlan(0, 0, 0, 4))
