@@ -218,6 +218,38 @@ int essm_backward(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t
                   size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Aperiodic (streaming) forward: the model of ldbp_forward (nl_ntap == NULL) or essm_forward applied
+ * to a signal that is not periodic.  The circular FIR of Sec. III-B describes one periodic block;
+ * continuous data is processed in blocks with overlap-and-save (Sec. III-A, choice of the block
+ * length n).  Here every FIR step is a full linear convolution: the signal is zero before its first
+ * and after its last input sample at the input and spreads into those margins by K_i per step.  With
+ * P = sum_i (K_i + kappa_i) (kappa_i = (nl_ntap[i] - 1) / 2, 0 for LDBP steps) every output depends
+ * only on the inputs within P samples of it.
+ *   edge   LDBP_EDGE_ZERO: y [nwave][n][npol] holds that model's output at the n input positions.
+ *          LDBP_EDGE_VALID: y [nwave][n - 2P][npol] holds the outputs at input positions P .. n-P-1,
+ *          the ones that x determines whatever lies outside it: consecutive chunks of a long
+ *          stream, each passed with the P stream samples before and after it, give exactly the
+ *          stream's outputs (overlap-save).  n <= 2P: LDBP_EINVAL.
+ *   (dtype .. c) as for ldbp_forward; nl_ntap, eta as for essm_forward, or NULL for LDBP steps.
+ *   x      device [nwave][n][npol] complex input
+ *   plan   as for ldbp_forward (steps_per_pass, chunks, outputs_per_thread, flags)
+ *   ws     device workspace of ldbp_forward_aperiodic_workspace_size() bytes (may be 0); the
+ *          passes run on n + 2P working samples per waveform (LDBP_EDGE_ZERO) or n (VALID)
+ * Results are bit-identical to those of ldbp_forward / essm_forward with the same plan on x padded
+ * with P zeros at each end (LDBP_EDGE_ZERO) or on x itself (LDBP_EDGE_VALID), at the output positions.
+ * -------------------------------------------------------------------------*/
+#define LDBP_EDGE_ZERO 1
+#define LDBP_EDGE_VALID 2
+int ldbp_forward_aperiodic_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                          const int32_t* ntap, const int32_t* nl_ntap, int32_t edge,
+                                          const ldbp_plan* plan, size_t* bytes);
+
+int ldbp_forward_aperiodic(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                           const int32_t* ntap, const int32_t* nl_ntap, const void* taps, const void* c,
+                           const void* eta, const void* x, void* y, int32_t edge, const ldbp_plan* plan,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Batched LDBP inference over uneven waveforms (eq. model for each waveform of the batch).
  * Waveform b has wave_len[b] samples, wave_nstep[b] steps with tap counts
  * step_ntap[sum_{j<b} wave_nstep[j] + s], its own taps and Kerr coefficients.  Packed layouts:

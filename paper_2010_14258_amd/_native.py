@@ -34,6 +34,8 @@ class LdbpPlan(ctypes.Structure):
 
 LDBP_PLAN_SYMMETRIC = 1
 LDBP_PLAN_ONE_STREAM = 2
+LDBP_EDGE_ZERO = 1
+LDBP_EDGE_VALID = 2
 
 
 P_plan = ctypes.POINTER(LdbpPlan)
@@ -64,6 +66,11 @@ SIGNATURES = {
     "essm_forward": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p, c_int32, P_plan, c_void_p, c_size_t,
                                c_void_p]),
+    "ldbp_forward_aperiodic_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32,
+                                                        c_int32, P_plan, P_size]),
+    "ldbp_forward_aperiodic": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32, c_void_p,
+                                         c_void_p, c_void_p, c_void_p, c_void_p, c_int32, P_plan, c_void_p, c_size_t,
+                                         c_void_p]),
     "essm_forward_plan_query": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32, c_int32,
                                           P_plan, P_i32, P_i32, P_i32]),
     "essm_backward_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32,

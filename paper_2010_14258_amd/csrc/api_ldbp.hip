@@ -10,6 +10,8 @@ namespace ldbp {
 
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
+static size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
 struct ModelArgs {
   int32_t dtype, npol;
   int64_t nwave, n;
@@ -360,6 +362,112 @@ static int forward_impl(const ModelArgs& m, const void* taps, const void* c, con
                      });
 }
 
+// Aperiodic forward: the passes of the periodic forward on a working circle of nw samples per
+// waveform (n + 2P with zero margins, or n for VALID), the first pass reading x through an EdgeMap
+// and the last one storing only the nout output positions.  P = sum (K_i + kappa_i) bounds the
+// dependence of an output, so no value that reaches a stored output ever wraps around the circle.
+struct AperGeom {
+  int64_t P, nw, nout;
+  size_t buf_bytes;  // one intermediate buffer (nwave working waveforms)
+  int nbuf;          // intermediate buffers: 0 (one pass), 1 (two) or 2 (ping-pong)
+};
+
+static int aperiodic_geom(const ModelArgs& m, int32_t edge, const ldbp_plan* plan, PassPlan& pp, AperGeom& g) {
+  if (edge != LDBP_EDGE_ZERO && edge != LDBP_EDGE_VALID)
+    return fail(LDBP_EINVAL, "edge %d is not LDBP_EDGE_ZERO/LDBP_EDGE_VALID", edge);
+  g.P = 0;
+  for (int i = 0; i < m.nstep; ++i) g.P += (m.ntap[i] - 1) / 2 + m.kap(i);
+  if (edge == LDBP_EDGE_VALID) {
+    if (m.n <= 2 * g.P)
+      return fail(LDBP_EINVAL, "n = %lld leaves no valid output (2P = %lld)", (long long)m.n, (long long)(2 * g.P));
+    g.nw = m.n;
+    g.nout = m.n - 2 * g.P;
+  } else {
+    g.nw = m.n + 2 * g.P;
+    g.nout = m.n;
+    if (g.nw > (1LL << 30)) return fail(LDBP_EUNSUPPORTED, "n + 2P = %lld exceeds 2^30", (long long)g.nw);
+  }
+  ModelArgs mw = m;
+  mw.n = g.nw;
+  const int st = make_plan(mw, 0, plan, pp);
+  if (st) return st;
+  const size_t np = pp.passes.size();
+  g.nbuf = np >= 3 ? 2 : (np == 2 ? 1 : 0);
+  g.buf_bytes = align256(static_cast<size_t>(m.nwave) * g.nw * m.npol * cx_size(m.dtype));
+  return LDBP_OK;
+}
+
+static int aperiodic_ws_impl(const ModelArgs& m, int32_t edge, const ldbp_plan* plan, size_t* bytes) {
+  if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
+  int st = check_model(m);
+  if (st) return st;
+  PassPlan pp;
+  AperGeom g;
+  st = aperiodic_geom(m, edge, plan, pp, g);
+  if (st) return st;
+  *bytes = g.nbuf * g.buf_bytes;
+  return LDBP_OK;
+}
+
+static int aperiodic_impl(const ModelArgs& m, const void* taps, const void* c, const void* eta, const void* x,
+                          void* y, int32_t edge, const ldbp_plan* plan, void* ws, size_t ws_bytes, void* stream) {
+  int st = check_model(m);
+  if (st) return st;
+  if (!taps || !c || !x || !y) return fail(LDBP_EINVAL, "taps, c, x and y must be non-NULL");
+  if (m.filtered() && !eta) return fail(LDBP_EINVAL, "eta must be non-NULL");
+  if (!aligned16(taps) || !aligned16(x) || !aligned16(y)) return fail(LDBP_EINVAL, "taps, x and y must be 16-byte aligned");
+  if (reinterpret_cast<uintptr_t>(c) % real_size(m.dtype)) return fail(LDBP_EINVAL, "c is not aligned to its real type");
+  if (eta && reinterpret_cast<uintptr_t>(eta) % real_size(m.dtype))
+    return fail(LDBP_EINVAL, "eta is not aligned to its real type");
+  if (plan && (plan->flags & ~(LDBP_PLAN_SYMMETRIC | LDBP_PLAN_ONE_STREAM)))
+    return fail(LDBP_EINVAL, "plan flags 0x%x: unknown bits", plan->flags);
+  PassPlan pp;
+  AperGeom g;
+  st = aperiodic_geom(m, edge, plan, pp, g);
+  if (st) return st;
+  const size_t sample_bytes = static_cast<size_t>(m.npol) * cx_size(m.dtype);
+  const size_t x_bytes = static_cast<size_t>(m.nwave) * m.n * sample_bytes;
+  const size_t y_bytes = static_cast<size_t>(m.nwave) * g.nout * sample_bytes;
+  if (overlaps(x, x_bytes, y, y_bytes)) return fail(LDBP_EINVAL, "x and y overlap");
+  const size_t need = g.nbuf * g.buf_bytes;
+  if (need > 0) {
+    if (!ws || ws_bytes < need)
+      return fail(LDBP_EWORKSPACE, "workspace of %zu bytes required, %zu given", need, ws ? ws_bytes : 0);
+    if (!aligned16(ws)) return fail(LDBP_EINVAL, "ws must be 16-byte aligned");
+    if (overlaps(ws, need, x, x_bytes) || overlaps(ws, need, y, y_bytes))
+      return fail(LDBP_EINVAL, "workspace overlaps x or y");
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* e = m.filtered() ? eta : nullptr;
+  const size_t np = pp.passes.size();
+  ModelArgs mw = m;
+  mw.n = g.nw;
+  const int32_t nw = static_cast<int32_t>(g.nw);
+  return over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(mw, pp)),
+                     [&](int64_t w0, int64_t w1, hipStream_t ss) {
+                       const char* in = static_cast<const char*>(x) + w0 * m.n * sample_bytes;
+                       for (size_t i = 0; i < np; ++i) {
+                         const bool first = i == 0, last = i + 1 == np;
+                         EdgeMap em{0, nw, 0, nw};
+                         if (first) em.in_len = static_cast<int32_t>(m.n);
+                         if (first && edge == LDBP_EDGE_ZERO) em.in_off = static_cast<int32_t>(g.P);
+                         if (last) {
+                           em.out_off = static_cast<int32_t>(g.P);
+                           em.out_len = static_cast<int32_t>(g.nout);
+                         }
+                         const bool use_em = last || (first && edge == LDBP_EDGE_ZERO);
+                         char* out = last ? static_cast<char*>(y) + w0 * g.nout * sample_bytes
+                                          : static_cast<char*>(ws) + (i % 2) * g.buf_bytes + w0 * g.nw * sample_bytes;
+                         const int r = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0, nw, pp.chunks,
+                                                       pp.passes[i], taps, c, pp.sym, nullptr, ss, e, 0,
+                                                       use_em ? &em : nullptr);
+                         if (r) return r;
+                         in = out;
+                       }
+                       return static_cast<int>(LDBP_OK);
+                     });
+}
+
 static int plan_query_impl(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* plan, int32_t* npasses,
                            int32_t* tile_len, int32_t* max_steps_per_pass) {
   int st = check_model(m);
@@ -443,7 +551,6 @@ static size_t bwd_lds_budget(bool filtered) {
   return filtered ? kBwdLdsBudgetFiltered : kBwdLdsBudget;
 }
 
-static size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 struct BwdLayout {
   PassPlan blocks;   // checkpoint blocks (passes of exactly S steps)
@@ -637,4 +744,18 @@ extern "C" int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwav
                                        int32_t* npasses, int32_t* tile_len, int32_t* max_steps_per_pass) {
   return plan_query_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap}, ckpt_every, plan, npasses, tile_len,
                          max_steps_per_pass);
+}
+
+extern "C" int ldbp_forward_aperiodic_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
+                                                     int32_t nstep, const int32_t* ntap, const int32_t* nl_ntap,
+                                                     int32_t edge, const ldbp_plan* plan, size_t* bytes) {
+  return aperiodic_ws_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap, nl_ntap}, edge, plan, bytes);
+}
+
+extern "C" int ldbp_forward_aperiodic(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                      const int32_t* ntap, const int32_t* nl_ntap, const void* taps, const void* c,
+                                      const void* eta, const void* x, void* y, int32_t edge, const ldbp_plan* plan,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  return aperiodic_impl(ModelArgs{dtype, npol, nwave, n, nstep, ntap, nl_ntap}, taps, c, eta, x, y, edge, plan, ws,
+                        ws_bytes, stream);
 }

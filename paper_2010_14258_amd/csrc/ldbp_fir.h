@@ -266,4 +266,43 @@ __device__ __forceinline__ void load_tile(const cx_t<R>* __restrict__ xw, cx_t<R
   }
 }
 
+// load_tile for a pass input given only on part of the circle of n samples: sample g of the pass
+// input is xw[g - in_off] for 0 <= g - in_off < in_len and zero elsewhere (the zero margins of an
+// aperiodic signal).  Out-of-range lanes load a clamped in-range sample and store zero, so every
+// global load stays inside the in_len samples of the waveform.
+template <typename R, int NPOL, int THREADS>
+__device__ __forceinline__ void load_tile_edge(const cx_t<R>* __restrict__ xw, cx_t<R>* __restrict__ buf, int n,
+                                               int t0, int H, int W0, int wrap_general, int in_off, int in_len) {
+  using V = cx_t<R>;
+  constexpr int kLoadBatch = 64 / static_cast<int>(sizeof(V) * NPOL);
+  for (int j0 = threadIdx.x; j0 < W0; j0 += kLoadBatch * THREADS) {
+    V v[kLoadBatch][NPOL];
+    bool ok[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int j = min(j0 + u * THREADS, W0 - 1);
+      int g = t0 - H + j;
+      if (wrap_general) {
+        g %= n;
+        if (g < 0) g += n;
+      } else {
+        if (g < 0) g += n;
+        else if (g >= n) g -= n;
+      }
+      const int src = g - in_off;
+      ok[u] = src >= 0 && src < in_len;
+      const int sc = min(max(src, 0), in_len - 1);
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) v[u][p] = xw[static_cast<int64_t>(sc) * NPOL + p];
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int j = j0 + u * THREADS;
+      if (j < W0)
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) buf[j * NPOL + p] = ok[u] ? v[u][p] : V{0, 0};
+    }
+  }
+}
+
 }  // namespace ldbp

@@ -21,15 +21,16 @@ namespace ldbp {
 constexpr int kFwdThreads = 256;
 
 
-// FILT: the steps are filtered nonlinear steps (eta != NULL); CKPT: the pass writes inner checkpoints.
+// FILT: the steps are filtered nonlinear steps (eta != NULL); CKPT: the pass writes inner checkpoints;
+// EDGE: the pass input and output follow an EdgeMap (aperiodic forward: zero margins, cropped output).
 // Separate instantiations keep the plain LDBP kernel's registers (and occupancy) unchanged.
-template <typename R, int NPOL, int RB, int THREADS, bool FILT, bool CKPT>
+template <typename R, int NPOL, int RB, int THREADS, bool FILT, bool CKPT, bool EDGE = false>
 __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __restrict__ x, cx_t<R>* __restrict__ y,
                                                            int32_t n, int32_t tile_len, int32_t ntiles,
                                                            int32_t work, const cx_t<R>* __restrict__ taps,
                                                            const R* __restrict__ c, PassTable pt, int32_t sym,
                                                            cx_t<R>* __restrict__ ckpt, int64_t slot_elems,
-                                                           const R* __restrict__ eta) {
+                                                           const R* __restrict__ eta, EdgeMap em) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   V* b0 = reinterpret_cast<V*>(smem);
@@ -42,10 +43,13 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
   const int Lw = min(tile_len, n - t0);
   const int H = pt.halo;
   const int W0 = Lw + 2 * H;
-  const V* xw = x + wave * static_cast<int64_t>(n) * NPOL;
-  V* yw = y + wave * static_cast<int64_t>(n) * NPOL;
+  const V* xw = x + wave * static_cast<int64_t>(EDGE ? em.in_len : n) * NPOL;
+  V* yw = y + wave * static_cast<int64_t>(EDGE ? em.out_len : n) * NPOL;
+  // a tile whose samples are all cropped from the output has nothing to do
+  if (EDGE && (t0 + Lw <= em.out_off || t0 >= em.out_off + em.out_len)) return;
 
-  load_tile<R, NPOL, THREADS>(xw, b0, n, t0, H, W0, pt.wrap_general);
+  if constexpr (EDGE) load_tile_edge<R, NPOL, THREADS>(xw, b0, n, t0, H, W0, pt.wrap_general, em.in_off, em.in_len);
+  else load_tile<R, NPOL, THREADS>(xw, b0, n, t0, H, W0, pt.wrap_general);
   __syncthreads();
 
   int lo = 0;
@@ -80,16 +84,22 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
   }
 
   for (int j = threadIdx.x; j < Lw; j += THREADS) {
+    int o = t0 + j;
+    if constexpr (EDGE) {
+      o -= em.out_off;
+      if (o < 0 || o >= em.out_len) continue;
+    }
 #pragma unroll
-    for (int p = 0; p < NPOL; ++p) yw[static_cast<int64_t>(t0 + j) * NPOL + p] = b0[(H + j) * NPOL + p];
+    for (int p = 0; p < NPOL; ++p) yw[static_cast<int64_t>(o) * NPOL + p] = b0[(H + j) * NPOL + p];
   }
 }
 
 template <typename R, int NPOL, int RB>
 inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                              const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                             hipStream_t stream, const void* eta, int64_t slot_elems) {
+                             hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em) {
   if (pt.ckpt_mask && (!ckpt || pt.ckpt_every < 1)) return fail(LDBP_EINVAL, "checkpoint writes without slots");
+  if (em && pt.ckpt_mask) return fail(LDBP_EINVAL, "an aperiodic pass writes no checkpoints");
   const int work = chunks * RB * kFwdThreads;
   const int tile_len = work - 2 * pt.halo;
   if (tile_len < 1) return fail(LDBP_EINVAL, "pass halo %d too large for work size %d", pt.halo, work);
@@ -98,10 +108,12 @@ inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, i
   if (nblocks > 0x7fffffffLL) return fail(LDBP_EUNSUPPORTED, "grid too large (%lld blocks)", (long long)nblocks);
   const size_t lds = 2 * static_cast<size_t>(work + RB) * NPOL * sizeof(cx_t<R>) +
                      (eta ? static_cast<size_t>(work + RB) * sizeof(R) : 0);
-  auto kern = eta ? (pt.ckpt_mask ? ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, true, true>
-                                  : ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, true, false>)
-                  : (pt.ckpt_mask ? ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, false, true>
-                                  : ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, false, false>);
+  auto kern = em ? (eta ? ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, true, false, true>
+                        : ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, false, false, true>)
+           : eta ? (pt.ckpt_mask ? ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, true, true>
+                                 : ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, true, false>)
+                 : (pt.ckpt_mask ? ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, false, true>
+                                 : ldbp_fwd_kernel<R, NPOL, RB, kFwdThreads, false, false>);
   if (lds > 65536) LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
                                                       static_cast<int>(lds)));
@@ -110,7 +122,7 @@ inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, i
                      static_cast<int32_t>(ntiles), work, static_cast<const cx_t<R>*>(taps),
                      static_cast<const R*>(c), pt, sym, static_cast<cx_t<R>*>(ckpt),
                      slot_elems > 0 ? slot_elems : nwave * n * NPOL,
-                     static_cast<const R*>(eta));
+                     static_cast<const R*>(eta), em ? *em : EdgeMap{0, n, 0, n});
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }

@@ -25,6 +25,14 @@ struct PassTable {
   int32_t etaoff[LDBP_MAX_STEPS_PER_PASS];  // offsets into the packed filters
 };
 
+// Pass input and output of an aperiodic forward (ldbp_forward_aperiodic): on the circle of n working
+// samples the pass input is x[g - in_off] for 0 <= g - in_off < in_len (zero elsewhere; the
+// waveform stride of x is in_len), and sample g of the result is stored to y[g - out_off] for
+// 0 <= g - out_off < out_len (waveform stride out_len).
+struct EdgeMap {
+  int32_t in_off, in_len, out_off, out_len;
+};
+
 // Forward pass kernel geometry: rb = outputs per thread, chunk = 256 * rb samples.
 int fwd_rb_default(int dtype, int npol);
 bool fwd_rb_supported(int dtype, int npol, int rb);
@@ -36,17 +44,18 @@ size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks, bool filtered = fa
 // wave w's state for slot j goes to ckpt + j * slot_elems + w * n * npol (slot_elems 0: nwave * n * npol,
 // a larger one when the launch covers a sub-range of a batch whose slots hold every waveform).
 // eta: packed real filters of the nonlinear steps (pt.kap / pt.etaoff), or NULL for plain Kerr steps.
+// em: NULL, or the aperiodic input/output map of this pass (no checkpoint writes with it).
 int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                     const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream,
-                    const void* eta = nullptr, int64_t slot_elems = 0);
+                    const void* eta = nullptr, int64_t slot_elems = 0, const EdgeMap* em = nullptr);
 
 // Instantiation groups of launch_fwd_pass (separate translation units).
 int launch_fwd_pass_c64p2(int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                           const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                          hipStream_t stream, const void* eta, int64_t slot_elems);
+                          hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em);
 int launch_fwd_pass_c128(int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                          const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                         hipStream_t stream, const void* eta, int64_t slot_elems);
+                         hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em);
 
 // Backward (adjoint) block kernel and the deterministic gradient reduction.
 // Partial-sum columns: [taps (ntaps)] [power filters (neta), ecol_base = ntaps] [c (l), ccol_base].
