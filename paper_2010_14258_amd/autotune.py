@@ -3,7 +3,7 @@
 For a problem signature (device, dtype, npol, nwave, n, tap profile, symmetric) it times every
 plan in a candidate set -- outputs per thread x steps per pass x LDS chunks -- with HIP events on
 the caller's stream and keeps the plan with the fewest steps per pass among those within 2% of the
-fastest.  Results are cached in memory and, when a path is
+fastest (each candidate timed as the least of three runs of back-to-back calls).  Results are cached in memory and, when a path is
 given (argument or LDBP_AUTOTUNE_CACHE), in a JSON file; a missing or unreadable cache file just
 means tuning again.  All candidates produce identical results for a fixed outputs-per-thread
 and symmetry flag; across those the results agree to rounding.
@@ -81,16 +81,21 @@ def pick(table, within: float = 0.02):
     return min(ok, key=lambda t: (t[0][0], t[0][1], t[1]))
 
 
-def _time(fn, stream, reps: int) -> float:
+def _time(fn, stream, reps: int, repeats: int = 3) -> float:
+    """Mean time of `reps` back-to-back calls, the least of `repeats` such runs (robust to clock and
+    scheduling noise, which only ever add time)."""
     fn()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        fn()
-    e1.record(stream)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps
+    best = float("inf")
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / reps)
+    return best
 
 
 def tune_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], npol: int = 1,
