@@ -346,6 +346,14 @@ int tx_shape_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
 int tx_shape(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho, double rs, double rolloff,
              const int32_t* sym_idx, const double* p_watt, void* x, void* ws, size_t ws_bytes, void* stream);
 
+/* The same transmitter for symbols given as values (e.g. the i.i.d. circularly-symmetric Gaussian
+ * symbols of the paper's simulations, Sec. IV-A and Table I, drawn with ldbp_randn):
+ *   sym device [nwave][nsym][npol] complex of the dtype, read only (unit mean energy gives mean
+ *   power P); workspace as tx_shape_workspace_size.  Other arguments and errors as tx_shape. */
+int tx_shape_symbols(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho, double rs,
+                     double rolloff, const void* sym, const double* p_watt, void* x, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* Receiver front end (Sec. IV-A): ideal brick-wall low-pass of two-sided bandwidth equal to the new
  * sampling rate and resampling from n_in to n_out samples per frame (DFT bins |f| < f_out / 2 kept,
  * Nyquist bin zeroed, sample values of in-band signals preserved).  y [nwave][n_in][npol] ->

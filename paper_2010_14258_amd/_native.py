@@ -100,6 +100,8 @@ SIGNATURES = {
     "tx_shape_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_size]),
     "tx_shape": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, c_double, c_double, c_void_p, c_void_p,
                            c_void_p, c_void_p, c_size_t, c_void_p]),
+    "tx_shape_symbols": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, c_double, c_double, c_void_p,
+                                   c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "rx_lpf_decimate_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int64, P_size]),
     "rx_lpf_decimate": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int64, c_void_p, c_void_p, c_void_p,
                                   c_size_t, c_void_p]),

@@ -76,6 +76,22 @@ extern "C" int tx_shape(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym
   return tx_run(dtype, nwave, nsym, npol, rho, rs, rolloff, sym_idx, p_watt, x, ws, static_cast<hipStream_t>(stream));
 }
 
+extern "C" int tx_shape_symbols(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho, double rs,
+                                double rolloff, const void* sym, const double* p_watt, void* x, void* ws,
+                                size_t ws_bytes, void* stream) {
+  size_t need;
+  int st = tx_shape_workspace_size(dtype, npol, nwave, nsym, rho, &need);
+  if (st) return st;
+  if (!(rs > 0) || !(rolloff > 0 && rolloff <= 1)) return fail(LDBP_EINVAL, "need rs > 0 and 0 < rolloff <= 1");
+  if (!sym || !aligned16(sym) || !p_watt || !x || !aligned16(x))
+    return fail(LDBP_EINVAL, "sym, p_watt and x must be valid (sym and x 16-byte aligned)");
+  if ((st = check_ws(ws, ws_bytes, need))) return st;
+  const size_t sb = static_cast<size_t>(nwave) * nsym * npol * cx_size(dtype);
+  if (overlaps(sym, sb, ws, need)) return fail(LDBP_EINVAL, "sym overlaps the workspace");
+  return tx_run(dtype, nwave, nsym, npol, rho, rs, rolloff, nullptr, p_watt, x, ws, static_cast<hipStream_t>(stream),
+                sym);
+}
+
 extern "C" int rx_lpf_decimate_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n_in,
                                               int64_t n_out, size_t* bytes) {
   if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");

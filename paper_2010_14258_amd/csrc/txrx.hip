@@ -377,9 +377,10 @@ __global__ void mf_unfold(const cx_t<R>* __restrict__ Gs, cx_t<R>* __restrict__ 
 
 static uint32_t blocks_for(int64_t count) { return static_cast<uint32_t>((count + kT - 1) / kT); }
 
+// Symbols from 16-QAM indices (idx) or given directly (sym, complex [nwave][nsym][npol]; idx NULL).
 template <typename R>
 int tx_run_t(int64_t nwave, int64_t nsym, int npol, int rho, double rs, double beta, const int32_t* idx,
-             const double* p, void* x, char* ws, hipStream_t s) {
+             const double* p, void* x, char* ws, hipStream_t s, const void* sym) {
   using V = cx_t<R>;
   const int dtype = sizeof(R) == 4 ? LDBP_C64 : LDBP_C128;
   const int64_t n = nsym * rho;
@@ -389,9 +390,14 @@ int tx_run_t(int64_t nwave, int64_t nsym, int npol, int rho, double rs, double b
   const size_t xb = (static_cast<size_t>(nwave) * n * npol * sizeof(V) + 255) & ~size_t(255);
   char* fws = ws + sb + xb;
   const int64_t cs = nwave * nsym * npol;
-  hipLaunchKernelGGL(qam16_map<R>, dim3(blocks_for(cs)), dim3(kT), 0, s, idx, S, cs);
-  LDBP_HIP_CHECK(hipGetLastError());
-  int st = fft_run(dtype, nwave, nsym, npol, S, S, 0, fws, s);
+  const V* src = S;
+  if (sym) {
+    src = static_cast<const V*>(sym);
+  } else {
+    hipLaunchKernelGGL(qam16_map<R>, dim3(blocks_for(cs)), dim3(kT), 0, s, idx, S, cs);
+    LDBP_HIP_CHECK(hipGetLastError());
+  }
+  int st = fft_run(dtype, nwave, nsym, npol, src, S, 0, fws, s);
   if (st) return st;
   const int64_t cx = nwave * n * npol;
   hipLaunchKernelGGL(tx_spectrum<R>, dim3(blocks_for(cx)), dim3(kT), 0, s, S, X, nwave, nsym, n, npol,
@@ -408,9 +414,10 @@ size_t tx_ws_bytes(int dtype, int64_t nwave, int64_t nsym, int npol, int rho) {
 }
 
 int tx_run(int dtype, int64_t nwave, int64_t nsym, int npol, int rho, double rs, double beta, const int32_t* idx,
-           const double* p, void* x, void* ws, hipStream_t s) {
-  return dtype == LDBP_C64 ? tx_run_t<float>(nwave, nsym, npol, rho, rs, beta, idx, p, x, static_cast<char*>(ws), s)
-                           : tx_run_t<double>(nwave, nsym, npol, rho, rs, beta, idx, p, x, static_cast<char*>(ws), s);
+           const double* p, void* x, void* ws, hipStream_t s, const void* sym) {
+  return dtype == LDBP_C64
+             ? tx_run_t<float>(nwave, nsym, npol, rho, rs, beta, idx, p, x, static_cast<char*>(ws), s, sym)
+             : tx_run_t<double>(nwave, nsym, npol, rho, rs, beta, idx, p, x, static_cast<char*>(ws), s, sym);
 }
 
 size_t lpf_ws_bytes(int dtype, int64_t nwave, int64_t nin, int64_t nout, int npol) {

@@ -15,8 +15,9 @@ int fft_run(int dtype, int64_t nwave, int64_t n, int npol, const void* x, void* 
             hipStream_t s);
 
 size_t tx_ws_bytes(int dtype, int64_t nwave, int64_t nsym, int npol, int rho);
+// idx: 16-QAM indices, or NULL with sym: the complex symbols themselves.
 int tx_run(int dtype, int64_t nwave, int64_t nsym, int npol, int rho, double rs, double beta, const int32_t* idx,
-           const double* p, void* x, void* ws, hipStream_t s);
+           const double* p, void* x, void* ws, hipStream_t s, const void* sym = nullptr);
 size_t lpf_ws_bytes(int dtype, int64_t nwave, int64_t nin, int64_t nout, int npol);
 int lpf_run(int dtype, int64_t nwave, int64_t nin, int64_t nout, int npol, const void* y, void* r, void* ws,
             hipStream_t s);

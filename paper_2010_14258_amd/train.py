@@ -7,7 +7,10 @@ hand-written adjoints (receiver, then LDBP) and an Adam step on the taps and Ker
 The training power of each waveform is drawn uniformly from a power set (Sec. IV-B).
 
 Progressive pruning (Sec. IV-C): filters start with ``t_init`` taps and lose their outermost
-symmetric pair at scheduled iterations until they have ``t_final``.  Events go round-robin over
+symmetric pair at scheduled iterations until they have ``t_final`` (or, with ``t_final_alt``, until
+even-numbered layers have ``t_final`` and odd-numbered ones ``t_final_alt``, the alternating 5/3-tap
+model of Sec. V-A).  Symbols are 16-QAM or, with ``symbols = "gauss"``, the i.i.d. circularly-symmetric
+Gaussian symbols of the paper's simulations (Table I).  Events go round-robin over
 the layers; event e of E fires at iteration floor(prune_frac * iters * (e/E)^2), so more taps go
 early.  A pruned pair is removed from the packed filters (equivalent to a zero mask on it) so the
 kernels stop paying for it.
@@ -70,6 +73,8 @@ class TrainConfig:
     train_taps: bool = True
     essm_kappa: int = -1              # >= 0: filtered nonlinear steps with 2 kappa + 1 real taps
     essm_shared: bool = False         # one filter in every nonlinear step (conventional ESSM)
+    symbols: str = "qam16"            # "qam16", or "gauss": i.i.d. circularly-symmetric Gaussian symbols
+    t_final_alt: int = 0              # > 0: odd-numbered layers prune to this length instead of t_final
 
 
 def pruning_plan(t_init: Sequence[int], t_final: Sequence[int], iters: int, frac: float):
@@ -129,8 +134,10 @@ class Trainer:
             self.v_e = torch.zeros_like(self.eta)
         self.t = 0
         self.it = 0
-        self.plan = pruning_plan(self.ntap, [cfg.t_final] * len(self.ntap), cfg.iters, cfg.prune_frac) \
-            if cfg.t_final < cfg.t_init else []
+        targets = [cfg.t_final if (i % 2 == 0 or cfg.t_final_alt <= 0) else cfg.t_final_alt
+                   for i in range(len(self.ntap))]
+        self.plan = pruning_plan(self.ntap, targets, cfg.iters, cfg.prune_frac) \
+            if any(t < cfg.t_init for t in targets) else []
         self.events_done = 0
         self._mirror = None
         self.history: List[dict] = []
@@ -146,13 +153,18 @@ class Trainer:
         cfg = self.cfg
         p = self.powers(it) if p_watt is None else p_watt
         shape = (cfg.nwave, cfg.nsym) if cfg.npol == 1 else (cfg.nwave, cfg.nsym, 2)
-        words = TX.randbits(int(np.prod(shape)), cfg.seed, 2 * it, device=self.dev).view(shape)
-        x = TX.tx_shape(words, p, cfg.rho_a, cfg.rs, cfg.rolloff, npol=cfg.npol, dtype=self.cdt)
+        if cfg.symbols == "gauss":
+            s = TX.randn(shape, cfg.seed, 2 * it, dtype=self.cdt, device=self.dev)
+            x = TX.tx_shape_symbols(s, p, cfg.rho_a, cfg.rs, cfg.rolloff, npol=cfg.npol)
+        else:
+            words = TX.randbits(int(np.prod(shape)), cfg.seed, 2 * it, device=self.dev).view(shape)
+            x = TX.tx_shape(words, p, cfg.rho_a, cfg.rs, cfg.rolloff, npol=cfg.npol, dtype=self.cdt)
         noise = TX.randn((cfg.nspan,) + tuple(x.shape), cfg.seed, 2 * it + 1, dtype=self.cdt, device=self.dev)
         y = SS.ssm_channel(x, self.channel, noise=noise, npol=cfg.npol, y=x)
         del noise
         r = TX.rx_lpf_decimate(y, self.n_d, npol=cfg.npol)
-        s = TX.qam16_symbols(words, dtype=self.cdt)
+        if cfg.symbols != "gauss":
+            s = TX.qam16_symbols(words, dtype=self.cdt)
         return r, s, p
 
     # ------------------------------------------------------------------ model

@@ -60,6 +60,22 @@ def rx_lpf_decimate(y: torch.Tensor, n_out: int, npol: int = 1, stream=None) -> 
     return r
 
 
+def tx_shape_symbols(sym: torch.Tensor, p_watt: torch.Tensor, rho: int, rs: float, rolloff: float = 0.1,
+                     npol: int = 1, stream=None) -> torch.Tensor:
+    """RRC-shaped periodic waveform [nwave, rho*nsym(, 2)] from complex symbols [nwave, nsym(, 2)]."""
+    lib = N.load()
+    _check_dev("sym", sym)
+    _check_dev("p_watt", p_watt, torch.float64)
+    code = _code(sym)
+    nwave, nsym = sym.shape[0], sym.shape[1]
+    shape = (nwave, rho * nsym) if npol == 1 else (nwave, rho * nsym, 2)
+    x = torch.empty(shape, dtype=sym.dtype, device=sym.device)
+    ws = _alloc(_ws(lib.tx_shape_workspace_size, code, npol, nwave, nsym, rho), x.device)
+    N.check(lib.tx_shape_symbols(code, npol, nwave, nsym, rho, rs, rolloff, _ptr(sym), _ptr(p_watt), _ptr(x),
+                                 _ptr(ws), ws.numel(), stream_handle(stream, x.device)))
+    return x
+
+
 def qam16_symbols(sym_idx: torch.Tensor, dtype=torch.complex64, stream=None) -> torch.Tensor:
     lib = N.load()
     _check_dev("sym_idx", sym_idx, torch.int32)

@@ -31,8 +31,11 @@ def _small(**kw):
 def _oracle_batch(tr, it, complex128=False):
     cfg = tr.cfg
     nwords = cfg.nwave * cfg.nsym
-    words = PH.words((nwords + 3) // 4, cfg.seed, 2 * it).reshape(-1)[:nwords].astype(np.int64)
-    s = X.qam16((words & 15).reshape(cfg.nwave, cfg.nsym))
+    if cfg.symbols == "gauss":
+        s = PH.complex_normal(nwords, cfg.seed, 2 * it).reshape(cfg.nwave, cfg.nsym)
+    else:
+        words = PH.words((nwords + 3) // 4, cfg.seed, 2 * it).reshape(-1)[:nwords].astype(np.int64)
+        s = X.qam16((words & 15).reshape(cfg.nwave, cfg.nsym))
     p = tr.powers(it).cpu().numpy()
     x = X.tx_shape(s, cfg.rho_a, p, cfg.rs)
     noise = PH.complex_normal(cfg.nspan * x.size, cfg.seed, 2 * it + 1).reshape((cfg.nspan,) + x.shape)
@@ -43,10 +46,13 @@ def _oracle_batch(tr, it, complex128=False):
     return X.lpf_decimate(y, tr.n_d), s, p
 
 
+@pytest.mark.parametrize("symbols", ["qam16", "gauss"])
 @pytest.mark.parametrize("c128,tol", [(True, 1e-10), (False, 2e-4)])
-def test_training_batch_matches_oracle_pipeline(c128, tol):
-    print("case: batch", c128, flush=True)
-    tr = T.Trainer(_small(complex128=c128))
+def test_training_batch_matches_oracle_pipeline(c128, tol, symbols):
+    """The GPU data pipeline (symbols, transmitter, channel with amplifier noise, receiver front end)
+    against the oracle pipeline driven by the oracle's own Philox; 16-QAM or Gaussian symbols."""
+    print("case: batch", c128, symbols, flush=True)
+    tr = T.Trainer(_small(complex128=c128, symbols=symbols))
     r, s, p = tr.batch(3)
     torch.cuda.synchronize()
     r_ref, s_ref, p_ref = _oracle_batch(tr, 3)
@@ -101,6 +107,15 @@ def test_resume_is_bitwise_identical(tmp_path):
     assert a.ntap == c.ntap
     np.testing.assert_array_equal(a.taps.cpu().numpy(), c.taps.cpu().numpy())
     np.testing.assert_array_equal(a.c.cpu().numpy(), c.c.cpu().numpy())
+
+
+def test_alternating_pruning_targets():
+    """The alternating 5/3-tap model (Sec. V-A): even-numbered layers end at 5 taps, odd ones at 3."""
+    print("case: alternating pruning", flush=True)
+    tr = T.Trainer(_small(nspan=4, t_init=9, t_final=5, t_final_alt=3, iters=30, prune_frac=0.5))
+    tr.train(30)
+    assert tr.ntap == [5, 3, 5, 3]
+    assert tr.events_done == len(tr.plan) == 2 + 3 + 2 + 3
 
 
 def test_pruning_shrinks_filters_and_keeps_symmetry():
