@@ -134,3 +134,45 @@ def test_checkpointed_forward_groups_whole_blocks():
     # a pass never splits a block, whatever the plan asks for
     npass, _, maxs = L.ldbp_forward_plan_query(0, 1, 64, 65536, [15] * 50, ckpt_every=5, plan=(3, 0))
     assert maxs == 5 and npass == 10
+
+
+def _aws(n=1000, ntap=(15, 15), nl=None, edge=1, nwave=2, plan=None):
+    lib = N.load()
+    out = ctypes.c_size_t(123)
+    st = lib.ldbp_forward_aperiodic_workspace_size(0, 1, nwave, n, len(ntap), N.i32_array(ntap),
+                                                   N.i32_array(nl) if nl else None, edge,
+                                                   ctypes.byref(plan) if plan else None, ctypes.byref(out))
+    return st, out.value
+
+
+def test_aperiodic_workspace_and_validation():
+    # one pass: no workspace; zero edge works on n + 2P samples, valid edge on n
+    st, b = _aws(ntap=[15] * 3)
+    assert st == 0 and b == 0
+    P = 7 * 50
+    st, b = _aws(ntap=[15] * 50, n=1000, nwave=4, edge=N.LDBP_EDGE_ZERO)
+    buf = (4 * (1000 + 2 * P) * 8 + 255) // 256 * 256
+    assert st == 0 and b == 2 * buf                   # several passes: two intermediate buffers
+    st, b = _aws(ntap=[15] * 50, n=1000, nwave=4, edge=N.LDBP_EDGE_VALID, plan=N.LdbpPlan(25, 0, 0, 0))
+    assert st == 0 and b == (4 * 1000 * 8 + 255) // 256 * 256   # two passes: one buffer
+    assert _aws(ntap=[15] * 50, n=2 * P, edge=N.LDBP_EDGE_VALID)[0] == N.LDBP_EINVAL   # no valid output
+    assert _aws(ntap=[15, 15], n=1000, nl=[41, 3], edge=N.LDBP_EDGE_VALID)[0] == 0
+    assert _aws(ntap=[15, 15], n=2 * (14 + 21), nl=[41, 3], edge=N.LDBP_EDGE_VALID)[0] == N.LDBP_EINVAL
+    assert _aws(edge=3)[0] == N.LDBP_EINVAL
+    # the call itself rejects the same before any GPU work
+    lib = N.load()
+    st = lib.ldbp_forward_aperiodic(0, 1, 1, 8, 2, N.i32_array([5, 5]), None, ctypes.c_void_p(16),
+                                    ctypes.c_void_p(16), None, ctypes.c_void_p(1024), ctypes.c_void_p(4096),
+                                    N.LDBP_EDGE_VALID, None, None, 0, None)
+    assert st == N.LDBP_EINVAL
+
+
+def test_tx_shape_symbols_validation():
+    lib = N.load()
+    args = (0, 1, 2, 64, 2, 10.7e9, 0.1)
+    assert lib.tx_shape_symbols(*args, None, ctypes.c_void_p(16), ctypes.c_void_p(4096), None, 0,
+                                None) == N.LDBP_EINVAL                       # no symbols
+    assert lib.tx_shape_symbols(0, 1, 2, 64, 3, 10.7e9, 0.1, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                ctypes.c_void_p(4096), None, 0, None) == N.LDBP_EUNSUPPORTED   # rho 3
+    assert lib.tx_shape_symbols(*args, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(4096), None, 0,
+                                None) == N.LDBP_EWORKSPACE
