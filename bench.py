@@ -488,33 +488,44 @@ def essm_trained(torch, dev, iters: int, powers, kappa: int = 20, ntaps: int = 1
             "train_iterations": iters, "models": out_models, "by_power": rows}
 
 
-def e1_reduced(torch, dev, iters: int, powers, out_dir: str):
+def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_at=None):
     """The paper's first scenario (Sec. V-A) at reduced training length: 10.7 GBd over 25 x 80 km,
     LDBP on the asymmetric split-step with one step per span (l = 25), symmetric filters pruned from 9
     taps to alternating 5 and 3 taps (overall impulse response 13 * 4 + 12 * 2 + 1 = 77 taps),
     Gaussian symbols, training powers {-2, -1, 0, 1} dBm, Adam lr 1e-3.  Channel: 50 uniform steps per
     span at 4 samples per symbol (the paper simulates at 6) with amplifier noise (NF 5 dB).  Effective
     SNR per launch power on held-out batches (4 x 32 x 8,192 symbols) for the trained model, its
-    least-squares initialisation, FFT-DBP with 1 and 2 steps per span and linear equalisation."""
+    least-squares initialisation, FFT-DBP with 1 and 2 steps per span and linear equalisation.
+    resume: a trainer checkpoint of the same configuration to continue from (training resumes bit for
+    bit); stop_at: save a checkpoint at that iteration and return without evaluating."""
     from paper_2010_14258_amd import train as TRN
 
     cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=4, rho_d=2, nspan=25, span_km=80.0, channel_steps=50,
                           ldbp_steps=1, t_init=9, t_final=5, t_final_alt=3, iters=iters,
                           powers_dbm=(-2.0, -1.0, 0.0, 1.0), symbols="gauss", seed=1101)
     trn = TRN.Trainer(cfg, device=dev)
-    init = {p_: trn.evaluate(nbatch=4, p_dbm=p_) for p_ in powers}
+    if resume:
+        trn.load(resume)
+    curve = json.load(open(resume + ".curve.json")) if resume and os.path.exists(resume + ".curve.json") else []
+    end = iters if stop_at is None else min(stop_at, iters)
     t0 = time.perf_counter()
-    curve = []
-    for it in range(iters):
+    while trn.it < end:
         loss = trn.step()
-        if (it + 1) % 500 == 0:
-            curve.append([it + 1, loss, int(sum(trn.ntap))])
-            print(f"e1 train {it + 1}/{iters} loss {loss:.4e} taps {list(trn.ntap)[:4]}... "
+        if trn.it % 500 == 0:
+            curve.append([trn.it, loss, int(sum(trn.ntap))])
+            print(f"e1 train {trn.it}/{iters} loss {loss:.4e} taps {list(trn.ntap)[:4]}... "
                   f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     os.makedirs(out_dir, exist_ok=True)
-    trn.save(os.path.join(out_dir, "e1_trained.pt"))
+    ck = os.path.join(out_dir, f"e1_it{trn.it}.pt")
+    trn.save(ck)
+    json.dump(curve, open(ck + ".curve.json", "w"))
+    if trn.it < iters:
+        return {"checkpoint": ck, "iteration": trn.it, "train_seconds": train_s}
+    init_model = TRN.Trainer(cfg, device=dev)
+    init = {p_: init_model.evaluate(nbatch=4, p_dbm=p_) for p_ in powers}
+    del init_model
     rows = []
     for p_ in powers:
         row = {"launch_dbm": p_, "ldbp_trained_snr_db": trn.evaluate(nbatch=4, p_dbm=p_),
@@ -527,7 +538,7 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str):
     resp = 1 + sum(t - 1 for t in trn.ntap)
     peak = {k: max(r[k] for r in rows) for k in rows[0] if k.endswith("_snr_db")}
     return {"workload": "10.7 GBd, 25 x 80 km SSMF, Gaussian symbols, LDBP l = 25 (1 step per span), 9 -> 5/3 taps",
-            "train_iterations": iters, "train_seconds": train_s, "final_ntap": list(trn.ntap),
+            "train_iterations": iters, "train_seconds_last_call": train_s, "final_ntap": list(trn.ntap),
             "impulse_response_taps": resp, "loss_curve": curve, "by_power": rows, "peak_snr_db": peak,
             "paper_context": {"ldbp_peak_snr_db": 23.5, "penalty_vs_fd_dbp_1stps_db": 2.0,
                               "train_iterations": 150000, "analog_oversampling": 6,
@@ -554,6 +565,8 @@ def main():
                          "e1: the 25 x 80 km scenario with Gaussian symbols and 9 -> 5/3-tap pruning")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
+    ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
+    ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
     ap.add_argument("--train-taps", default="25:3",
                     help="models of --mode snr: initial:final taps per step, comma separated (pruned in training)")
     ap.add_argument("--one-stream", action="store_true",
@@ -591,7 +604,7 @@ def main():
         return
     if args.mode == "e1":
         out = e1_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
-                         os.path.join(ROOT, "gpurun_out"))
+                         os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at)
         print(json.dumps(out), flush=True)
         return
     if args.mode == "essm":
