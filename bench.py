@@ -545,6 +545,36 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
                               "note": "the paper's values (Sec. V-A, Fig. results_Ip2008), context only"}}
 
 
+def init_schemes(torch, dev, iters: int, every: int = 1000):
+    """Initialisation study (Sec. V-D) on the 25 x 80 km link: LDBP with one step per span and 9 general
+    (unconstrained) taps per step, no pruning, trained at P = {0 dBm} with Gaussian symbols from
+    least-squares, unit and random filters (random: i.i.d. N(0, 1) parts divided by the sum of squared
+    magnitudes).  Learning curves: effective SNR at 0 dBm on held-out batches every `every` iterations."""
+    from paper_2010_14258_amd import train as TRN
+
+    out = {}
+    for name, kw in (("least_squares", {}), ("unit", {"unit_init": True}), ("random", {"random_init": True})):
+        cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=4, rho_d=2, nspan=25, span_km=80.0, channel_steps=50,
+                              ldbp_steps=1, t_init=9, t_final=9, iters=iters, powers_dbm=(0.0,), symbols="gauss",
+                              symmetric=False, seed=1201, **kw)
+        trn = TRN.Trainer(cfg, device=dev)
+        curve = [[0, trn.evaluate(nbatch=2, p_dbm=0.0)]]
+        t0 = time.perf_counter()
+        while trn.it < iters:
+            trn.step()
+            if trn.it % every == 0:
+                curve.append([trn.it, trn.evaluate(nbatch=2, p_dbm=0.0)])
+                print(f"init {name} {trn.it}/{iters} SNR {curve[-1][1]:.2f} dB {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+        out[name] = {"snr_curve_db": curve, "final_snr_db": trn.evaluate(nbatch=4, p_dbm=0.0),
+                     "train_seconds": time.perf_counter() - t0}
+        del trn
+    return {"workload": "10.7 GBd, 25 x 80 km, Gaussian symbols, LDBP l = 25, 9 taps, trained at 0 dBm",
+            "train_iterations": iters, "schemes": out,
+            "paper_context": {"least_squares_db": 25.6, "unit_db": 25.1, "random": "stuck", "iterations": 10000,
+                              "note": "the paper's values (Sec. V-D, Fig. results(c)), context only"}}
+
+
 def snr_db(TX, z, s, p):
     mse, _, _ = TX.rx_mse(z, s, p, RHO_D, RS)
     return 10.0 * math.log10(1.0 / float(mse.mean().item()))
@@ -557,12 +587,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
-    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp", "snr", "essm", "e1"], default="full",
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp", "snr", "essm", "e1", "init"], default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "dbp: FFT-DBP at one step per span only (for kernel traces of the split-step passes); "
                          "snr: train LDBP, then the equal-SNR comparison with FFT-DBP over launch powers; "
                          "essm: train conventional and generalised ESSM (and LDBP) with one step per span; "
-                         "e1: the 25 x 80 km scenario with Gaussian symbols and 9 -> 5/3-tap pruning")
+                         "e1: the 25 x 80 km scenario with Gaussian symbols and 9 -> 5/3-tap pruning; "
+                         "init: least-squares, unit and random initialisation on that link")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
@@ -606,6 +637,9 @@ def main():
         out = e1_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
                          os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at)
         print(json.dumps(out), flush=True)
+        return
+    if args.mode == "init":
+        print(json.dumps(init_schemes(torch, dev, args.train_iters)), flush=True)
         return
     if args.mode == "essm":
         out = essm_trained(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")])

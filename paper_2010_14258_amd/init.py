@@ -14,6 +14,9 @@ the device parameters the kernels train and apply.
     normal equations, whose matrix is Hermitian Toeplitz.  "full": the full-band
     fit, which on an N-point grid is the truncated inverse DFT of the response,
     computed with one FFT;
+  * unit filters (h_0 = 1) and random filters (real and imaginary parts i.i.d. N(0, 1), each filter
+    divided by the sum of its squared magnitudes), the alternatives the paper compares with the
+    least-squares filters (Sec. V-D);
   * Kerr coefficients: c = -kerr_scale gamma L_eff(delta) e^{-alpha z_a} for the
     forward step that starts at span position z_a (unit-gain filters keep the
     signal at launch power, so the span's power profile is carried by c).
@@ -106,17 +109,28 @@ def backprop_schedule(span_len: float, nspan: int, steps: Sequence[float]) -> Li
     return order
 
 
+def random_filter(T: int, g: np.random.Generator) -> np.ndarray:
+    """T taps with real and imaginary parts i.i.d. N(0, 1), divided by sum_j |h_j|^2 (Sec. V-D)."""
+    h = g.standard_normal(T) + 1j * g.standard_normal(T)
+    return h / np.sum(np.abs(h) ** 2)
+
+
 def ldbp_parameters(span_len: float, nspan: int, steps_per_span: int, ntap, fs: float, alpha: float, beta2: float,
                     gamma: float, kerr_scale: float = 1.0, log_steps: bool = True, unit_taps: bool = False,
-                    method: str = "inband", rho: int = 2, rolloff: float = 0.1, mu: float = 1e-3):
-    """Asymmetric-SSM LDBP (l = nspan * steps_per_span): returns (list of tap vectors, c array)."""
+                    method: str = "inband", rho: int = 2, rolloff: float = 0.1, mu: float = 1e-3,
+                    random_seed=None):
+    """Asymmetric-SSM LDBP (l = nspan * steps_per_span): returns (list of tap vectors, c array).
+
+    unit_taps: unit filters; random_seed (int): random filters (see random_filter) instead of the fit."""
     steps = log_step_sizes(span_len, steps_per_span, alpha) if log_steps else [span_len / steps_per_span] * steps_per_span
     sched = backprop_schedule(span_len, nspan, steps)
     L = len(sched)
     ts = [int(ntap)] * L if np.isscalar(ntap) else [int(t) for t in ntap]
     taps, c = [], np.zeros(L)
     for i, (d, z0) in enumerate(sched):
-        if unit_taps:
+        if random_seed is not None:
+            h = random_filter(ts[i], np.random.Generator(np.random.PCG64([int(random_seed), i])))
+        elif unit_taps:
             h = np.zeros(ts[i], dtype=np.complex128)
             h[(ts[i] - 1) // 2] = 1.0
         elif method == "inband":

@@ -70,6 +70,7 @@ class TrainConfig:
     seed: int = 301
     complex128: bool = False
     unit_init: bool = False
+    random_init: bool = False         # random filters (normalised) instead of least squares
     train_taps: bool = True
     essm_kappa: int = -1              # >= 0: filtered nonlinear steps with 2 kappa + 1 real taps
     essm_shared: bool = False         # one filter in every nonlinear step (conventional ESSM)
@@ -111,7 +112,10 @@ class Trainer:
                                ase_var=I.ase_variance(self.alpha, self.span, cfg.nf_db, self.fs_a),
                                kerr_scale=self.kerr_scale)
         taps, c = I.ldbp_parameters(self.span, cfg.nspan, cfg.ldbp_steps, cfg.t_init, self.fs_d, self.alpha,
-                                    self.beta2, self.gamma, kerr_scale=self.kerr_scale, unit_taps=cfg.unit_init)
+                                    self.beta2, self.gamma, kerr_scale=self.kerr_scale, unit_taps=cfg.unit_init,
+                                    random_seed=cfg.seed if cfg.random_init else None)
+        if cfg.random_init and cfg.symmetric:
+            raise ValueError("random filters are not symmetric: use symmetric=False with random_init")
         if cfg.symmetric:
             # the least-squares fit of an even response is symmetric up to rounding; make it exact, since
             # the folded kernels read only one side of each filter

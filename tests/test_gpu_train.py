@@ -231,3 +231,15 @@ def test_learned_essm_gains_over_its_initialisation():
     snr1 = tr.evaluate(nbatch=4, p_dbm=4.0)
     print(f"ESSM LS init {snr0:.2f} dB, trained {snr1:.2f} dB", flush=True)
     assert snr1 >= snr0 + 1.0
+
+
+def test_unit_and_random_initialisations_train():
+    """Unit and random (normalised Gaussian) filters (Sec. V-D) run through training with general taps;
+    symmetric folding is refused for random filters."""
+    print("case: init schemes", flush=True)
+    for kw in ({"unit_init": True}, {"random_init": True}):
+        tr = T.Trainer(_small(symmetric=False, iters=5, **kw))
+        tr.train(5)
+        assert all(np.isfinite(h["loss"]) for h in tr.history)
+    with pytest.raises(ValueError):
+        T.Trainer(_small(random_init=True))

@@ -52,3 +52,17 @@ def test_inband_taps_match_oracle_reading():
         for a, b in zip(pt, ot):
             np.testing.assert_allclose(a, b, atol=1e-9)
             np.testing.assert_allclose(a, a[::-1], atol=1e-9)   # symmetric filters
+
+
+def test_random_filters_are_seeded_and_normalised():
+    """Random initialisation (Sec. V-D): i.i.d. N(0, 1) real and imaginary parts divided by the sum
+    of the squared magnitudes; reproducible from the seed, different per step."""
+    g = np.random.Generator(np.random.PCG64([5, 0]))
+    raw = g.standard_normal(9) + 1j * g.standard_normal(9)
+    taps, _ = I.ldbp_parameters(80e3, 3, 1, 9, 21.4e9, I.db_per_km_to_alpha(0.2), I.ps2_per_km_to_beta2(-21.7),
+                                1.3e-3, random_seed=5)
+    np.testing.assert_allclose(taps[0], raw / np.sum(np.abs(raw) ** 2), rtol=1e-15)
+    assert not np.allclose(taps[0], taps[1])
+    again, _ = I.ldbp_parameters(80e3, 3, 1, 9, 21.4e9, I.db_per_km_to_alpha(0.2), I.ps2_per_km_to_beta2(-21.7),
+                                 1.3e-3, random_seed=5)
+    np.testing.assert_array_equal(taps[2], again[2])
