@@ -548,18 +548,24 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
                               "note": "the paper's values (Sec. V-A, Fig. results_Ip2008), context only"}}
 
 
-def init_schemes(torch, dev, iters: int, every: int = 1000):
-    """Initialisation study (Sec. V-D) on the 25 x 80 km link: LDBP with one step per span and 9 general
+def init_schemes(torch, dev, iters: int, every: int = 1000, schemes=("least_squares", "unit", "random"),
+                 ntaps: int = 9):
+    """Initialisation study (Sec. V-E) on the 25 x 80 km link: LDBP with one step per span and 9 general
     (unconstrained) taps per step, no pruning, trained at P = {0 dBm} with Gaussian symbols from
     least-squares, unit and random filters (random: i.i.d. N(0, 1) parts divided by the sum of squared
-    magnitudes).  Learning curves: effective SNR at 0 dBm on held-out batches every `every` iterations."""
+    magnitudes; multiobjective: the least-squares filters refined jointly by the multi-objective
+    weighted least squares of Sec. VI-B).  Learning curves: effective SNR at 0 dBm on held-out batches
+    every `every` iterations."""
     from paper_2010_14258_amd import train as TRN
 
     out = {}
-    for name, kw in (("least_squares", {}), ("unit", {"unit_init": True}), ("random", {"random_init": True})):
+    options = {"least_squares": {}, "unit": {"unit_init": True}, "random": {"random_init": True},
+               "multiobjective": {"init_method": "multiobjective"}}
+    for name in schemes:
+        kw = options[name]
         cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=4, rho_d=2, nspan=25, span_km=80.0, channel_steps=50,
-                              ldbp_steps=1, t_init=9, t_final=9, iters=iters, powers_dbm=(0.0,), symbols="gauss",
-                              symmetric=False, seed=1201, **kw)
+                              ldbp_steps=1, t_init=ntaps, t_final=ntaps, iters=iters, powers_dbm=(0.0,),
+                              symbols="gauss", symmetric=False, seed=1201, **kw)
         trn = TRN.Trainer(cfg, device=dev)
         curve = [[0, trn.evaluate(nbatch=2, p_dbm=0.0)]]
         t0 = time.perf_counter()
@@ -572,10 +578,10 @@ def init_schemes(torch, dev, iters: int, every: int = 1000):
         out[name] = {"snr_curve_db": curve, "final_snr_db": trn.evaluate(nbatch=4, p_dbm=0.0),
                      "train_seconds": time.perf_counter() - t0}
         del trn
-    return {"workload": "10.7 GBd, 25 x 80 km, Gaussian symbols, LDBP l = 25, 9 taps, trained at 0 dBm",
+    return {"workload": f"10.7 GBd, 25 x 80 km, Gaussian symbols, LDBP l = 25, {ntaps} taps, trained at 0 dBm",
             "train_iterations": iters, "schemes": out,
             "paper_context": {"least_squares_db": 25.6, "unit_db": 25.1, "random": "stuck", "iterations": 10000,
-                              "note": "the paper's values (Sec. V-D, Fig. results(c)), context only"}}
+                              "note": "the paper's values (Sec. V-E, Fig. results(c)), context only"}}
 
 
 def snr_db(TX, z, s, p):
@@ -602,6 +608,9 @@ def main():
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
     ap.add_argument("--train-c", action="store_true", help="--mode e1: also train the Kerr coefficients")
     ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
+    ap.add_argument("--schemes", default="least_squares,unit,random",
+                    help="--mode init: initialisations (least_squares, unit, random, multiobjective)")
+    ap.add_argument("--init-taps", type=int, default=9, help="--mode init: taps per step")
     ap.add_argument("--train-taps", default="25:3",
                     help="models of --mode snr: initial:final taps per step, comma separated (pruned in training)")
     ap.add_argument("--one-stream", action="store_true",
@@ -643,7 +652,8 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.mode == "init":
-        print(json.dumps(init_schemes(torch, dev, args.train_iters)), flush=True)
+        print(json.dumps(init_schemes(torch, dev, args.train_iters, schemes=args.schemes.split(","),
+                                      ntaps=args.init_taps)), flush=True)
         return
     if args.mode == "essm":
         out = essm_trained(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")])

@@ -16,7 +16,7 @@ the device parameters the kernels train and apply.
     computed with one FFT;
   * unit filters (h_0 = 1) and random filters (real and imaginary parts i.i.d. N(0, 1), each filter
     divided by the sum of its squared magnitudes), the alternatives the paper compares with the
-    least-squares filters (Sec. V-D);
+    least-squares filters (Sec. V-E);
   * Kerr coefficients: c = -kerr_scale gamma L_eff(delta) e^{-alpha z_a} for the
     forward step that starts at span position z_a (unit-gain filters keep the
     signal at launch power, so the span's power profile is carried by c).
@@ -92,6 +92,67 @@ def inverse_cd_taps_inband(delta: float, beta2: float, fs: float, ntap: int, rho
     return np.linalg.solve(G, rhs)
 
 
+def multi_objective_taps(taps: Sequence[np.ndarray], xis: Sequence[float], rho: int = 2, rolloff: float = 0.1,
+                         mu: float = 1e-3, max_window: int = 0, sweeps: int = 3, grid: int = 1024,
+                         history: list = None) -> List[np.ndarray]:
+    """Joint filter design as a multi-objective weighted least-squares problem (Sec. VI-B, eqs.
+    objectives and weighted_ls): besides each response F(h_i) ~ e^{j xi_i w^2}, the response of every
+    run of neighbouring filters F(h_a * ... * h_b) ~ e^{j (xi_a + ... + xi_b) w^2} (runs of up to
+    max_window filters; 0 = all).  With all filters but h_i fixed, the runs containing i give the
+    weighted LS problem  min_h sum_runs || (B h) o e_run - d_run ||^2_W  with e_run the product of the
+    other filters' responses, d_run the run's target and W the in-band weights of
+    inverse_cd_taps_inband; the filters are updated in turn for `sweeps` passes (block coordinate
+    descent, so the total objective never increases).  All runs weigh the same.  taps: the starting
+    filters (odd lengths, e.g. the individual fits); returns the new filters.  history (a list):
+    receives the total objective before the first and after every sweep."""
+    M = len(taps)
+    L = M if max_window <= 0 else min(max_window, M)
+    w = 2.0 * np.pi * np.arange(-grid // 2, grid // 2 + 1) / grid
+    wt2 = np.where(np.abs(w) <= np.pi * (1.0 + rolloff) / rho, 1.0, mu)
+    Ks = [(len(h) - 1) // 2 for h in taps]
+    Bs = [np.exp(-1j * np.outer(w, np.arange(-K, K + 1))) for K in Ks]   # response = B h = sum_k h_k e^{-j k w}
+    hs = [np.asarray(h, dtype=np.complex128).copy() for h in taps]
+    H = [B @ h for B, h in zip(Bs, hs)]
+    ph = [np.exp(1j * x * w * w) for x in xis]
+
+    def total():
+        J = 0.0
+        for a in range(M):
+            prod, tgt = np.ones_like(w, dtype=np.complex128), np.ones_like(w, dtype=np.complex128)
+            for b in range(a, min(M, a + L)):
+                prod = prod * H[b]
+                tgt = tgt * ph[b]
+                J += float(np.sum(wt2 * np.abs(prod - tgt) ** 2))
+        return J
+
+    if history is not None:
+        history.append(total())
+    for _ in range(sweeps):
+        for i in range(M):
+            A = np.zeros((len(hs[i]), len(hs[i])), dtype=np.complex128)
+            rhs = np.zeros(len(hs[i]), dtype=np.complex128)
+            left, ltgt = np.ones_like(w, dtype=np.complex128), np.ones_like(w, dtype=np.complex128)
+            for a in range(i, max(-1, i - L), -1):        # runs start at a <= i ...
+                if a < i:
+                    left = left * H[a]
+                    ltgt = ltgt * ph[a]
+                right, rtgt = np.ones_like(w, dtype=np.complex128), np.ones_like(w, dtype=np.complex128)
+                for b in range(i, min(M, a + L)):         # ... and end at b >= i
+                    if b > i:
+                        right = right * H[b]
+                        rtgt = rtgt * ph[b]
+                    e = left * right
+                    d = ltgt * ph[i] * rtgt
+                    Be = Bs[i] * e[:, None]
+                    A += Be.conj().T @ (wt2[:, None] * Be)
+                    rhs += Be.conj().T @ (wt2 * d)
+            hs[i] = np.linalg.solve(A, rhs)
+            H[i] = Bs[i] @ hs[i]
+        if history is not None:
+            history.append(total())
+    return hs
+
+
 def unit_peak_gain(h: np.ndarray, grid: int = 4096) -> np.ndarray:
     """Scales a filter so that its largest gain over all frequencies is one (non-expansive cascade)."""
     K = (len(h) - 1) // 2
@@ -110,7 +171,7 @@ def backprop_schedule(span_len: float, nspan: int, steps: Sequence[float]) -> Li
 
 
 def random_filter(T: int, g: np.random.Generator) -> np.ndarray:
-    """T taps with real and imaginary parts i.i.d. N(0, 1), divided by sum_j |h_j|^2 (Sec. V-D)."""
+    """T taps with real and imaginary parts i.i.d. N(0, 1), divided by sum_j |h_j|^2 (Sec. V-E)."""
     h = g.standard_normal(T) + 1j * g.standard_normal(T)
     return h / np.sum(np.abs(h) ** 2)
 
@@ -118,10 +179,12 @@ def random_filter(T: int, g: np.random.Generator) -> np.ndarray:
 def ldbp_parameters(span_len: float, nspan: int, steps_per_span: int, ntap, fs: float, alpha: float, beta2: float,
                     gamma: float, kerr_scale: float = 1.0, log_steps: bool = True, unit_taps: bool = False,
                     method: str = "inband", rho: int = 2, rolloff: float = 0.1, mu: float = 1e-3,
-                    random_seed=None):
+                    random_seed=None, mo_window: int = 0, mo_sweeps: int = 3):
     """Asymmetric-SSM LDBP (l = nspan * steps_per_span): returns (list of tap vectors, c array).
 
-    unit_taps: unit filters; random_seed (int): random filters (see random_filter) instead of the fit."""
+    unit_taps: unit filters; random_seed (int): random filters (see random_filter) instead of the fit;
+    method "multiobjective": the in-band fits refined jointly by multi_objective_taps (runs of up to
+    mo_window filters, mo_sweeps passes)."""
     steps = log_step_sizes(span_len, steps_per_span, alpha) if log_steps else [span_len / steps_per_span] * steps_per_span
     sched = backprop_schedule(span_len, nspan, steps)
     L = len(sched)
@@ -133,10 +196,13 @@ def ldbp_parameters(span_len: float, nspan: int, steps_per_span: int, ntap, fs: 
         elif unit_taps:
             h = np.zeros(ts[i], dtype=np.complex128)
             h[(ts[i] - 1) // 2] = 1.0
-        elif method == "inband":
+        elif method in ("inband", "multiobjective"):
             h = inverse_cd_taps_inband(d, beta2, fs, ts[i], rho, rolloff, mu)
         else:
             h = inverse_cd_taps(d, beta2, fs, ts[i])
         taps.append(h)
         c[i] = -kerr_scale * gamma * effective_length(d, alpha) * math.exp(-alpha * z0)
+    if method == "multiobjective" and not unit_taps and random_seed is None:
+        xis = [-beta2 * d * fs * fs / 2.0 for d, _ in sched]
+        taps = multi_objective_taps(taps, xis, rho, rolloff, mu, mo_window, mo_sweeps)
     return taps, c

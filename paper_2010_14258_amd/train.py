@@ -71,6 +71,7 @@ class TrainConfig:
     complex128: bool = False
     unit_init: bool = False
     random_init: bool = False         # random filters (normalised) instead of least squares
+    init_method: str = "inband"       # least-squares design: "inband", "full" or "multiobjective"
     train_taps: bool = True
     essm_kappa: int = -1              # >= 0: filtered nonlinear steps with 2 kappa + 1 real taps
     essm_shared: bool = False         # one filter in every nonlinear step (conventional ESSM)
@@ -113,7 +114,7 @@ class Trainer:
                                kerr_scale=self.kerr_scale)
         taps, c = I.ldbp_parameters(self.span, cfg.nspan, cfg.ldbp_steps, cfg.t_init, self.fs_d, self.alpha,
                                     self.beta2, self.gamma, kerr_scale=self.kerr_scale, unit_taps=cfg.unit_init,
-                                    random_seed=cfg.seed if cfg.random_init else None)
+                                    random_seed=cfg.seed if cfg.random_init else None, method=cfg.init_method)
         if cfg.random_init and cfg.symmetric:
             raise ValueError("random filters are not symmetric: use symmetric=False with random_init")
         if cfg.symmetric:

@@ -234,7 +234,7 @@ def test_learned_essm_gains_over_its_initialisation():
 
 
 def test_unit_and_random_initialisations_train():
-    """Unit and random (normalised Gaussian) filters (Sec. V-D) run through training with general taps;
+    """Unit and random (normalised Gaussian) filters (Sec. V-E) run through training with general taps;
     symmetric folding is refused for random filters."""
     print("case: init schemes", flush=True)
     for kw in ({"unit_init": True}, {"random_init": True}):

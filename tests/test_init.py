@@ -55,7 +55,7 @@ def test_inband_taps_match_oracle_reading():
 
 
 def test_random_filters_are_seeded_and_normalised():
-    """Random initialisation (Sec. V-D): i.i.d. N(0, 1) real and imaginary parts divided by the sum
+    """Random initialisation (Sec. V-E): i.i.d. N(0, 1) real and imaginary parts divided by the sum
     of the squared magnitudes; reproducible from the seed, different per step."""
     g = np.random.Generator(np.random.PCG64([5, 0]))
     raw = g.standard_normal(9) + 1j * g.standard_normal(9)
@@ -66,3 +66,56 @@ def test_random_filters_are_seeded_and_normalised():
     again, _ = I.ldbp_parameters(80e3, 3, 1, 9, 21.4e9, I.db_per_km_to_alpha(0.2), I.ps2_per_km_to_beta2(-21.7),
                                  1.3e-3, random_seed=5)
     np.testing.assert_array_equal(taps[2], again[2])
+
+
+def _steps(M, T):
+    fs, beta2 = 21.4e9, I.ps2_per_km_to_beta2(-21.683)
+    ds = [80e3 * (1.0 + 0.1 * (i % 3)) for i in range(M)]
+    taps = [I.inverse_cd_taps_inband(d, beta2, fs, T, grid=1024) for d in ds]
+    xis = [-beta2 * d * fs * fs / 2.0 for d in ds]
+    return taps, xis
+
+
+def test_multi_objective_with_single_filter_runs_is_the_individual_fit():
+    """Runs of one filter only: each weighted LS problem is the individual in-band fit (Sec. VI-B)."""
+    taps, xis = _steps(4, 7)
+    start = [np.zeros(7, dtype=complex) + 0.1 for _ in taps]
+    out = I.multi_objective_taps(start, xis, max_window=1, sweeps=1)
+    for a, b in zip(out, taps):
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12)
+
+
+def test_multi_objective_descent_trades_single_fits_for_joint_fits():
+    """Block coordinate descent never raises the total objective.  The individual fits minimise the
+    single-filter terms exactly, so the joint design can only lose there; its gain is in the responses
+    of runs of neighbouring filters (Sec. VI-B: individual accuracy traded for the combined one)."""
+    M, T = 6, 5
+    taps, xis = _steps(M, T)
+    hist = []
+    out = I.multi_objective_taps(taps, xis, sweeps=4, history=hist)
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(hist, hist[1:]))
+    assert hist[-1] < 0.5 * hist[0]
+    w = 2.0 * np.pi * np.arange(-512, 513) / 1024
+    wt2 = np.where(np.abs(w) <= np.pi * 1.1 / 2, 1.0, 1e-3)
+
+    def resp(h):
+        K = (len(h) - 1) // 2
+        return np.exp(-1j * np.outer(w, np.arange(-K, K + 1))) @ h
+
+    def parts(hs):
+        single = multi = 0.0
+        for a in range(M):
+            prod = np.ones_like(w, dtype=complex)
+            for b in range(a, M):
+                prod = prod * resp(hs[b])
+                e = float(np.sum(wt2 * np.abs(prod - np.exp(1j * sum(xis[a:b + 1]) * w * w)) ** 2))
+                if b == a:
+                    single += e
+                else:
+                    multi += e
+        return single, multi
+
+    s0, m0 = parts(taps)
+    s1, m1 = parts(out)
+    assert abs(s0 + m0 - hist[0]) <= 1e-9 * hist[0] and abs(s1 + m1 - hist[-1]) <= 1e-9 * hist[0]
+    assert s1 >= s0 and m1 < m0
