@@ -488,12 +488,12 @@ def essm_trained(torch, dev, iters: int, powers, kappa: int = 20, ntaps: int = 1
             "train_iterations": iters, "models": out_models, "by_power": rows}
 
 
-def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_at=None, train_c: bool = False):
+def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_at=None, train_c: bool = True):
     """The paper's first scenario (Sec. V-A) at reduced training length: 10.7 GBd over 25 x 80 km,
     LDBP on the asymmetric split-step with one step per span (l = 25), symmetric filters pruned from 9
     taps to alternating 5 and 3 taps (overall impulse response 13 * 4 + 12 * 2 + 1 = 77 taps),
-    Gaussian symbols, training powers {-2, -1, 0, 1} dBm, Adam lr 1e-3, fixed nonlinear steps (only the
-    filters are trained, as in the paper; train_c also trains the Kerr coefficients).  Channel: 50
+    Gaussian symbols, training powers {-2, -1, 0, 1} dBm, Adam lr 1e-3 on the filters and the Kerr
+    coefficients (train_c False: fixed nonlinear steps, the paper's setting).  Channel: 50
     uniform steps per span at 4 samples per symbol (the paper simulates at 6) with amplifier noise
     (NF 5 dB).  Effective
     SNR per launch power on held-out batches (4 x 32 x 8,192 symbols) for the trained model, its
@@ -606,7 +606,7 @@ def main():
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
-    ap.add_argument("--train-c", action="store_true", help="--mode e1: also train the Kerr coefficients")
+    ap.add_argument("--fixed-c", action="store_true", help="--mode e1: keep the Kerr coefficients fixed")
     ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
     ap.add_argument("--schemes", default="least_squares,unit,random",
                     help="--mode init: initialisations (least_squares, unit, random, multiobjective)")
@@ -648,7 +648,7 @@ def main():
         return
     if args.mode == "e1":
         out = e1_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
-                         os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, args.train_c)
+                         os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, not args.fixed_c)
         print(json.dumps(out), flush=True)
         return
     if args.mode == "init":
