@@ -548,6 +548,54 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
                               "note": "the paper's values (Sec. V-A, Fig. results_Ip2008), context only"}}
 
 
+def e8_reduced(torch, dev, iters: int, powers):
+    """The paper's 32 GBd scenario (Sec. V-F) at reduced training length: 10 x 100 km, LDBP on the
+    symmetric split-step with log step sizes, 2 steps per span (l = 21, 23 taps per filter: an overall
+    impulse response of 21 * 22 + 1 = 463 taps) trained at P = {3, 4, 5} dBm, and 4 steps per span
+    (l = 41, 13 taps: 493) at {4, 5, 6} dBm; Gaussian symbols, no pruning, Adam lr 1e-3 on the filters
+    and the Kerr coefficients (the last step stays linear).  Channel at 4 samples per symbol (the paper:
+    6) with 100 steps per span and amplifier noise.  Effective SNR per power on held-out batches, with
+    FFT-DBP at the same number of steps per span (and 10) for reference."""
+    from paper_2010_14258_amd import train as TRN
+
+    out = {}
+    for stps, ntaps, ptrain in ((2, 23, (3.0, 4.0, 5.0)), (4, 13, (4.0, 5.0, 6.0))):
+        cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=4, rho_d=2, rs=32e9, nspan=10, span_km=100.0,
+                              channel_steps=100, ldbp_steps=stps, t_init=ntaps, t_final=ntaps, iters=iters,
+                              powers_dbm=ptrain, symbols="gauss", ssm="symmetric", seed=1301 + stps)
+        trn = TRN.Trainer(cfg, device=dev)
+        init = {p_: trn.evaluate(nbatch=4, p_dbm=p_) for p_ in powers}
+        t0 = time.perf_counter()
+        curve = []
+        while trn.it < iters:
+            loss = trn.step()
+            if trn.it % 500 == 0:
+                curve.append([trn.it, loss])
+                print(f"e8 {stps} StPS {trn.it}/{iters} loss {loss:.4e} {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+        train_s = time.perf_counter() - t0
+        rows = []
+        for p_ in powers:
+            row = {"launch_dbm": p_, "ldbp_trained_snr_db": trn.evaluate(nbatch=4, p_dbm=p_),
+                   "ldbp_ls_init_snr_db": init[p_],
+                   "fft_dbp_same_stps_snr_db": trn.evaluate_fft_dbp(stps, nbatch=4, p_dbm=p_),
+                   "fft_dbp_10stps_snr_db": trn.evaluate_fft_dbp(10, nbatch=4, p_dbm=p_)}
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+        peak = {k: max(r[k] for r in rows) for k in rows[0] if k.endswith("_snr_db")}
+        out[f"{stps}_stps"] = {"l": len(trn.ntap), "taps_per_filter": ntaps,
+                               "impulse_response_taps": 1 + sum(t - 1 for t in trn.ntap),
+                               "train_powers_dbm": list(ptrain), "train_seconds": train_s, "loss_curve": curve,
+                               "by_power": rows, "peak_snr_db": peak,
+                               "peak_gain_over_fft_dbp_same_stps_db": peak["ldbp_trained_snr_db"]
+                               - peak["fft_dbp_same_stps_snr_db"]}
+        del trn
+    return {"workload": "32 GBd, 10 x 100 km SSMF, Gaussian symbols, symmetric-SSM LDBP, 2 and 4 steps per span",
+            "train_iterations": iters, "models": out,
+            "paper_context": {"gain_over_dbp_db": {"2_stps": 2.1, "4_stps": 0.6}, "taps": 463,
+                              "note": "the paper's values (Sec. V-F), after 150,000 + 1,500 iterations; context only"}}
+
+
 def init_schemes(torch, dev, iters: int, every: int = 1000, schemes=("least_squares", "unit", "random"),
                  ntaps: int = 9):
     """Initialisation study (Sec. V-E) on the 25 x 80 km link: LDBP with one step per span and 9 general
@@ -596,13 +644,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
-    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp", "snr", "essm", "e1", "init"], default="full",
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp", "snr", "essm", "e1", "init", "e8"], default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "dbp: FFT-DBP at one step per span only (for kernel traces of the split-step passes); "
                          "snr: train LDBP, then the equal-SNR comparison with FFT-DBP over launch powers; "
                          "essm: train conventional and generalised ESSM (and LDBP) with one step per span; "
                          "e1: the 25 x 80 km scenario with Gaussian symbols and 9 -> 5/3-tap pruning; "
-                         "init: least-squares, unit and random initialisation on that link")
+                         "init: least-squares, unit and random initialisation on that link; "
+                         "e8: the 32 GBd scenario (symmetric-SSM LDBP, 2 and 4 steps per span)")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
@@ -650,6 +699,10 @@ def main():
         out = e1_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
                          os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, not args.fixed_c)
         print(json.dumps(out), flush=True)
+        return
+    if args.mode == "e8":
+        print(json.dumps(e8_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")])),
+              flush=True)
         return
     if args.mode == "init":
         print(json.dumps(init_schemes(torch, dev, args.train_iters, schemes=args.schemes.split(","),

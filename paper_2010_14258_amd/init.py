@@ -153,6 +153,30 @@ def multi_objective_taps(taps: Sequence[np.ndarray], xis: Sequence[float], rho: 
     return hs
 
 
+def ldbp_parameters_symmetric(span_len: float, nspan: int, steps_per_span: int, ntap, fs: float, alpha: float,
+                              beta2: float, gamma: float, kerr_scale: float = 1.0, log_steps: bool = True,
+                              method: str = "inband", rho: int = 2, rolloff: float = 0.1, mu: float = 1e-3):
+    """Symmetric-SSM LDBP (Sec. III-C, IV-C): M = nspan * steps_per_span nonlinear steps and l = M + 1
+    linear ones -- the first and last half-steps and, between nonlinear steps, the merged halves of the
+    two neighbouring steps -- so the model's last step is linear only (c_l = 0).  Returns (taps, c)."""
+    steps = log_step_sizes(span_len, steps_per_span, alpha) if log_steps else [span_len / steps_per_span] * steps_per_span
+    sched = backprop_schedule(span_len, nspan, steps)
+    deltas = [d for d, _ in sched]
+    merged = [deltas[0] / 2.0] + [(deltas[i - 1] + deltas[i]) / 2.0 for i in range(1, len(deltas))] + [deltas[-1] / 2.0]
+    L = len(merged)
+    ts = [int(ntap)] * L if np.isscalar(ntap) else [int(t) for t in ntap]
+    taps = []
+    for i, d in enumerate(merged):
+        if method == "inband":
+            taps.append(inverse_cd_taps_inband(d, beta2, fs, ts[i], rho, rolloff, mu))
+        else:
+            taps.append(inverse_cd_taps(d, beta2, fs, ts[i]))
+    c = np.zeros(L)
+    for i, (d, z0) in enumerate(sched):
+        c[i] = -kerr_scale * gamma * effective_length(d, alpha) * math.exp(-alpha * z0)
+    return taps, c
+
+
 def unit_peak_gain(h: np.ndarray, grid: int = 4096) -> np.ndarray:
     """Scales a filter so that its largest gain over all frequencies is one (non-expansive cascade)."""
     K = (len(h) - 1) // 2

@@ -72,6 +72,7 @@ class TrainConfig:
     unit_init: bool = False
     random_init: bool = False         # random filters (normalised) instead of least squares
     init_method: str = "inband"       # least-squares design: "inband", "full" or "multiobjective"
+    ssm: str = "asymmetric"           # "symmetric": l = M + 1 with merged half-steps, last step linear
     train_taps: bool = True
     essm_kappa: int = -1              # >= 0: filtered nonlinear steps with 2 kappa + 1 real taps
     essm_shared: bool = False         # one filter in every nonlinear step (conventional ESSM)
@@ -112,9 +113,15 @@ class Trainer:
                                span_len=self.span, nspan=cfg.nspan, nstep=cfg.channel_steps, edfa_gain=True,
                                ase_var=I.ase_variance(self.alpha, self.span, cfg.nf_db, self.fs_a),
                                kerr_scale=self.kerr_scale)
-        taps, c = I.ldbp_parameters(self.span, cfg.nspan, cfg.ldbp_steps, cfg.t_init, self.fs_d, self.alpha,
-                                    self.beta2, self.gamma, kerr_scale=self.kerr_scale, unit_taps=cfg.unit_init,
-                                    random_seed=cfg.seed if cfg.random_init else None, method=cfg.init_method)
+        if cfg.ssm == "symmetric":
+            taps, c = I.ldbp_parameters_symmetric(self.span, cfg.nspan, cfg.ldbp_steps, cfg.t_init, self.fs_d,
+                                                  self.alpha, self.beta2, self.gamma, kerr_scale=self.kerr_scale,
+                                                  method="inband" if cfg.init_method == "multiobjective"
+                                                  else cfg.init_method)
+        else:
+            taps, c = I.ldbp_parameters(self.span, cfg.nspan, cfg.ldbp_steps, cfg.t_init, self.fs_d, self.alpha,
+                                        self.beta2, self.gamma, kerr_scale=self.kerr_scale, unit_taps=cfg.unit_init,
+                                        random_seed=cfg.seed if cfg.random_init else None, method=cfg.init_method)
         if cfg.random_init and cfg.symmetric:
             raise ValueError("random filters are not symmetric: use symmetric=False with random_init")
         if cfg.symmetric:
@@ -128,6 +135,11 @@ class Trainer:
         self.v_t = torch.zeros_like(self.m_t)
         self.m_c = torch.zeros_like(self.c)
         self.v_c = torch.zeros_like(self.c)
+        # symmetric SSM: the last step is linear only, its coefficient stays 0
+        self.c_mask = None
+        if cfg.ssm == "symmetric":
+            self.c_mask = torch.ones_like(self.c)
+            self.c_mask[-1] = 0
         self.essm = cfg.essm_kappa >= 0
         if self.essm:
             ne = 2 * cfg.essm_kappa + 1
@@ -244,7 +256,7 @@ class Trainer:
             TX.adam_(self.taps, gt, self.m_t, self.v_t, self.t, lr=cfg.lr,
                      mirror=self.mirror() if cfg.symmetric else None)
         if cfg.train_c:
-            TX.adam_(self.c, gc, self.m_c, self.v_c, self.t, lr=cfg.lr)
+            TX.adam_(self.c, gc, self.m_c, self.v_c, self.t, lr=cfg.lr, mask=self.c_mask)
         if self.essm:
             TX.adam_(self.eta, ge, self.m_e, self.v_e, self.t, lr=cfg.lr)
         loss = float(mse.mean().item())

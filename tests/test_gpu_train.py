@@ -243,3 +243,14 @@ def test_unit_and_random_initialisations_train():
         assert all(np.isfinite(h["loss"]) for h in tr.history)
     with pytest.raises(ValueError):
         T.Trainer(_small(random_init=True))
+
+
+def test_symmetric_ssm_model_keeps_its_last_step_linear():
+    """Symmetric-SSM LDBP (Sec. III-C): l = M + 1 filters; the last Kerr coefficient stays 0 in training."""
+    print("case: symmetric ssm", flush=True)
+    tr = T.Trainer(_small(nspan=3, ldbp_steps=2, ssm="symmetric", iters=6, rs=32e9))
+    assert len(tr.ntap) == 3 * 2 + 1
+    tr.train(6)
+    c = tr.c.cpu().numpy()
+    assert c[-1] == 0.0 and np.all(c[:-1] != 0.0)
+    assert all(np.isfinite(h["loss"]) for h in tr.history)

@@ -119,3 +119,19 @@ def test_multi_objective_descent_trades_single_fits_for_joint_fits():
     s1, m1 = parts(out)
     assert abs(s0 + m0 - hist[0]) <= 1e-9 * hist[0] and abs(s1 + m1 - hist[-1]) <= 1e-9 * hist[0]
     assert s1 >= s0 and m1 < m0
+
+
+def test_symmetric_ssm_initialisation_matches_the_oracle_design():
+    """Symmetric-SSM LDBP (Sec. III-C, IV-C): merged half-steps give l = M + 1 filters, the last step
+    is linear only; full-band fits against the oracle's truncated inverse DFT of each merged step."""
+    alpha, beta2, gamma, fs = I.db_per_km_to_alpha(0.2), I.ps2_per_km_to_beta2(-21.7), 1.3e-3, 64e9
+    span, nspan, stps, T = 100e3, 3, 2, 11
+    taps, c = I.ldbp_parameters_symmetric(span, nspan, stps, T, fs, alpha, beta2, gamma, method="full")
+    steps = D.log_steps(span, stps, alpha)
+    plan = D.dbp_step_plan(span, nspan, steps)
+    merged = D.merge_half_steps([d for d, _ in plan])
+    assert len(taps) == len(c) == nspan * stps + 1 and c[-1] == 0.0
+    for h, dm in zip(taps, merged):
+        np.testing.assert_allclose(h, D.truncated_idft_taps(D.xi_of(dm, beta2, fs), T), atol=1e-12)
+    for i, (d, z0) in enumerate(plan):
+        assert abs(c[i] - D.kerr_coef(d, z0, alpha, gamma)) <= 1e-15 * abs(c[i])
