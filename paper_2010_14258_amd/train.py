@@ -58,6 +58,8 @@ class TrainConfig:
     iters: int = 5000
     prune_frac: float = 0.6
     lr: float = 1e-3
+    lr_schedule: str = "constant"     # "cosine": after the last pruning event, decay to lr_final by a half cosine
+    lr_final: float = 1e-4
     powers_dbm: Sequence[float] = (2.0, 3.0, 4.0)
     alpha_db_km: float = 0.2
     beta2_ps2_km: float = -21.683
@@ -232,6 +234,18 @@ class Trainer:
                       plan=(S, 0, 0, sym) if ck is None else (0, 0, 0, sym))
         return z, ck
 
+    def learning_rate(self, it: int) -> float:
+        """Adam step size at iteration `it` (constant, or a half-cosine decay from the last pruning event
+        to the end of training)."""
+        cfg = self.cfg
+        if cfg.lr_schedule != "cosine":
+            return cfg.lr
+        t0 = self.plan[-1][0] if self.plan else 0
+        if it < t0 or cfg.iters <= t0:
+            return cfg.lr
+        f = min(1.0, (it - t0) / (cfg.iters - t0))
+        return cfg.lr_final + 0.5 * (cfg.lr - cfg.lr_final) * (1.0 + math.cos(math.pi * f))
+
     def step(self):
         """One training iteration; returns the batch loss (mean MSE over frames)."""
         cfg = self.cfg
@@ -252,13 +266,14 @@ class Trainer:
             _, gt, gc = L.ldbp_backward(r, self.taps, self.c, self.ntap, gz, npol=cfg.npol, ckpt=ck, ckpt_every=S,
                                         need_gx=False, symmetric=cfg.symmetric)
         self.t += 1
+        lr = self.learning_rate(self.it)
         if cfg.train_taps:
-            TX.adam_(self.taps, gt, self.m_t, self.v_t, self.t, lr=cfg.lr,
+            TX.adam_(self.taps, gt, self.m_t, self.v_t, self.t, lr=lr,
                      mirror=self.mirror() if cfg.symmetric else None)
         if cfg.train_c:
-            TX.adam_(self.c, gc, self.m_c, self.v_c, self.t, lr=cfg.lr, mask=self.c_mask)
+            TX.adam_(self.c, gc, self.m_c, self.v_c, self.t, lr=lr, mask=self.c_mask)
         if self.essm:
-            TX.adam_(self.eta, ge, self.m_e, self.v_e, self.t, lr=cfg.lr)
+            TX.adam_(self.eta, ge, self.m_e, self.v_e, self.t, lr=lr)
         loss = float(mse.mean().item())
         self.history.append({"it": self.it, "loss": loss, "taps": int(sum(self.ntap))})
         self.it += 1

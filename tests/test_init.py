@@ -135,3 +135,21 @@ def test_symmetric_ssm_initialisation_matches_the_oracle_design():
         np.testing.assert_allclose(h, D.truncated_idft_taps(D.xi_of(dm, beta2, fs), T), atol=1e-12)
     for i, (d, z0) in enumerate(plan):
         assert abs(c[i] - D.kerr_coef(d, z0, alpha, gamma)) <= 1e-15 * abs(c[i])
+
+
+def test_cosine_learning_rate_after_pruning():
+    """The optional schedule: constant through the pruning events, then a half cosine to lr_final."""
+    cfg = T.TrainConfig(iters=1000, t_init=9, t_final=5, nspan=2, ldbp_steps=1, lr=1e-3, lr_final=1e-4,
+                        lr_schedule="cosine")
+    plan = T.pruning_plan([9, 9], [5, 5], cfg.iters, cfg.prune_frac)
+    t0 = plan[-1][0]
+
+    class _Stub:
+        pass
+    tr = _Stub()
+    tr.cfg, tr.plan = cfg, plan
+    lr = lambda it: T.Trainer.learning_rate(tr, it)  # noqa: E731
+    assert lr(0) == lr(t0 - 1) == 1e-3
+    assert abs(lr(t0) - 1e-3) < 1e-15 and abs(lr(1000) - 1e-4) < 1e-15
+    assert abs(lr((t0 + 1000) // 2) - 0.5 * (1e-3 + 1e-4)) < 2e-6
+    assert all(lr(a) >= lr(a + 1) for a in range(t0, 1000))
