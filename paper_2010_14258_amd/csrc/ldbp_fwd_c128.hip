@@ -3,18 +3,22 @@
 
 namespace ldbp {
 
+#define LDBP_FWD_ARGS x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em
+
 int launch_fwd_pass_c128(int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                          const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
                          hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em) {
   if (npol == 1 && rb == 3)
-    return launch_fwd_pass_t<double, 1, 3>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
+    return launch_fwd_pass_t<double, 1, 3>(LDBP_FWD_ARGS);
   if (npol == 1 && rb == 4)
-    return launch_fwd_pass_t<double, 1, 4>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
+    return launch_fwd_pass_t<double, 1, 4>(LDBP_FWD_ARGS);
   if (npol == 2 && rb == 1)
-    return launch_fwd_pass_t<double, 2, 1>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
+    return launch_fwd_pass_t<double, 2, 1>(LDBP_FWD_ARGS);
   if (npol == 2 && rb == 2)
-    return launch_fwd_pass_t<double, 2, 2>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
+    return launch_fwd_pass_t<double, 2, 2>(LDBP_FWD_ARGS);
   return fail(LDBP_EUNSUPPORTED, "outputs per thread %d not available for this dtype/npol", rb);
 }
+
+#undef LDBP_FWD_ARGS
 
 }  // namespace ldbp

@@ -19,7 +19,8 @@ from .ldbp import _check_dev, _code, _plan, _ptr, _real_dtype, _shape, stream_ha
 def _check_model(ntap, nl_ntap, taps, c, eta):
     if len(nl_ntap) != len(ntap):
         raise ValueError("nl_ntap must have one entry per step")
-    if taps.numel() != sum(int(t) for t in ntap) or c.numel() != len(ntap) or eta.numel() != sum(int(t) for t in nl_ntap):
+    if (taps.numel() != sum(int(t) for t in ntap) or c.numel() != len(ntap)
+            or eta.numel() != sum(int(t) for t in nl_ntap)):
         raise ValueError("taps/c/eta sizes do not match ntap/nl_ntap")
 
 

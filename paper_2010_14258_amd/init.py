@@ -159,10 +159,12 @@ def ldbp_parameters_symmetric(span_len: float, nspan: int, steps_per_span: int, 
     """Symmetric-SSM LDBP (Sec. III-C, IV-C): M = nspan * steps_per_span nonlinear steps and l = M + 1
     linear ones -- the first and last half-steps and, between nonlinear steps, the merged halves of the
     two neighbouring steps -- so the model's last step is linear only (c_l = 0).  Returns (taps, c)."""
-    steps = log_step_sizes(span_len, steps_per_span, alpha) if log_steps else [span_len / steps_per_span] * steps_per_span
+    steps = (log_step_sizes(span_len, steps_per_span, alpha) if log_steps
+             else [span_len / steps_per_span] * steps_per_span)
     sched = backprop_schedule(span_len, nspan, steps)
     deltas = [d for d, _ in sched]
-    merged = [deltas[0] / 2.0] + [(deltas[i - 1] + deltas[i]) / 2.0 for i in range(1, len(deltas))] + [deltas[-1] / 2.0]
+    merged = ([deltas[0] / 2.0] + [(deltas[i - 1] + deltas[i]) / 2.0 for i in range(1, len(deltas))]
+              + [deltas[-1] / 2.0])
     L = len(merged)
     ts = [int(ntap)] * L if np.isscalar(ntap) else [int(t) for t in ntap]
     taps = []
@@ -209,7 +211,8 @@ def ldbp_parameters(span_len: float, nspan: int, steps_per_span: int, ntap, fs: 
     unit_taps: unit filters; random_seed (int): random filters (see random_filter) instead of the fit;
     method "multiobjective": the in-band fits refined jointly by multi_objective_taps (runs of up to
     mo_window filters, mo_sweeps passes)."""
-    steps = log_step_sizes(span_len, steps_per_span, alpha) if log_steps else [span_len / steps_per_span] * steps_per_span
+    steps = (log_step_sizes(span_len, steps_per_span, alpha) if log_steps
+             else [span_len / steps_per_span] * steps_per_span)
     sched = backprop_schedule(span_len, nspan, steps)
     L = len(sched)
     ts = [int(ntap)] * L if np.isscalar(ntap) else [int(t) for t in ntap]
