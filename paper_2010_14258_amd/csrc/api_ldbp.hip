@@ -560,7 +560,7 @@ struct BwdLayout {
   int32_t ncols;     // sum T + sum(power-filter lengths) + l
   int32_t ntaps;     // sum T
   int32_t neta;      // sum of the power-filter lengths (0 for LDBP)
-  size_t off_ckpt, off_g0, off_g1, off_part, total;
+  size_t off_ckpt, off_g0, off_g1, off_part, off_chunks, total;
 };
 
 static int default_bwd_S(const ModelArgs& m) { return std::min<int32_t>(m.nstep, m.dtype == LDBP_C64 ? 2 : 3); }
@@ -585,6 +585,8 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
                 L.S);
   L.tile_len = best;
   L.ntiles = m.nwave * ((m.n + best - 1) / best);
+  if (grad_reduce_chunks(L.ntiles) > 65535)
+    return fail(LDBP_EUNSUPPORTED, "%lld backward tiles exceed the gradient reduction's grid", (long long)L.ntiles);
   L.ntaps = 0;
   L.neta = 0;
   for (int i = 0; i < m.nstep; ++i) {
@@ -603,6 +605,8 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
   off += align256(wave_bytes);
   L.off_part = off;
   off += align256(static_cast<size_t>(L.ntiles) * L.ncols * sizeof(double) * 2);
+  L.off_chunks = off;
+  off += align256(static_cast<size_t>(grad_reduce_chunks(L.ntiles)) * L.ncols * sizeof(double) * 2);
   L.total = off;
   return LDBP_OK;
 }
@@ -703,7 +707,7 @@ static int backward_impl(const ModelArgs& m, const void* taps, const void* c, co
     return static_cast<int>(LDBP_OK);
   });
   if (st) return st;
-  return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s, L.neta, geta);
+  return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s, L.neta, geta, wsb + L.off_chunks);
 }
 
 }  // namespace ldbp

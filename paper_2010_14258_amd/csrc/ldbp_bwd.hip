@@ -401,6 +401,10 @@ __device__ __forceinline__ void eta_grad(const R* __restrict__ Q, const R* __res
   }
 }
 
+// Zeroed entries of Q and PP past the filled range, read by the fixed-kappa windows (RBF - 1 of them at
+// most); they fit in the arrays' padding for complex64 (pad 8).
+constexpr int kFiltTail = 8;
+
 // Adjoint of the filtered phase of one step over G indices [lo + kap, hi - kap), with q = dL/dphi in Q
 // and P = |y|^2 in PP, both filled on [lo, hi):
 //   F_i = sum_k eta_k P_{i-k},  r_i = c sum_k eta_k q_{i+k},  G_u,i = (G_y,i + 2 r_i y_i) e^{-j c F_i};
@@ -438,8 +442,8 @@ __device__ __forceinline__ R nl_adjoint_generic(const cx_t<R>* __restrict__ ycur
 
 // Fixed kappa: RBF (odd) consecutive samples per thread from register windows of P and q (2 (RBF + 2 kappa)
 // LDS reads for RBF samples instead of 2 (2 kappa + 1) each), the filter taps uniform (scalar
-// registers).  Window entries outside [lo, hi) are read as zero, so LDS left over from other data
-// never enters a sum.
+// registers).  Windows reach up to hi + RBF - 2; the caller zeroes Q and PP on [hi, hi + kFiltTail), so
+// no LDS left over from other data enters a sum.
 template <typename R, int NPOL, int THREADS, int KAP>
 __device__ __forceinline__ R nl_adjoint_fixed(const cx_t<R>* __restrict__ ycur, int yoff, const cx_t<R>* __restrict__ GA,
                                               cx_t<R>* __restrict__ GB, const R* __restrict__ Q,
@@ -447,6 +451,7 @@ __device__ __forceinline__ R nl_adjoint_fixed(const cx_t<R>* __restrict__ ycur, 
                                               R cr, R coef, int own_lo, int own_hi) {
   using V = cx_t<R>;
   constexpr int RBF = 7;  // odd: lanes RBF words apart fall on distinct LDS banks
+  static_assert(RBF - 1 <= kFiltTail, "windows must stay inside the zeroed tail");
   constexpr int W = RBF + 2 * KAP;
   R accc = 0;
   const int lo2 = lo + KAP, hi2 = hi - KAP;
@@ -456,10 +461,7 @@ __device__ __forceinline__ R nl_adjoint_fixed(const cx_t<R>* __restrict__ ycur, 
     {
       R w[W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int m = base - KAP + j;
-        w[j] = m < hi ? PP[m] : R(0);
-      }
+      for (int j = 0; j < W; ++j) w[j] = PP[base - KAP + j];
 #pragma unroll
       for (int r = 0; r < RBF; ++r) F[r] = 0;
 #pragma unroll
@@ -472,10 +474,7 @@ __device__ __forceinline__ R nl_adjoint_fixed(const cx_t<R>* __restrict__ ycur, 
     {
       R w[W];
 #pragma unroll
-      for (int j = 0; j < W; ++j) {
-        const int m = base - KAP + j;
-        w[j] = m < hi ? Q[m] : R(0);
-      }
+      for (int j = 0; j < W; ++j) w[j] = Q[base - KAP + j];
 #pragma unroll
       for (int r = 0; r < RBF; ++r) {
         rr[r] = 0;
@@ -534,6 +533,7 @@ template <typename R, int THREADS, int KAP>
 __device__ __forceinline__ void eta_grad_fixed(const R* __restrict__ Q, const R* __restrict__ PP, int own_lo, int Lw,
                                                double2* __restrict__ red, int ldr, int col0) {
   constexpr int RBF = 7;  // odd: lanes RBF words apart fall on distinct LDS banks
+  static_assert(RBF - 1 <= kFiltTail, "windows must stay inside the zeroed tail");
   constexpr int NE = 2 * KAP + 1;
   constexpr int W = RBF + 2 * KAP;
   const int own_hi = own_lo + Lw;
@@ -543,10 +543,7 @@ __device__ __forceinline__ void eta_grad_fixed(const R* __restrict__ Q, const R*
   for (int base = own_lo + static_cast<int>(threadIdx.x) * RBF; base < own_hi; base += THREADS * RBF) {
     R wp[W], q[RBF];
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int m = base - KAP + j;
-      wp[j] = m < own_hi + KAP ? PP[m] : R(0);
-    }
+    for (int j = 0; j < W; ++j) wp[j] = PP[base - KAP + j];   // below hi + kFiltTail (zeroed beyond hi)
 #pragma unroll
     for (int r = 0; r < RBF; ++r) q[r] = base + r < own_hi ? Q[base + r] : R(0);
 #pragma unroll
@@ -692,6 +689,12 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
         Q[i] = q;
         PP[i] = pw;
       }
+      if constexpr (sizeof(R) == 4) {
+        if (static_cast<int>(threadIdx.x) < kFiltTail) {
+          Q[hi + threadIdx.x] = 0;
+          PP[hi + threadIdx.x] = 0;
+        }
+      }
       __syncthreads();
       accc = nl_adjoint_dispatch<R, NPOL, THREADS>(ycur, yoff, GA, GB, Q, PP, lo, hi, kp, eta + pt.etaoff[s - 1], cr,
                                                    coef, H, H + Lw);
@@ -764,33 +767,56 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
 }
 
 // Sums part[tile][col] over tiles in a fixed order; one workgroup per column.
+// Deterministic reduction of the per-tile partial sums part[tile][col] in two fixed-order stages.
+// Stage 1: block (column group of 16, chunk of kReduceRows tiles); thread (g, c) sums tiles
+// chunk*kReduceRows + g + 16 j in increasing j, so each row of 16 columns is one 256-byte read, then
+// the 16 row lanes are added in order g = 0..15 into chunk_sums[chunk][col].
+constexpr int kReduceRows = 256;
+
+__global__ __launch_bounds__(256) void ldbp_grad_reduce_chunks(const double2* __restrict__ part, int64_t ntiles,
+                                                               int32_t ncols, double2* __restrict__ chunk_sums) {
+  __shared__ double2 acc[16][17];
+  const int c = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int col = blockIdx.x * 16 + c;
+  const int64_t t0 = static_cast<int64_t>(blockIdx.y) * kReduceRows;
+  const int64_t t1 = min(t0 + kReduceRows, ntiles);
+  double ax = 0, ay = 0;
+  if (col < ncols) {
+    for (int64_t t = t0 + g; t < t1; t += 16) {
+      const double2 v = part[t * ncols + col];
+      ax += v.x;
+      ay += v.y;
+    }
+  }
+  acc[g][c] = double2{ax, ay};
+  __syncthreads();
+  if (g == 0 && col < ncols) {
+    double sx = 0, sy = 0;
+    for (int k = 0; k < 16; ++k) {
+      sx += acc[k][c].x;
+      sy += acc[k][c].y;
+    }
+    chunk_sums[static_cast<int64_t>(blockIdx.y) * ncols + col] = double2{sx, sy};
+  }
+}
+
+// Stage 2: one thread per column adds the chunk sums in chunk order and stores the gradient
+// (columns: taps, then power filters, then Kerr coefficients).
 template <typename R>
-__global__ __launch_bounds__(256) void ldbp_grad_reduce(const double2* __restrict__ part, int64_t ntiles,
+__global__ __launch_bounds__(256) void ldbp_grad_reduce(const double2* __restrict__ chunk_sums, int64_t nchunks,
                                                         int32_t ncols, int32_t ntaps, cx_t<R>* __restrict__ gtaps,
                                                         R* __restrict__ gc, int32_t neta, R* __restrict__ geta) {
-  __shared__ double sx[256], sy[256];
-  const int col = blockIdx.x;
-  double ax = 0, ay = 0;
-  for (int64_t t = threadIdx.x; t < ntiles; t += 256) {
-    const double2 v = part[t * ncols + col];
-    ax += v.x;
-    ay += v.y;
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= ncols) return;
+  double sx = 0, sy = 0;
+  for (int64_t k = 0; k < nchunks; ++k) {
+    const double2 v = chunk_sums[k * ncols + col];
+    sx += v.x;
+    sy += v.y;
   }
-  sx[threadIdx.x] = ax;
-  sy[threadIdx.x] = ay;
-  __syncthreads();
-  for (int off = 128; off > 0; off >>= 1) {
-    if (static_cast<int>(threadIdx.x) < off) {
-      sx[threadIdx.x] += sx[threadIdx.x + off];
-      sy[threadIdx.x] += sy[threadIdx.x + off];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (col < ntaps) gtaps[col] = cx_t<R>{static_cast<R>(sx[0]), static_cast<R>(sy[0])};
-    else if (col < ntaps + neta) geta[col - ntaps] = static_cast<R>(sx[0]);
-    else gc[col - ntaps - neta] = static_cast<R>(sx[0]);
-  }
+  if (col < ntaps) gtaps[col] = cx_t<R>{static_cast<R>(sx), static_cast<R>(sy)};
+  else if (col < ntaps + neta) geta[col - ntaps] = static_cast<R>(sx);
+  else gc[col - ntaps - neta] = static_cast<R>(sx);
 }
 
 // ---------------------------------------------------------------- host side
@@ -861,15 +887,23 @@ int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void
 #undef LDBP_BWD_ARGS
 }
 
+int64_t grad_reduce_chunks(int64_t ntiles) { return (ntiles + kReduceRows - 1) / kReduceRows; }
+
 int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,
-                       void* gc, hipStream_t stream, int32_t neta, void* geta) {
+                       void* gc, hipStream_t stream, int32_t neta, void* geta, void* chunk_sums) {
+  const int64_t nchunks = grad_reduce_chunks(ntiles);
+  if (nchunks > 65535) return fail(LDBP_EUNSUPPORTED, "too many tiles (%lld) for the gradient reduction", (long long)ntiles);
+  hipLaunchKernelGGL(ldbp_grad_reduce_chunks, dim3((ncols + 15) / 16, static_cast<uint32_t>(nchunks)), dim3(256), 0,
+                     stream, static_cast<const double2*>(part), ntiles, ncols, static_cast<double2*>(chunk_sums));
+  LDBP_HIP_CHECK(hipGetLastError());
+  const dim3 grid((ncols + 255) / 256);
   if (dtype == LDBP_C64)
-    hipLaunchKernelGGL(ldbp_grad_reduce<float>, dim3(ncols), dim3(256), 0, stream,
-                       static_cast<const double2*>(part), ntiles, ncols, ntaps, static_cast<float2*>(gtaps),
+    hipLaunchKernelGGL(ldbp_grad_reduce<float>, grid, dim3(256), 0, stream,
+                       static_cast<const double2*>(chunk_sums), nchunks, ncols, ntaps, static_cast<float2*>(gtaps),
                        static_cast<float*>(gc), neta, static_cast<float*>(geta));
   else
-    hipLaunchKernelGGL(ldbp_grad_reduce<double>, dim3(ncols), dim3(256), 0, stream,
-                       static_cast<const double2*>(part), ntiles, ncols, ntaps, static_cast<double2*>(gtaps),
+    hipLaunchKernelGGL(ldbp_grad_reduce<double>, grid, dim3(256), 0, stream,
+                       static_cast<const double2*>(chunk_sums), nchunks, ncols, ntaps, static_cast<double2*>(gtaps),
                        static_cast<double*>(gc), neta, static_cast<double*>(geta));
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;

@@ -65,7 +65,9 @@ int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
                      int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream, const void* eta = nullptr,
                      int32_t ecol_base = 0);
+// Two fixed-order stages through chunk_sums (grad_reduce_chunks(ntiles) x ncols double2).
+int64_t grad_reduce_chunks(int64_t ntiles);
 int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,
-                       void* gc, hipStream_t stream, int32_t neta = 0, void* geta = nullptr);
+                       void* gc, hipStream_t stream, int32_t neta, void* geta, void* chunk_sums);
 
 }  // namespace ldbp
