@@ -195,6 +195,45 @@ __device__ __forceinline__ void nl_filter_fixed(cx_t<R>* __restrict__ u, const R
   }
 }
 
+// Runtime kappa <= KMAX with the register-window structure of nl_filter_fixed<KMAX>: the window is laid
+// out for KMAX and only its entries within kappa of the outputs are loaded; taps beyond kappa are
+// skipped (uniform branches), so every register index is a compile-time constant.
+template <typename R, int NPOL, int RB, int THREADS, int KMAX>
+__device__ __forceinline__ void nl_filter_win(cx_t<R>* __restrict__ u, const R* __restrict__ pw, int lo, int hi,
+                                              int kap, const R* __restrict__ eta, R coef) {
+  using V = cx_t<R>;
+  constexpr int W = RB + 2 * KMAX;
+  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
+    R win[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      if (j >= KMAX - kap && j < KMAX + kap + RB) win[j] = pw[base - KMAX + j];
+    }
+    R F[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) F[r] = 0;
+#pragma unroll
+    for (int k = -KMAX; k <= KMAX; ++k) {
+      if (k < -kap || k > kap) continue;
+      const R e = eta[kap + k];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) F[r] = fma(e, win[r - k + KMAX], F[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (base + r < hi) {
+        R s, co;
+        phase_sincos(coef, F[r], s, co);
+#pragma unroll
+        for (int p = 0; p < NPOL; ++p) {
+          const V a = u[(base + r) * NPOL + p];
+          u[(base + r) * NPOL + p] = V{a.x * co - a.y * s, a.x * s + a.y * co};
+        }
+      }
+    }
+  }
+}
+
 template <typename R, int NPOL, int RB, int THREADS>
 __device__ __forceinline__ void nl_filter_generic(cx_t<R>* __restrict__ u, const R* __restrict__ pw, int lo, int hi,
                                                   int kap, const R* __restrict__ eta, R coef) {
@@ -221,7 +260,10 @@ __device__ __forceinline__ void nl_filter_dispatch(cx_t<R>* u, const R* pw, int 
     LDBP_NL_CASE(0) LDBP_NL_CASE(1) LDBP_NL_CASE(2) LDBP_NL_CASE(3) LDBP_NL_CASE(4) LDBP_NL_CASE(5)
     LDBP_NL_CASE(6) LDBP_NL_CASE(8) LDBP_NL_CASE(10) LDBP_NL_CASE(12) LDBP_NL_CASE(16) LDBP_NL_CASE(20)
 #undef LDBP_NL_CASE
-    default: nl_filter_generic<R, NPOL, RB, THREADS>(u, pw, lo, hi, kap, eta, coef); break;
+    default:
+      if (kap < 20) nl_filter_win<R, NPOL, RB, THREADS, 20>(u, pw, lo, hi, kap, eta, coef);
+      else nl_filter_generic<R, NPOL, RB, THREADS>(u, pw, lo, hi, kap, eta, coef);
+      break;
   }
 }
 
