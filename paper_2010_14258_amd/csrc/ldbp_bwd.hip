@@ -509,76 +509,6 @@ __device__ __forceinline__ R nl_adjoint_fixed(const cx_t<R>* __restrict__ ycur, 
   return accc;
 }
 
-// Runtime kappa <= KMAX with the structure of nl_adjoint_fixed<KMAX>: windows laid out for KMAX, only
-// the entries within kappa of the outputs loaded, taps beyond kappa skipped (uniform branches).
-template <typename R, int NPOL, int THREADS, int KMAX>
-__device__ __forceinline__ R nl_adjoint_win(const cx_t<R>* __restrict__ ycur, int yoff, const cx_t<R>* __restrict__ GA,
-                                            cx_t<R>* __restrict__ GB, const R* __restrict__ Q,
-                                            const R* __restrict__ PP, int lo, int hi, int kap,
-                                            const R* __restrict__ e, R cr, R coef, int own_lo, int own_hi) {
-  using V = cx_t<R>;
-  constexpr int RBF = 7;
-  static_assert(RBF - 1 <= kFiltTail, "windows must stay inside the zeroed tail");
-  constexpr int W = RBF + 2 * KMAX;
-  R accc = 0;
-  const int lo2 = lo + kap, hi2 = hi - kap;
-  for (int base = lo2 + static_cast<int>(threadIdx.x) * RBF; base < hi2; base += THREADS * RBF) {
-    R F[RBF], rr[RBF], qo[RBF];
-    {
-      R w[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j)
-        if (j >= KMAX - kap && j < KMAX + kap + RBF) w[j] = PP[base - KMAX + j];
-#pragma unroll
-      for (int r = 0; r < RBF; ++r) F[r] = 0;
-#pragma unroll
-      for (int k = -KMAX; k <= KMAX; ++k) {
-        if (k < -kap || k > kap) continue;
-        const R ek = e[kap + k];
-#pragma unroll
-        for (int r = 0; r < RBF; ++r) F[r] = fma(ek, w[r - k + KMAX], F[r]);
-      }
-    }
-    {
-      R w[W];
-#pragma unroll
-      for (int j = 0; j < W; ++j)
-        if (j >= KMAX - kap && j < KMAX + kap + RBF) w[j] = Q[base - KMAX + j];
-#pragma unroll
-      for (int r = 0; r < RBF; ++r) {
-        rr[r] = 0;
-        qo[r] = w[r + KMAX];
-      }
-#pragma unroll
-      for (int k = -KMAX; k <= KMAX; ++k) {
-        if (k < -kap || k > kap) continue;
-        const R ek = e[kap + k];
-#pragma unroll
-        for (int r = 0; r < RBF; ++r) rr[r] = fma(ek, w[r + k + KMAX], rr[r]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RBF; ++r) {
-      const int i = base + r;
-      if (i < hi2) {
-        R sn, co;
-        phase_sincos(coef, F[r], sn, co);
-        const R tr = 2 * cr * rr[r];
-#pragma unroll
-        for (int pp = 0; pp < NPOL; ++pp) {
-          const V yv = ycur[(i + yoff) * NPOL + pp];
-          const V gv = GA[i * NPOL + pp];
-          const R tx = gv.x + tr * yv.x;
-          const R ty = gv.y + tr * yv.y;
-          GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
-        }
-        if (i >= own_lo && i < own_hi) accc += qo[r] * F[r];
-      }
-    }
-  }
-  return accc;
-}
-
 template <typename R, int NPOL, int THREADS>
 __device__ __forceinline__ R nl_adjoint_dispatch(const cx_t<R>* ycur, int yoff, const cx_t<R>* GA, cx_t<R>* GB,
                                                  const R* Q, const R* PP, int lo, int hi, int kap, const R* e, R cr,
@@ -590,11 +520,7 @@ __device__ __forceinline__ R nl_adjoint_dispatch(const cx_t<R>* ycur, int yoff, 
       LDBP_NLA_CASE(0) LDBP_NLA_CASE(1) LDBP_NLA_CASE(2) LDBP_NLA_CASE(3) LDBP_NLA_CASE(4) LDBP_NLA_CASE(5) LDBP_NLA_CASE(6)
       LDBP_NLA_CASE(8) LDBP_NLA_CASE(10) LDBP_NLA_CASE(12) LDBP_NLA_CASE(16) LDBP_NLA_CASE(20)
 #undef LDBP_NLA_CASE
-      default:
-        if (kap < 20)
-          return nl_adjoint_win<R, NPOL, THREADS, 20>(ycur, yoff, GA, GB, Q, PP, lo, hi, kap, e, cr, coef, own_lo,
-                                                      own_hi);
-        break;
+      default: break;
     }
   }
   return nl_adjoint_generic<R, NPOL, THREADS>(ycur, yoff, GA, GB, Q, PP, lo, hi, kap, e, cr, coef, own_lo, own_hi);
@@ -638,46 +564,6 @@ __device__ __forceinline__ void eta_grad_fixed(const R* __restrict__ Q, const R*
   }
 }
 
-// Runtime kappa <= KMAX with the structure of eta_grad_fixed<KMAX>.
-template <typename R, int THREADS, int KMAX>
-__device__ __forceinline__ void eta_grad_win(const R* __restrict__ Q, const R* __restrict__ PP, int own_lo, int Lw,
-                                             int kap, double2* __restrict__ red, int ldr, int col0) {
-  constexpr int RBF = 7;
-  static_assert(RBF - 1 <= kFiltTail, "windows must stay inside the zeroed tail");
-  constexpr int NE = 2 * KMAX + 1;
-  constexpr int W = RBF + 2 * KMAX;
-  const int own_hi = own_lo + Lw;
-  R g[NE];
-#pragma unroll
-  for (int k = 0; k < NE; ++k) g[k] = 0;
-  for (int base = own_lo + static_cast<int>(threadIdx.x) * RBF; base < own_hi; base += THREADS * RBF) {
-    R wp[W], q[RBF];
-#pragma unroll
-    for (int j = 0; j < W; ++j)
-      if (j >= KMAX - kap && j < KMAX + kap + RBF) wp[j] = PP[base - KMAX + j];
-#pragma unroll
-    for (int r = 0; r < RBF; ++r) q[r] = base + r < own_hi ? Q[base + r] : R(0);
-#pragma unroll
-    for (int k = -KMAX; k <= KMAX; ++k) {
-      if (k < -kap || k > kap) continue;
-#pragma unroll
-      for (int r = 0; r < RBF; ++r) g[KMAX + k] = fma(q[r], wp[r - k + KMAX], g[KMAX + k]);
-    }
-  }
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-#pragma unroll
-  for (int g0 = 0; g0 < NE; g0 += 16) {
-    float vals[16];
-#pragma unroll
-    for (int j = 0; j < 16; ++j) vals[j] = g0 + j < NE ? g[g0 + j] : 0.f;
-    const float tot = wave_reduce_multi<16>(vals, lane);
-    const int k = g0 + reduce_index<16>(lane) - KMAX;   // tap offset of this lane's total
-    if (reduce_owner<16>(lane) && k >= -kap && k <= kap)
-      red[wv * ldr + col0 + kap + k] = double2{static_cast<double>(tot), 0.0};
-  }
-}
-
 template <typename R, int THREADS>
 __device__ __forceinline__ void eta_grad_dispatch(const R* Q, const R* PP, int own_lo, int Lw, int kap,
                                                   double2* red, int ldr, int col0) {
@@ -688,12 +574,7 @@ __device__ __forceinline__ void eta_grad_dispatch(const R* Q, const R* PP, int o
       LDBP_EG_CASE(0) LDBP_EG_CASE(1) LDBP_EG_CASE(2) LDBP_EG_CASE(3) LDBP_EG_CASE(4) LDBP_EG_CASE(5) LDBP_EG_CASE(6)
       LDBP_EG_CASE(8) LDBP_EG_CASE(10) LDBP_EG_CASE(12) LDBP_EG_CASE(16) LDBP_EG_CASE(20)
 #undef LDBP_EG_CASE
-      default:
-        if (kap < 20) {
-          eta_grad_win<R, THREADS, 20>(Q, PP, own_lo, Lw, kap, red, ldr, col0);
-          return;
-        }
-        break;
+      default: break;
     }
   }
   eta_grad<R>(Q, PP, own_lo, Lw, kap, red, ldr, col0, THREADS);
