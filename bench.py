@@ -489,7 +489,7 @@ def essm_trained(torch, dev, iters: int, powers, kappa: int = 20, ntaps: int = 1
 
 
 def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_at=None, train_c: bool = True,
-               lr_schedule: str = "constant"):
+               lr_schedule: str = "constant", prune_frac: float = 0.6):
     """The paper's first scenario (Sec. V-A) at reduced training length: 10.7 GBd over 25 x 80 km,
     LDBP on the asymmetric split-step with one step per span (l = 25), symmetric filters pruned from 9
     taps to alternating 5 and 3 taps (overall impulse response 13 * 4 + 12 * 2 + 1 = 77 taps),
@@ -506,7 +506,7 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
     cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=4, rho_d=2, nspan=25, span_km=80.0, channel_steps=50,
                           ldbp_steps=1, t_init=9, t_final=5, t_final_alt=3, iters=iters,
                           powers_dbm=(-2.0, -1.0, 0.0, 1.0), symbols="gauss", seed=1101, train_c=train_c,
-                          lr_schedule=lr_schedule)
+                          lr_schedule=lr_schedule, prune_frac=prune_frac)
     trn = TRN.Trainer(cfg, device=dev)
     if resume:
         trn.load(resume)
@@ -542,7 +542,7 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
     resp = 1 + sum(t - 1 for t in trn.ntap)
     peak = {k: max(r[k] for r in rows) for k in rows[0] if k.endswith("_snr_db")}
     return {"workload": "10.7 GBd, 25 x 80 km SSMF, Gaussian symbols, LDBP l = 25 (1 step per span), 9 -> 5/3 taps",
-            "train_kerr_coefficients": train_c, "lr_schedule": lr_schedule,
+            "train_kerr_coefficients": train_c, "lr_schedule": lr_schedule, "prune_frac": prune_frac,
             "train_iterations": iters, "train_seconds_last_call": train_s, "final_ntap": list(trn.ntap),
             "impulse_response_taps": resp, "loss_curve": curve, "by_power": rows, "peak_snr_db": peak,
             "paper_context": {"ldbp_peak_snr_db": 23.5, "penalty_vs_fd_dbp_1stps_db": 2.0,
@@ -658,6 +658,8 @@ def main():
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
     ap.add_argument("--fixed-c", action="store_true", help="--mode e1: keep the Kerr coefficients fixed")
+    ap.add_argument("--prune-frac", type=float, default=0.6,
+                    help="--mode e1: fraction of the iterations over which the pruning events fall")
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"],
                     help="--mode e1: Adam step size; cosine: decay to 1e-4 after the last pruning event")
     ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
@@ -702,7 +704,7 @@ def main():
     if args.mode == "e1":
         out = e1_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
                          os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, not args.fixed_c,
-                         args.lr_schedule)
+                         args.lr_schedule, args.prune_frac)
         print(json.dumps(out), flush=True)
         return
     if args.mode == "e8":
