@@ -1,4 +1,5 @@
-// C ABI of the LDBP forward (and, later, backward): validation, planning, pass sequencing.
+// C ABI of the LDBP and generalised-ESSM forward (periodic, checkpointed, aperiodic) and backward:
+// validation, planning, pass sequencing and the batch split over a second stream.
 #include <algorithm>
 #include <cstdlib>
 #include <vector>

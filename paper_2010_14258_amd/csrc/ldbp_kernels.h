@@ -1,4 +1,4 @@
-// Internal launch interface between the C ABI (api.hip) and the kernel files.
+// Internal launch interface between the C ABI (api_ldbp.hip) and the kernel files.
 #pragma once
 
 #include <hip/hip_runtime.h>
