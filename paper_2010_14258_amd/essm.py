@@ -117,3 +117,34 @@ def essm_backward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, eta: tor
                               _ptr(gtaps), _ptr(gc), _ptr(geta), ctypes.byref(pl), _ptr(ws), ws.numel(),
                               stream_handle(stream, x.device)))
     return gx, gtaps, gc, geta
+
+
+class ESSMFunction(torch.autograd.Function):
+    """y = f_theta(x) of the generalised ESSM with the hand-written adjoint; checkpoints every
+    ``ckpt_every`` steps.  Gradients flow to x, taps, c and eta.
+
+    apply(x, taps, c, eta, ntap, nl_ntap, npol, ckpt_every) -> y
+    """
+
+    @staticmethod
+    def forward(ctx, x, taps, c, eta, ntap, nl_ntap, npol=1, ckpt_every=5):
+        from .ldbp import num_checkpoints
+        ntap = [int(t) for t in ntap]
+        nl_ntap = [int(t) for t in nl_ntap]
+        S = max(1, min(int(ckpt_every), len(ntap)))
+        nslot = num_checkpoints(len(ntap), S)
+        ckpt = torch.empty((nslot,) + tuple(x.shape), dtype=x.dtype, device=x.device) if nslot else None
+        y = essm_forward(x.contiguous(), taps.contiguous(), c.contiguous(), eta.contiguous(), ntap, nl_ntap,
+                         npol=npol, ckpt=ckpt, ckpt_every=S if ckpt is not None else 0,
+                         plan=(S, 0) if ckpt is None else None)
+        ctx.save_for_backward(x, taps, c, eta, ckpt if ckpt is not None else torch.empty(0, device=x.device))
+        ctx.ntap, ctx.nl_ntap, ctx.npol, ctx.S, ctx.has_ckpt = ntap, nl_ntap, npol, S, ckpt is not None
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, taps, c, eta, ckpt = ctx.saved_tensors
+        gx, gt, gc, ge = essm_backward(x, taps, c, eta, ctx.ntap, ctx.nl_ntap, gy.contiguous(), npol=ctx.npol,
+                                       ckpt=ckpt if ctx.has_ckpt else None, ckpt_every=ctx.S,
+                                       need_gx=ctx.needs_input_grad[0])
+        return gx, gt, gc, ge, None, None, None, None

@@ -211,3 +211,26 @@ def test_essm_unit_filters_backward_equals_ldbp():
     rx, rt, rc = O.ldbp_grad(x, taps, c, gy)
     _cmp((gx, gt, gc), (rx, rt, rc), 1e-10)
     np.testing.assert_allclose([g[0] for g in ge], np.asarray(c) * rc, rtol=1e-9, atol=1e-12)
+
+
+def test_essm_autograd_function_matches_oracle():
+    """ESSMFunction: gradients of sum w |y|^2 for x, taps, c and eta through torch autograd."""
+    print("case: essm autograd", flush=True)
+    Ts = [9, 7, 5, 3, 9, 7]
+    taps, c, eta = _model(130, Ts, [3, 20, 0, 7, 1, 2])
+    x = synth.complex_normal(131, (2, 1500)) * 0.5
+    w = synth.rng(132).uniform(0.5, 1.5, size=x.shape)
+    tp, ntap = W.pack_taps(taps)
+    xt = torch.from_numpy(x).to(DEV, torch.complex64).requires_grad_(True)
+    tt = torch.from_numpy(tp).to(DEV, torch.complex64).requires_grad_(True)
+    ct = torch.from_numpy(np.asarray(c)).to(DEV, torch.float32).requires_grad_(True)
+    et = torch.from_numpy(np.concatenate(eta)).to(DEV, torch.float32).requires_grad_(True)
+    y = GE.ESSMFunction.apply(xt, tt, ct, et, ntap, [len(e) for e in eta], 1, 4)
+    loss = torch.sum(torch.from_numpy(w).to(DEV, torch.float32) * (y.abs() ** 2))
+    loss.backward()
+    yo = OE.essm_forward(x, taps, c, eta)
+    gx, gts, gc, ge = OE.essm_grad(x, taps, c, eta, 2 * w * yo)   # d/dy of sum w |y|^2 is 2 w y
+    assert _rel(xt.grad.cpu().numpy(), gx) <= 1e-4
+    assert _rel(tt.grad.cpu().numpy(), np.concatenate(gts)) <= 1e-4
+    assert _rel(ct.grad.cpu().numpy(), gc) <= 1e-4
+    assert _rel(et.grad.cpu().numpy(), np.concatenate(ge)) <= 1e-4
