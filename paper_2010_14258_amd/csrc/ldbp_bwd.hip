@@ -154,9 +154,7 @@ __device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx
   for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
     V win[W][NPOL];
 #pragma unroll
-    for (int j = 0; j < W; ++j)
-#pragma unroll
-      for (int p = 0; p < NPOL; ++p) win[j][p] = in[(base - K + j) * NPOL + p];
+    for (int j = 0; j < W; ++j) load_sample<R, NPOL>(in + (base - K + j) * NPOL, win[j]);
     V acc[RB][NPOL];
 #pragma unroll
     for (int r = 0; r < RB; ++r)

@@ -14,6 +14,21 @@ namespace ldbp {
 // An odd RB keeps the lanes' window starts on distinct LDS banks (stride RB * 8 bytes).
 // LIN: no phase; out receives u and pw[j] = |u_j|^2 (summed over polarisations), the input of a
 // filtered nonlinear step (nl_filter below).
+// The NPOL values of one sample from LDS.  Two complex64 polarisations are read as one 16-byte access
+// (a sample starts on a 16-byte boundary in every buffer): lanes RB samples apart then spread over all
+// banks, where the two 8-byte accesses the compiler would otherwise emit use half of them.
+template <typename R, int NPOL>
+__device__ __forceinline__ void load_sample(const cx_t<R>* __restrict__ src, cx_t<R> (&v)[NPOL]) {
+  if constexpr (NPOL == 2 && sizeof(R) == 4) {
+    const float4 q = *reinterpret_cast<const float4*>(src);
+    v[0] = float2{q.x, q.y};
+    v[1] = float2{q.z, q.w};
+  } else {
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) v[p] = src[p];
+  }
+}
+
 template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM, bool LIN = false>
 __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out,
                                                int lo, int hi, const cx_t<R>* __restrict__ h, R coef,
@@ -23,9 +38,7 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
   for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
     V win[W][NPOL];
 #pragma unroll
-    for (int j = 0; j < W; ++j)
-#pragma unroll
-      for (int p = 0; p < NPOL; ++p) win[j][p] = in[(base - K + j) * NPOL + p];
+    for (int j = 0; j < W; ++j) load_sample<R, NPOL>(in + (base - K + j) * NPOL, win[j]);
     V acc[RB][NPOL];
     if constexpr (SYM) {
       const V h0 = h[K];
