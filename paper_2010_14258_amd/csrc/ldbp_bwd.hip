@@ -246,24 +246,31 @@ __device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, in
   for (int k = 0; k < NA; ++k) acc[k] = V{0, 0};
   const int own_hi = own_lo + Lw;
   for (int jb = own_lo + static_cast<int>(threadIdx.x) * RB2; jb < own_hi; jb += THREADS * RB2) {
+    // both polarisations of a time sample in one load (one 16-byte LDS access for two complex64)
+    V win[W][NPOL];
 #pragma unroll
-    for (int p = 0; p < NPOL; ++p) {
-      V win[W];
+    for (int j = 0; j < W; ++j) load_sample<R, NPOL>(yprev + (jb + yshift - K + j) * NPOL, win[j]);
 #pragma unroll
-      for (int j = 0; j < W; ++j) win[j] = yprev[(jb + yshift - K + j) * NPOL + p];
+    for (int r = 0; r < RB2; ++r) {
+      V g[NPOL];
+      if (jb + r < own_hi) {
+        load_sample<R, NPOL>(gu + (jb + r) * NPOL, g);
+      } else {
 #pragma unroll
-      for (int r = 0; r < RB2; ++r) {
-        const V g = (jb + r < own_hi) ? gu[(jb + r) * NPOL + p] : V{0, 0};
+        for (int p = 0; p < NPOL; ++p) g[p] = V{0, 0};
+      }
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) {
         if constexpr (SYM) {
-          cmac_yconj(acc[0], g, win[r + K]);
+          cmac_yconj(acc[0], g[p], win[r + K][p]);
 #pragma unroll
           for (int k = 1; k <= K; ++k) {
-            const V a = win[r - k + K], b = win[r + k + K];
-            cmac_yconj(acc[k], g, V{a.x + b.x, a.y + b.y});
+            const V a = win[r - k + K][p], b = win[r + k + K][p];
+            cmac_yconj(acc[k], g[p], V{a.x + b.x, a.y + b.y});
           }
         } else {
 #pragma unroll
-          for (int k = -K; k <= K; ++k) cmac_yconj(acc[K + k], g, win[r - k + K]);
+          for (int k = -K; k <= K; ++k) cmac_yconj(acc[K + k], g[p], win[r - k + K][p]);
         }
       }
     }
