@@ -42,14 +42,17 @@ LDBP_STPS, TAPS = 5, 15
 P_DBM = 4.0
 RS = 10.7e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ldbp_fwd_traffic.json")
+BWD_KERNEL_SOURCES = ["paper_2010_14258_amd/csrc/ldbp_bwd.hip", "paper_2010_14258_amd/csrc/ldbp_fir.h",
+                      "paper_2010_14258_amd/csrc/ldbp_kernels.h", "paper_2010_14258_amd/csrc/common.h"]
+BWD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ldbp_bwd_traffic.json")
 KERNEL_SOURCES = ["paper_2010_14258_amd/csrc/ldbp_fwd.hip", "paper_2010_14258_amd/csrc/ldbp_fwd_impl.h",
                   "paper_2010_14258_amd/csrc/ldbp_fir.h",
                   "paper_2010_14258_amd/csrc/common.h"]
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=None) -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -62,6 +65,19 @@ def fwd_flops_per_sample_step(T: int, folded: bool = False) -> int:
     # Kerr: |u|^2 (3) + c |u|^2 (1) + rotation, a complex multiply (6) = 10; sine/cosine not counted.
     K = (T - 1) // 2
     return (10 * K + 6 if folded else 8 * T - 2) + 10
+
+
+def bwd_flops_per_sample_step(T: int, folded: bool = False) -> int:
+    # the forward step recomputed from the block checkpoint (as above);
+    # Kerr adjoint: q = Im(G_y conj y) (3), G_y e^{-j phi} (6), 2 c q (2), times u (2), sum (2),
+    # the c-gradient term q |u|^2 (2) = 17;
+    # FIR adjoint (correlation with the conjugate taps): the forward FIR count;
+    # tap correlation sum_m G_u,m conj(x_{m-k}): a conjugate complex multiply-accumulate (8) per tap,
+    # folded: K pair additions (2) and K+1 of them.
+    K = (T - 1) // 2
+    fir = 10 * K + 6 if folded else 8 * T - 2
+    tapcorr = 2 * K + 8 * (K + 1) if folded else 8 * T
+    return (fir + 10) + 17 + fir + tapcorr
 
 
 def event_time(torch, stream, fn, steps: int, warmup: int):
@@ -634,6 +650,19 @@ def init_schemes(torch, dev, iters: int, every: int = 1000, schemes=("least_squa
                               "note": "the paper's values (Sec. V-E, Fig. results(c)), context only"}}
 
 
+COPY_PROBE_ELEMS = 64 << 20   # complex64 elements: 512 MiB per buffer, beyond the last-level cache
+
+
+def copy_probe(torch, dev):
+    """Three device-to-device copies of 512 MiB: a plain kernel of known traffic, against which the
+    FETCH_SIZE and WRITE_SIZE counters of the same run are calibrated."""
+    big = torch.empty(COPY_PROBE_ELEMS, dtype=torch.complex64, device=dev)
+    dst = torch.empty_like(big)
+    for _ in range(3):
+        dst.copy_(big)
+    torch.cuda.synchronize()
+
+
 def snr_db(TX, z, s, p):
     mse, _, _ = TX.rx_mse(z, s, p, RHO_D, RS)
     return 10.0 * math.log10(1.0 / float(mse.mean().item()))
@@ -646,8 +675,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
-    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "dbp", "snr", "essm", "e1", "init", "e8"], default="full",
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "dbp", "snr", "essm", "e1", "init", "e8"],
+                    default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
+                         "bwd: the training step (checkpointed forward + backward) and a copy probe; "
                          "dbp: FFT-DBP at one step per span only (for kernel traces of the split-step passes); "
                          "snr: train LDBP, then the equal-SNR comparison with FFT-DBP over launch powers; "
                          "essm: train conventional and generalised ESSM (and LDBP) with one step per span; "
@@ -669,7 +700,7 @@ def main():
     ap.add_argument("--train-taps", default="25:3",
                     help="models of --mode snr: initial:final taps per step, comma separated (pruned in training)")
     ap.add_argument("--one-stream", action="store_true",
-                    help="fwd/pmc modes: keep every launch on one stream (the kernel's own per-launch time)")
+                    help="fwd/pmc/bwd modes: keep every launch on one stream (the kernel's own per-launch time)")
     ap.add_argument("--plan", default=None,
                     help="forward plan S,chunks,outputs_per_thread,symmetric (default: autotuned, folded)")
     args = ap.parse_args()
@@ -729,6 +760,29 @@ def main():
         print(json.dumps({"fft_dbp_ms": ms, "dbp_steps": nstep, "us_per_step": ms / nstep * 1e3,
                           "nwave": nwave, "n": n}))
         return
+    if args.mode == "bwd":
+        # the training step alone: forward with 2-step block checkpoints + backward (folded symmetric
+        # filters, the gradient reduction included), then the copy probe that calibrates the counters
+        S = 2
+        ck = torch.empty((L.num_checkpoints(ell, S),) + tuple(r.shape), dtype=r.dtype, device=dev)
+        z = L.ldbp_forward(r, taps, c, ntap)
+        _, _, gy = TX.rx_mse(z, W["s"], W["p"], RHO_D, RS, want_grad=True)
+        bws = torch.empty(L.ldbp_backward_workspace_size(r, ntap, ckpt=ck, ckpt_every=S), dtype=torch.uint8,
+                          device=dev)
+
+        fplan = (0, 0, 0, 1, 1) if args.one_stream else (0, 0, 0, 1)
+
+        def fwd_bwd():
+            L.ldbp_forward(r, taps, c, ntap, y=y, ckpt=ck, ckpt_every=S, plan=fplan, stream=stream)
+            L.ldbp_backward(r, taps, c, ntap, gy, ckpt=ck, ckpt_every=S, need_gx=False, symmetric=True,
+                            ws=bws, stream=stream, one_stream=args.one_stream)
+
+        ms = event_time(torch, stream, fwd_bwd, args.steps, args.warmup)
+        copy_probe(torch, dev)
+        print(json.dumps({"mode": "bwd", "fwd_bwd_ms": ms, "ckpt_every": S, "one_stream": args.one_stream,
+                          "nwave": nwave, "n": n, "steps_l": ell, "taps": TAPS,
+                          "copy_probe": "3 copies of 512 MiB"}), flush=True)
+        return
     from paper_2010_14258_amd import autotune as AT
     if args.plan:
         plan = tuple(int(v) for v in args.plan.split(","))
@@ -754,14 +808,10 @@ def main():
     if args.mode == "pmc":
         for _ in range(3):
             fwd()
-        big = torch.empty(64 << 20, dtype=torch.complex64, device=dev)   # 512 MiB copy probe
-        dst = torch.empty_like(big)
-        for _ in range(3):
-            dst.copy_(big)
-        torch.cuda.synchronize()
+        copy_probe(torch, dev)
         print(json.dumps({"pmc_probe": True, "plan": list(plan),
                           "fwd_launches": 3 * L.ldbp_forward_plan_query(0, 1, nwave, n, ntap, plan=plan)[0],
-                          "copy_bytes": 2 * big.numel() * 8, "kernel_hash": kernel_hash()}))
+                          "copy_bytes": 2 * COPY_PROBE_ELEMS * 8, "kernel_hash": kernel_hash()}))
         return
 
     t0 = time.perf_counter()
@@ -839,9 +889,37 @@ def main():
 
         ms_fb = event_time(torch, stream, lambda: fwd_bwd(1), max(5, args.steps // 5), 2)
         ms_fb_gen = event_time(torch, stream, lambda: fwd_bwd(0), max(5, args.steps // 5), 2)
+        # the backward kernel's own position: the backward call alone with every launch on one stream,
+        # one launch per block of S steps over the whole batch (the two small gradient-reduction
+        # launches, about 1% of the call, are included in the per-launch time)
+        ms_b = event_time(torch, stream,
+                          lambda: L.ldbp_backward(r, taps, c, ntap, gy, ckpt=ck, ckpt_every=S, need_gx=False,
+                                                  symmetric=True, ws=bws, stream=stream, one_stream=True),
+                          max(5, args.steps // 5), 2)
+        nblk = -(-ell // S)
+        b_launch_ms = ms_b / nblk
+        b_flops_launch = nwave * n * sum(bwd_flops_per_sample_step(t, True) for t in ntap) / nblk
+        b_tflops = b_flops_launch / (b_launch_ms * 1e-3) / 1e12
+        # read the block checkpoint and G_y, write G_x (not for the first block: need_gx=False)
+        b_bytes_launch = nwave * n * 8 * (2 * nblk + (nblk - 1)) / nblk
+        b_traffic = None
+        if os.path.exists(BWD_TRAFFIC_FILE):
+            with open(BWD_TRAFFIC_FILE) as fh:
+                tr = json.load(fh)
+            if tr.get("kernel_hash") == kernel_hash(BWD_KERNEL_SOURCES) \
+                    and tr.get("workload") == [nwave, n, ell, TAPS, S]:
+                b_traffic = tr.get("bytes_per_launch")
         out["fwd_bwd"] = {"value": ss / (ms_fb * 1e-3), "unit": "samples*steps/s", "ms_per_step": ms_fb,
                           "ckpt_every": S, "folded_symmetric_filters": True,
-                          "general_taps_ms": ms_fb_gen, "general_taps_value": ss / (ms_fb_gen * 1e-3)}
+                          "general_taps_ms": ms_fb_gen, "general_taps_value": ss / (ms_fb_gen * 1e-3),
+                          "backward_roofline": {
+                              "bound": "alu", "achieved": b_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                              "frac": b_tflops / FP32_PEAK_TFLOPS, "traffic": b_traffic,
+                              "kernel": "ldbp_bwd_kernel<float,1,5,5,256> folded", "launch_ms": b_launch_ms,
+                              "launches": nblk, "one_stream_backward_ms": ms_b,
+                              "flops_per_sample_step": bwd_flops_per_sample_step(TAPS, True),
+                              "flops_per_launch": b_flops_launch, "algorithmic_bytes_per_launch": b_bytes_launch,
+                              "hbm_achieved_gbs": b_bytes_launch / (b_launch_ms * 1e-3) / 1e9}}
         # equal-SNR comparison with FFT-DBP on the same waveforms
         snr_ldbp = snr_db(TX, z, W["s"], W["p"])
         sweep = {}
