@@ -832,11 +832,13 @@ def main():
     achieved_gbs = bytes_launch / (launch_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
+        # counter runs of this kernel source, one entry per plan the autotuner has picked
         with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == [nwave, n, ell, TAPS] \
-                and tr.get("plan") == list(plan):
-            traffic = tr.get("bytes_per_launch")
+            entries = json.load(fh).get("entries", [])
+        for tr in entries:
+            if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == [nwave, n, ell, TAPS] \
+                    and tr.get("plan") == list(plan):
+                traffic = tr.get("bytes_per_launch")
 
     out = {
         "metric": "samples*steps/s of the LDBP forward (waveform samples x LDBP steps per second)",
