@@ -189,9 +189,7 @@ __device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
-      if (base + r < hi)
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+      if (base + r < hi) store_sample<R, NPOL>(out + (base + r) * NPOL, acc[r]);
   }
 }
 
@@ -215,9 +213,7 @@ __device__ __forceinline__ void fir_adj_generic(const cx_t<R>* __restrict__ in, 
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r)
-      if (base + r < hi)
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+      if (base + r < hi) store_sample<R, NPOL>(out + (base + r) * NPOL, acc[r]);
   }
 }
 
@@ -684,12 +680,13 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
       // the range shrunk by kappa: G_u = G_y e^{-j phi} + 2 r u, r_i = c sum_k eta_k q_{i+k}
       for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += THREADS) {
         R pw = 0, q = 0;
+        V yv[NPOL], gv[NPOL];
+        load_sample<R, NPOL>(ycur + (i + yoff) * NPOL, yv);
+        load_sample<R, NPOL>(GA + i * NPOL, gv);
 #pragma unroll
         for (int pp = 0; pp < NPOL; ++pp) {
-          const V yv = ycur[(i + yoff) * NPOL + pp];
-          const V gv = GA[i * NPOL + pp];
-          pw += yv.x * yv.x + yv.y * yv.y;
-          q += gv.y * yv.x - gv.x * yv.y;
+          pw += yv[pp].x * yv[pp].x + yv[pp].y * yv[pp].y;
+          q += gv[pp].y * yv[pp].x - gv[pp].x * yv[pp].y;
         }
         Q[i] = q;
         PP[i] = pw;
@@ -708,22 +705,24 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
       for (int i = lo + static_cast<int>(threadIdx.x); i < hi; i += THREADS) {
         V yv[NPOL], gv[NPOL];
         R pw = 0, q = 0;
+        load_sample<R, NPOL>(ycur + (i + yoff) * NPOL, yv);
+        load_sample<R, NPOL>(GA + i * NPOL, gv);
 #pragma unroll
         for (int pp = 0; pp < NPOL; ++pp) {
-          yv[pp] = ycur[(i + yoff) * NPOL + pp];
-          gv[pp] = GA[i * NPOL + pp];
           pw += yv[pp].x * yv[pp].x + yv[pp].y * yv[pp].y;
           q += gv[pp].y * yv[pp].x - gv[pp].x * yv[pp].y;
         }
         R sn, co;
         phase_sincos(coef, pw, sn, co);
         const R tq = 2 * cr * q;
+        V gb[NPOL];
 #pragma unroll
         for (int pp = 0; pp < NPOL; ++pp) {
           const R tx = gv[pp].x + tq * yv[pp].x;
           const R ty = gv[pp].y + tq * yv[pp].y;
-          GB[i * NPOL + pp] = V{tx * co + ty * sn, ty * co - tx * sn};
+          gb[pp] = V{tx * co + ty * sn, ty * co - tx * sn};
         }
+        store_sample<R, NPOL>(GB + i * NPOL, gb);
         if (i >= H && i < H + Lw) accc += q * pw;
       }
     }
@@ -743,9 +742,11 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
   // 4. block-input gradient and the tile's partial sums
   if (gin) {
     V* gi = gin + wave * static_cast<int64_t>(n) * NPOL;
-    for (int j = threadIdx.x; j < Lw; j += THREADS)
-#pragma unroll
-      for (int pp = 0; pp < NPOL; ++pp) gi[static_cast<int64_t>(t0 + j) * NPOL + pp] = GA[(H + j) * NPOL + pp];
+    for (int j = threadIdx.x; j < Lw; j += THREADS) {
+      V v[NPOL];
+      load_sample<R, NPOL>(GA + (H + j) * NPOL, v);
+      store_sample<R, NPOL>(gi + static_cast<int64_t>(t0 + j) * NPOL, v);
+    }
   }
   double2* prow = part + static_cast<int64_t>(blockIdx.x) * ncols;
   for (int col = threadIdx.x; col < ldr; col += THREADS) {

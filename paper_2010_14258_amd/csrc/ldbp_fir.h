@@ -29,6 +29,17 @@ __device__ __forceinline__ void load_sample(const cx_t<R>* __restrict__ src, cx_
   }
 }
 
+// The NPOL values of one sample into LDS, as one 16-byte access for two complex64 polarisations.
+template <typename R, int NPOL>
+__device__ __forceinline__ void store_sample(cx_t<R>* __restrict__ dst, const cx_t<R> (&v)[NPOL]) {
+  if constexpr (NPOL == 2 && sizeof(R) == 4) {
+    *reinterpret_cast<float4*>(dst) = float4{v[0].x, v[0].y, v[1].x, v[1].y};
+  } else {
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) dst[p] = v[p];
+  }
+}
+
 template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM, bool LIN = false>
 __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out,
                                                int lo, int hi, const cx_t<R>* __restrict__ h, R coef,
@@ -82,20 +93,19 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
       if constexpr (LIN) {
         if (base + r < hi) {
           pw[base + r] = pwr;
-#pragma unroll
-          for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+          store_sample<R, NPOL>(out + (base + r) * NPOL, acc[r]);
         }
       } else {
         R s, co;
         phase_sincos(coef, pwr, s, co);
         if (base + r < hi) {
+          V o[NPOL];
 #pragma unroll
           for (int p = 0; p < NPOL; ++p) {
-            V o;
-            o.x = acc[r][p].x * co - acc[r][p].y * s;
-            o.y = acc[r][p].x * s + acc[r][p].y * co;
-            out[(base + r) * NPOL + p] = o;
+            o[p].x = acc[r][p].x * co - acc[r][p].y * s;
+            o[p].y = acc[r][p].x * s + acc[r][p].y * co;
           }
+          store_sample<R, NPOL>(out + (base + r) * NPOL, o);
         }
       }
     }
@@ -129,20 +139,19 @@ __device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in,
       if constexpr (LIN) {
         if (base + r < hi) {
           pw[base + r] = pwr;
-#pragma unroll
-          for (int p = 0; p < NPOL; ++p) out[(base + r) * NPOL + p] = acc[r][p];
+          store_sample<R, NPOL>(out + (base + r) * NPOL, acc[r]);
         }
       } else {
         R s, co;
         phase_sincos(coef, pwr, s, co);
         if (base + r < hi) {
+          V o[NPOL];
 #pragma unroll
           for (int p = 0; p < NPOL; ++p) {
-            V o;
-            o.x = acc[r][p].x * co - acc[r][p].y * s;
-            o.y = acc[r][p].x * s + acc[r][p].y * co;
-            out[(base + r) * NPOL + p] = o;
+            o[p].x = acc[r][p].x * co - acc[r][p].y * s;
+            o[p].y = acc[r][p].x * s + acc[r][p].y * co;
           }
+          store_sample<R, NPOL>(out + (base + r) * NPOL, o);
         }
       }
     }
@@ -198,11 +207,11 @@ __device__ __forceinline__ void nl_filter_fixed(cx_t<R>* __restrict__ u, const R
       if (base + r < hi) {
         R s, co;
         phase_sincos(coef, F[r], s, co);
+        V a[NPOL];
+        load_sample<R, NPOL>(u + (base + r) * NPOL, a);
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) {
-          const V a = u[(base + r) * NPOL + p];
-          u[(base + r) * NPOL + p] = V{a.x * co - a.y * s, a.x * s + a.y * co};
-        }
+        for (int p = 0; p < NPOL; ++p) a[p] = V{a[p].x * co - a[p].y * s, a[p].x * s + a[p].y * co};
+        store_sample<R, NPOL>(u + (base + r) * NPOL, a);
       }
     }
   }
@@ -237,11 +246,11 @@ __device__ __forceinline__ void nl_filter_win(cx_t<R>* __restrict__ u, const R* 
       if (base + r < hi) {
         R s, co;
         phase_sincos(coef, F[r], s, co);
+        V a[NPOL];
+        load_sample<R, NPOL>(u + (base + r) * NPOL, a);
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) {
-          const V a = u[(base + r) * NPOL + p];
-          u[(base + r) * NPOL + p] = V{a.x * co - a.y * s, a.x * s + a.y * co};
-        }
+        for (int p = 0; p < NPOL; ++p) a[p] = V{a[p].x * co - a[p].y * s, a[p].x * s + a[p].y * co};
+        store_sample<R, NPOL>(u + (base + r) * NPOL, a);
       }
     }
   }
@@ -256,11 +265,11 @@ __device__ __forceinline__ void nl_filter_generic(cx_t<R>* __restrict__ u, const
     for (int k = -kap; k <= kap; ++k) F = fma(eta[kap + k], pw[m - k], F);
     R s, co;
     phase_sincos(coef, F, s, co);
+    V a[NPOL];
+    load_sample<R, NPOL>(u + m * NPOL, a);
 #pragma unroll
-    for (int p = 0; p < NPOL; ++p) {
-      const V a = u[m * NPOL + p];
-      u[m * NPOL + p] = V{a.x * co - a.y * s, a.x * s + a.y * co};
-    }
+    for (int p = 0; p < NPOL; ++p) a[p] = V{a[p].x * co - a[p].y * s, a[p].x * s + a[p].y * co};
+    store_sample<R, NPOL>(u + m * NPOL, a);
   }
 }
 
@@ -308,15 +317,12 @@ __device__ __forceinline__ void load_tile(const cx_t<R>* __restrict__ xw, cx_t<R
         if (g < 0) g += n;
         else if (g >= n) g -= n;
       }
-#pragma unroll
-      for (int p = 0; p < NPOL; ++p) v[u][p] = xw[static_cast<int64_t>(g) * NPOL + p];
+      load_sample<R, NPOL>(xw + static_cast<int64_t>(g) * NPOL, v[u]);
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
       const int j = j0 + u * THREADS;
-      if (j < W0)
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) buf[j * NPOL + p] = v[u][p];
+      if (j < W0) store_sample<R, NPOL>(buf + j * NPOL, v[u]);
     }
   }
 }
@@ -347,15 +353,18 @@ __device__ __forceinline__ void load_tile_edge(const cx_t<R>* __restrict__ xw, c
       const int src = g - in_off;
       ok[u] = src >= 0 && src < in_len;
       const int sc = min(max(src, 0), in_len - 1);
-#pragma unroll
-      for (int p = 0; p < NPOL; ++p) v[u][p] = xw[static_cast<int64_t>(sc) * NPOL + p];
+      load_sample<R, NPOL>(xw + static_cast<int64_t>(sc) * NPOL, v[u]);
     }
 #pragma unroll
     for (int u = 0; u < kLoadBatch; ++u) {
       const int j = j0 + u * THREADS;
-      if (j < W0)
+      if (j < W0) {
+        if (!ok[u]) {
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) buf[j * NPOL + p] = ok[u] ? v[u][p] : V{0, 0};
+          for (int p = 0; p < NPOL; ++p) v[u][p] = V{0, 0};
+        }
+        store_sample<R, NPOL>(buf + j * NPOL, v[u]);
+      }
     }
   }
 }

@@ -77,8 +77,9 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
       const int64_t slot = (pt.c0 + s + 1) / pt.ckpt_every - 1;
       V* cw = ckpt + slot * slot_elems + wave * static_cast<int64_t>(n) * NPOL;
       for (int j = threadIdx.x; j < Lw; j += THREADS) {
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) cw[static_cast<int64_t>(t0 + j) * NPOL + p] = b0[(H + j) * NPOL + p];
+        V v[NPOL];
+        load_sample<R, NPOL>(b0 + (H + j) * NPOL, v);
+        store_sample<R, NPOL>(cw + static_cast<int64_t>(t0 + j) * NPOL, v);
       }
     }
   }
@@ -89,8 +90,9 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
       o -= em.out_off;
       if (o < 0 || o >= em.out_len) continue;
     }
-#pragma unroll
-    for (int p = 0; p < NPOL; ++p) yw[static_cast<int64_t>(o) * NPOL + p] = b0[(H + j) * NPOL + p];
+    V v[NPOL];
+    load_sample<R, NPOL>(b0 + (H + j) * NPOL, v);
+    store_sample<R, NPOL>(yw + static_cast<int64_t>(o) * NPOL, v);
   }
 }
 
