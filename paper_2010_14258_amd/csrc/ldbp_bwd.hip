@@ -839,6 +839,12 @@ static int bwd_pad(int dtype, int npol) {
   return dtype == LDBP_C64 ? 8 : 4;
 }
 
+// Waves per backward workgroup: the FP64 partial-sum rows at the start of the LDS, one per wave.
+static int bwd_waves(int dtype, int npol) {
+  if (dtype == LDBP_C64) return (npol == 2 ? BwdCfg<float, 2>::THREADS : BwdCfg<float, 1>::THREADS) / 64;
+  return (npol == 2 ? BwdCfg<double, 2>::THREADS : BwdCfg<double, 1>::THREADS) / 64;
+}
+
 size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt, bool filtered) {
   const int pad = bwd_pad(dtype, npol);
   const int S = pt.nstep;
@@ -854,7 +860,8 @@ size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt, bool filt
   elems += 2 * static_cast<size_t>(Lw + 2 * pt.halo + pad);
   size_t reals = 0;
   if (filtered) reals = static_cast<size_t>(Lw + 2 * pt.halo + pad) + static_cast<size_t>(Lw + 4 * pt.halo + pad + 8);
-  return static_cast<size_t>(4) * (ntap_blk + neta_blk + S) * sizeof(double2) + elems * npol * cx_size(dtype) +
+  return static_cast<size_t>(bwd_waves(dtype, npol)) * (ntap_blk + neta_blk + S) * sizeof(double2) +
+         elems * npol * cx_size(dtype) +
          reals * real_size(dtype);
 }
 
