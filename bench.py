@@ -675,10 +675,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
-    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "dbp", "snr", "essm", "e1", "init", "e8"],
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "dbp", "snr", "essm", "e1", "init", "e8"],
                     default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "bwd: the training step (checkpointed forward + backward) and a copy probe; "
+                         "train: whole training iterations (channel simulation to Adam) for kernel traces; "
                          "dbp: FFT-DBP at one step per span only (for kernel traces of the split-step passes); "
                          "snr: train LDBP, then the equal-SNR comparison with FFT-DBP over launch powers; "
                          "essm: train conventional and generalised ESSM (and LDBP) with one step per span; "
@@ -721,6 +722,21 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
+    if args.mode == "train":
+        # training iterations alone on the 32 x 16,384 configuration (l = 50, 25 -> 3 taps, channel
+        # 1,000 steps): transmitter, channel, receiver, LDBP forward and backward, loss, Adam
+        from paper_2010_14258_amd import train as TRN
+        trn = TRN.Trainer(TRN.TrainConfig(iters=5000), device=dev)
+        for _ in range(max(1, args.warmup)):
+            trn.step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            trn.step()
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "train", "iteration_ms": (time.perf_counter() - t1) / args.steps * 1e3,
+                          "iterations": args.steps, "warmup": max(1, args.warmup)}), flush=True)
+        return
     W = build_workload(torch, dev, cheap=args.mode != "full")
     r, taps, c, ntap = W["r"], W["taps"], W["c"], W["ntap"]
     nwave, n = r.shape
