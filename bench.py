@@ -16,8 +16,11 @@ the 32 x 16,384 training configuration, the same forward on 1,024 waveforms (512
 beyond the 256 MB last-level cache), the dual-polarisation 8 x 2^20 x 2 configuration (32 x 80 km,
 l = 64, 5 shared taps), the 256-waveform uneven batch, the generalised ESSM (every nonlinear step
 filtering the power with 41 real taps) forward and forward + backward, overlap-save streaming (the
-aperiodic forward on blocks of a continuous stream), the roofline position of the forward kernel and
-the FP64 oracle on the host (one core and all cores of the process's CPU set).
+aperiodic forward on blocks of a continuous stream), the roofline positions of the forward and
+backward kernels and the FP64 oracle on the host (one core and all cores of the process's CPU set).
+
+Other --mode values run one part alone (for kernel traces and counters: fwd, pmc, bwd, train, dbp)
+or the training experiments (snr, essm, e1, e8, init), each printing its own JSON line.
 """
 from __future__ import annotations
 
