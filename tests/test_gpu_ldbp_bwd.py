@@ -86,7 +86,8 @@ def _sym_projection(gt):
 
 
 @pytest.mark.parametrize("dtype,tol", [(torch.complex64, 1e-4), (torch.complex128, 1e-10)])
-@pytest.mark.parametrize("npol,S,use_ckpt", [(1, 3, True), (1, 2, False), (2, 3, True), (1, 0, False)])
+@pytest.mark.parametrize("npol,S,use_ckpt", [(1, 3, True), (1, 2, False), (2, 3, True), (1, 0, False), (2, 1, True),
+                                             (2, 0, False)])
 def test_backward_symmetric_folded_vs_oracle(dtype, tol, npol, S, use_ckpt):
     """Folded evaluation for symmetric filters (incl. T = 1 and the K > 12 direct path): dL/dx and dL/dc as
     the oracle's, taps as the oracle's gradient projected on symmetric filters."""
