@@ -19,7 +19,8 @@ filtering the power with 41 real taps) forward and forward + backward, overlap-s
 aperiodic forward on blocks of a continuous stream), the roofline positions of the forward and
 backward kernels and the FP64 oracle on the host (one core and all cores of the process's CPU set).
 
-Other --mode values run one part alone (for kernel traces and counters: fwd, pmc, bwd, train, dbp)
+Other --mode values run one part alone (for kernel traces and counters: fwd, pmc, bwd, train, variants,
+dbp)
 or the training experiments (snr, essm, e1, e8, init), each printing its own JSON line.
 """
 from __future__ import annotations
@@ -362,7 +363,7 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
             "train_iterations": iters, "models": out_models, "by_power": rows}
 
 
-def essm_timing(torch, dev, W, reps: int, kappa: int = 20):
+def essm_timing(torch, dev, W, reps: int, kappa: int = 20, plan=None):
     """The generalised ESSM on the inference workload: the same l = 50 steps of 15 folded taps, every
     nonlinear step filtering the power with 2 kappa + 1 real taps.  Forward (autotuned plan) and forward
     with checkpoints every 2 steps + backward.  The filters are unit filters padded with zeros (the
@@ -380,7 +381,8 @@ def essm_timing(torch, dev, W, reps: int, kappa: int = 20):
     eta = torch.from_numpy(eta_np.reshape(-1)).to(dev)
     nl = [ne] * ell
     stream = torch.cuda.current_stream(dev)
-    plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=3, eta=eta, nl_ntap=nl)
+    if plan is None:
+        plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=3, eta=eta, nl_ntap=nl)
     y = torch.empty_like(r)
     ws = torch.empty(max(E.essm_forward_workspace_size(r, ntap, nl, plan=plan), 1), dtype=torch.uint8, device=dev)
     ms = event_time(torch, stream,
@@ -678,11 +680,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
-    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "dbp", "snr", "essm", "e1", "init", "e8"],
+    ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "variants", "dbp", "snr", "essm", "e1",
+                                       "init", "e8"],
                     default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "bwd: the training step (checkpointed forward + backward) and a copy probe; "
                          "train: whole training iterations (channel simulation to Adam) for kernel traces; "
+                         "variants: the generalised ESSM and overlap-save timings alone (fixed plans); "
                          "dbp: FFT-DBP at one step per span only (for kernel traces of the split-step passes); "
                          "snr: train LDBP, then the equal-SNR comparison with FFT-DBP over launch powers; "
                          "essm: train conventional and generalised ESSM (and LDBP) with one step per span; "
@@ -801,6 +805,16 @@ def main():
         print(json.dumps({"mode": "bwd", "fwd_bwd_ms": ms, "ckpt_every": S, "one_stream": args.one_stream,
                           "nwave": nwave, "n": n, "steps_l": ell, "taps": TAPS,
                           "copy_probe": "3 copies of 512 MiB"}), flush=True)
+        return
+    if args.mode == "variants":
+        # the generalised ESSM (forward; forward with checkpoints + backward) and overlap-save streaming
+        # alone, with fixed plans, for kernel traces; first bring the GPU to its steady clock
+        for _ in range(600):
+            L.ldbp_forward(r, taps, c, ntap, y=y, plan=(10, 1, 7, 1), stream=stream)
+        torch.cuda.synchronize()
+        out = {"mode": "variants", "essm": essm_timing(torch, dev, W, args.steps, plan=(3, 1, 7, 1)),
+               "aperiodic": aperiodic_timing(torch, dev, W, (10, 1, 7, 1), args.steps)}
+        print(json.dumps(out), flush=True)
         return
     from paper_2010_14258_amd import autotune as AT
     if args.plan:
