@@ -567,7 +567,13 @@ struct BwdLayout {
   size_t off_ckpt, off_g0, off_g1, off_part, off_chunks, total;
 };
 
-static int default_bwd_S(const ModelArgs& m) { return std::min<int32_t>(m.nstep, m.dtype == LDBP_C64 ? 2 : 3); }
+// Block length of the backward when the caller gives none.  complex64: 2 steps for one polarisation,
+// 3 for two (forward with checkpoints + backward on 64 x 65,536, l = 50, 15 taps: S = 1-5 took 2.44,
+// 1.98, 2.11, 2.39, 2.55 ms; on 8 x 2^20 x 2, l = 64, 5 taps: 9.34, 7.33, 6.93, 7.17, 6.82 ms).
+static int default_bwd_S(const ModelArgs& m) {
+  const int s = m.dtype == LDBP_C64 ? (m.npol == 2 ? 3 : 2) : 3;
+  return std::min<int32_t>(m.nstep, s);
+}
 
 static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_every, BwdLayout& L) {
   L.S = ckpt_every > 0 ? ckpt_every : default_bwd_S(m);
