@@ -33,10 +33,19 @@ position z_a uses c = -kerr_scale * gamma * L_eff(delta) * e^{-alpha z_a}: the
 LDBP filters have unit gain, so the signal keeps the launch-power level and the
 span's power profile is carried by c instead.
 
+Multi-objective design (Sec. VI-B): every run of neighbouring filters adds one
+weighted LS objective on its combined response; with all other filters fixed the
+objectives of one filter stack into a single weighted LS problem (eq. weighted_ls),
+solved for each filter in turn.  The weights lambda_j and the update order are not
+given: all runs weigh the same and filters are updated in step order.
+
 Pins (tests/test_oracle_design.py): Example 1 step sizes and merged lengths and
 the identical filters h^(2..4); least squares on the N-point grid equals the
 truncated inverse DFT (Parseval); symmetric taps for the even response; the
-initialised LDBP with T = n taps reproduces FFT-DBP; T_cd arithmetic (Sec. V-B, V-F).
+initialised LDBP with T = n taps reproduces FFT-DBP; T_cd arithmetic (Sec. V-B, V-F);
+multi-objective design: single-filter runs give the individual in-band fits, the
+total objective of eq. objectives never rises over the updates, and the last
+updated filter is a stationary point of it (central differences).
 """
 from __future__ import annotations
 
@@ -171,3 +180,64 @@ def init_symmetric(span_len: float, nspan: int, steps_per_span: Sequence[float],
     for i, (d, z0) in enumerate(plan):
         c[i] = kerr_coef(d, z0, alpha, gamma, kerr_scale)
     return taps, c
+
+
+def multi_objective_ls(taps: Sequence[np.ndarray], xis: Sequence[float], band_edge: float, mu: float = 1e-3,
+                       max_window: int = 0, sweeps: int = 3, N: int = 1024) -> list[np.ndarray]:
+    """Joint filter design of Sec. VI-B (eqs. objectives and weighted_ls), written out plainly.
+
+    Objectives: for every run a..b of neighbouring filters (length b - a + 1 <= max_window; 0 = all
+    lengths) the combined response F(h^(a) * ... * h^(b)) = prod_m (B h^(m)) should be close to
+    e^{j (xi_a + ... + xi_b) w^2} on the (N+1)-point grid w_i = 2 pi i / N, i = -N/2..N/2, with the
+    in-band weight of ls_taps_inband (squared weight 1 for |w| <= band_edge, mu outside) and all
+    lambda_j = 1.  With every filter but h^(i) held at its current value, each run containing i is one
+    term || ((B h^(i)) o e_j - d_j) ||^2_W of eq. weighted_ls, e_j the product of the other filters'
+    responses in the run and d_j its target.  The terms are stacked into one weighted matrix and solved
+    with one least-squares call; filters are updated in step order (i = 1..M) for `sweeps` passes,
+    each update using the filters already updated in the same pass.  Returns the new filters."""
+    M = len(taps)
+    L = M if max_window <= 0 else min(max_window, M)
+    i_grid = np.arange(-N // 2, N // 2 + 1)
+    w = 2.0 * np.pi * i_grid / N
+    sqrt_wt = np.where(np.abs(w) <= band_edge, 1.0, np.sqrt(mu))
+    hs = [np.array(h, dtype=np.complex128) for h in taps]
+
+    def dtft_matrix(T):
+        K = (T - 1) // 2
+        return np.exp(-1j * np.outer(w, np.arange(-K, K + 1)))
+
+    for _ in range(sweeps):
+        for i in range(M):
+            Bi = dtft_matrix(len(hs[i]))
+            blocks, rhs = [], []
+            for a in range(M):
+                for b in range(a, M):
+                    if not (a <= i <= b) or b - a + 1 > L:
+                        continue
+                    e = np.ones(len(w), dtype=np.complex128)
+                    for m in range(a, b + 1):
+                        if m != i:
+                            e = e * (dtft_matrix(len(hs[m])) @ hs[m])
+                    d = np.exp(1j * sum(xis[a:b + 1]) * w * w)
+                    blocks.append(sqrt_wt[:, None] * (e[:, None] * Bi))
+                    rhs.append(sqrt_wt * d)
+            hs[i], *_ = np.linalg.lstsq(np.vstack(blocks), np.concatenate(rhs), rcond=None)
+    return hs
+
+
+def multi_objective_total(taps: Sequence[np.ndarray], xis: Sequence[float], band_edge: float, mu: float = 1e-3,
+                          max_window: int = 0, N: int = 1024) -> float:
+    """Sum over the objectives of eq. objectives of the weighted squared errors (all lambda_j = 1)."""
+    M = len(taps)
+    L = M if max_window <= 0 else min(max_window, M)
+    w = 2.0 * np.pi * np.arange(-N // 2, N // 2 + 1) / N
+    wt = np.where(np.abs(w) <= band_edge, 1.0, mu)
+    J = 0.0
+    for a in range(M):
+        for b in range(a, min(M, a + L)):
+            resp = np.ones(len(w), dtype=np.complex128)
+            for m in range(a, b + 1):
+                K = (len(taps[m]) - 1) // 2
+                resp = resp * (np.exp(-1j * np.outer(w, np.arange(-K, K + 1))) @ taps[m])
+            J += float(np.sum(wt * np.abs(resp - np.exp(1j * sum(xis[a:b + 1]) * w * w)) ** 2))
+    return J

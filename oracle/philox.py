@@ -16,11 +16,13 @@ feed sample 2p and w2,w3 sample 2p+1.  Each word pair (a, b) maps to
 u_a = (a + 0.5) 2^-32, u_b = (b + 0.5) 2^-32 and
 w = sqrt(-ln u_a) (cos 2 pi u_b + j sin 2 pi u_b), so E|w|^2 = 1.
 
-Pins (tests/test_oracle_philox.py): distribution tests (uniformity of the
-words, moments and tail of the normals, independence of streams).  No
-known-answer vector is available in the container, so the exact word values
-are "parity unpinned" against the publication; the device generator is held to
-bit equality with this one.
+Pins (tests/test_oracle_philox.py): the three published known-answer vectors
+of the Random123 test set (tests/golden/philox_kat.json), which fix the round
+function, both multipliers and the key schedule; the Weyl constants recomputed
+from their definition (the first 32 fractional bits of the golden ratio and of
+sqrt(3) - 1); the counter layout of words(); distribution tests (uniformity of
+the words, moments and tail of the normals, independence of streams).  The
+device generator is held to bit equality with this one.
 """
 from __future__ import annotations
 

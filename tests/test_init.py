@@ -153,3 +153,17 @@ def test_cosine_learning_rate_after_pruning():
     assert abs(lr(t0) - 1e-3) < 1e-15 and abs(lr(1000) - 1e-4) < 1e-15
     assert abs(lr((t0 + 1000) // 2) - 0.5 * (1e-3 + 1e-4)) < 2e-6
     assert all(lr(a) >= lr(a + 1) for a in range(t0, 1000))
+
+
+def test_multi_objective_design_matches_the_oracle():
+    """The product's joint design (normal equations accumulated run by run) against the oracle's
+    stacked weighted least squares of Sec. VI-B (eqs. objectives and weighted_ls), same update order,
+    for all run lengths and for runs of at most 3 filters."""
+    M, T = 6, 5
+    taps, xis = _steps(M, T)
+    edge = np.pi * 1.1 / 2
+    for window in (0, 3):
+        got = I.multi_objective_taps(taps, xis, max_window=window, sweeps=3)
+        ref = D.multi_objective_ls(taps, xis, edge, mu=1e-3, max_window=window, sweeps=3, N=1024)
+        for a, b in zip(got, ref):
+            np.testing.assert_allclose(a, b, rtol=1e-10, atol=1e-12)

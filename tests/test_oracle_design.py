@@ -163,3 +163,51 @@ def test_inband_fit_reduces_to_full_band_and_improves_band_error():
     assert band_err(hb) < 0.2 * band_err(D.ls_taps(xi, T))
     # out-of-band gain stays bounded (no blow-up of the cascade)
     assert np.max(np.abs(np.exp(-1j * np.outer(w, k)) @ hb)) < 2.0
+
+
+def _mo_case(M, T, fs=21.4e9, rho=2, rolloff=0.1):
+    ds = [80e3 * (1.0 + 0.1 * (i % 3)) for i in range(M)]
+    xis = [D.xi_of(d, BETA2, fs) for d in ds]
+    edge = np.pi * (1.0 + rolloff) / rho
+    return xis, edge
+
+
+def test_multi_objective_single_filter_runs_give_individual_fits():
+    """Runs of one filter only (max_window = 1): each filter's weighted LS problem is its own in-band fit
+    (Sec. VI-B, first line of eq. objectives), whatever the starting values."""
+    xis, edge = _mo_case(4, 7)
+    start = [np.full(7, 0.1 + 0.2j) for _ in xis]
+    out = D.multi_objective_ls(start, xis, edge, max_window=1, sweeps=1, N=1024)
+    for h, xi in zip(out, xis):
+        np.testing.assert_allclose(h, D.ls_taps_inband(xi, 7, edge, 1e-3, N=1024), rtol=1e-10, atol=1e-13)
+
+
+def test_multi_objective_descends_and_ends_block_stationary():
+    """Each update solves its weighted LS problem exactly, so the total objective (eq. objectives,
+    all weights 1) never rises over the sweeps, and after the last update the last filter is a
+    stationary point of the total objective: its central-difference derivative along random
+    complex directions vanishes relative to the curvature."""
+    M, T = 5, 5
+    xis, edge = _mo_case(M, T)
+    start = [D.ls_taps_inband(xi, T, edge, 1e-3, N=1024) for xi in xis]
+    totals = [D.multi_objective_total(start, xis, edge)]
+    hs = start
+    for _ in range(3):
+        hs = D.multi_objective_ls(hs, xis, edge, sweeps=1)
+        totals.append(D.multi_objective_total(hs, xis, edge))
+    assert all(b <= a * (1 + 1e-12) for a, b in zip(totals, totals[1:]))
+    assert totals[-1] < 0.7 * totals[0]
+    g = np.random.Generator(np.random.PCG64(11))
+    for _ in range(3):
+        v = g.standard_normal(T) + 1j * g.standard_normal(T)
+        eps = 1e-4
+
+        def J(t):
+            hh = list(hs)
+            hh[-1] = hs[-1] + t * v
+            return D.multi_objective_total(hh, xis, edge)
+        j0, jp, jm = J(0.0), J(eps), J(-eps)
+        slope = (jp - jm) / (2 * eps)
+        curv = (jp - 2 * j0 + jm) / eps ** 2
+        assert curv > 0
+        assert abs(slope) <= 1e-6 * curv
