@@ -46,6 +46,13 @@ LDBP_STPS, TAPS = 5, 15
 P_DBM = 4.0
 RS = 10.7e9
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ldbp_fwd_traffic.json")
+# Fixed plans of the timed forwards (steps per pass, LDS chunks, outputs per thread, folded symmetric
+# filters), so that the kernel traces and counters under profiles/ are of the plan the line reports;
+# --autotune times the autotuner's pick instead.
+HEADLINE_PLAN = (10, 1, 7, 1)
+GENERAL_PLAN = (10, 1, 7, 0)
+MANAKOV_PLAN = (16, 2, 3, 1)
+BIG_BATCH_PLAN = (10, 1, 7, 1)
 BWD_KERNEL_SOURCES = ["paper_2010_14258_amd/csrc/ldbp_bwd.hip", "paper_2010_14258_amd/csrc/ldbp_fir.h",
                       "paper_2010_14258_amd/csrc/ldbp_kernels.h", "paper_2010_14258_amd/csrc/common.h"]
 BWD_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ldbp_bwd_traffic.json")
@@ -210,14 +217,13 @@ def uneven_batch(torch, dev, reps: int):
 def big_batch(torch, dev, W, reps: int):
     """The inference forward on 1,024 waveforms (the 64 received waveforms repeated 16 times): 512 MiB
     per buffer, so input and output no longer fit the 256 MB last-level cache."""
-    from paper_2010_14258_amd import autotune as AT
     from paper_2010_14258_amd import ldbp as L
 
     r = W["r"].repeat(16, 1)
     taps, c, ntap = W["taps"], W["c"], W["ntap"]
     nwave, n = r.shape
     stream = torch.cuda.current_stream(dev)
-    plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=3)
+    plan = BIG_BATCH_PLAN
     y = torch.empty_like(r)
     ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, plan=plan), 1), dtype=torch.uint8, device=dev)
     ms = event_time(torch, stream, lambda: L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan, ws=ws, stream=stream),
@@ -237,7 +243,6 @@ def manakov(torch, dev, reps: int):
     polarisation), 32 x 80 km, PMD-free Manakov channel (Kerr phase 8/9 gamma (|x|^2 + |y|^2)) with 10
     uniform steps per span and amplifier noise, LDBP l = 64 (2 steps per span) with 5 taps shared by
     both polarisations.  Forward and forward + backward."""
-    from paper_2010_14258_amd import autotune as AT
     from paper_2010_14258_amd import init as I
     from paper_2010_14258_amd import ldbp as L
     from paper_2010_14258_amd import ssm as SS
@@ -268,7 +273,7 @@ def manakov(torch, dev, reps: int):
     ell = len(ntap)
     n = r.shape[1]
     stream = torch.cuda.current_stream(dev)
-    plan, _, _ = AT.tune_forward(r, taps, c, ntap, npol=2, symmetric=True, reps=3)
+    plan = MANAKOV_PLAN
     y = torch.empty_like(r)
     ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, 2, plan=plan), 1), dtype=torch.uint8, device=dev)
     ms = event_time(torch, stream,
@@ -339,12 +344,10 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
         z = L.ldbp_forward(r, taps, c, ntap, plan=(0, 0, 0, 1))
         snr_tr = snr_db(TX, z, W["s"], W["p"])
         snr_ls = snr_db(TX, L.ldbp_forward(r, W["taps"], W["c"], W["ntap"], plan=(0, 0, 0, 1)), W["s"], W["p"])
-        sweep, chosen = {}, None
+        sweep = {}
         for k in (1, 2, 3, 5, 10, 20):
             sweep[k] = snr_db(TX, SS.fft_dbp(r, W["dbp_link"](k)), W["s"], W["p"])
-            if chosen is None and sweep[k] >= snr_tr - 0.1:
-                chosen = k
-        k = chosen if chosen is not None else max(sweep, key=lambda q: sweep[q])
+        k, equal = pick_dbp_setting(sweep, snr_tr)
         plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=3)
         ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, plan=plan), 1), dtype=torch.uint8, device=dev)
         ms_l = event_time(torch, stream, lambda: L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan, ws=ws,
@@ -354,8 +357,10 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
         ms_d = event_time(torch, stream, lambda: SS.fft_dbp(r, link, y=y, ws=dws, stream=stream), max(3, reps // 3), 1)
         rows.append({"model": mi, "launch_dbm": p_dbm, "ldbp_trained_snr_db": snr_tr, "ldbp_ls_init_snr_db": snr_ls,
                      "fft_dbp_snr_db_by_steps_per_span": sweep, "fft_dbp_steps_per_span": k,
-                     "fft_dbp_reaches_ldbp_snr": chosen is not None, "ldbp_ms": ms_l, "fft_dbp_ms": ms_d,
-                     "ldbp_plan": list(plan), "ldbp_speedup_at_equal_snr": ms_d / ms_l})
+                     "fft_dbp_reaches_ldbp_snr": equal, "ldbp_ms": ms_l, "fft_dbp_ms": ms_d,
+                     "ldbp_plan": list(plan),
+                     ("ldbp_speedup_at_equal_snr" if equal else "ldbp_speedup_vs_best_fft_dbp_unequal_snr"):
+                         ms_d / ms_l})
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
         del W, r, y, z
         torch.cuda.empty_cache()
@@ -668,6 +673,18 @@ def copy_probe(torch, dev):
     torch.cuda.synchronize()
 
 
+def pick_dbp_setting(sweep, snr_ldbp: float):
+    """FFT-DBP setting to compare with: the fewest steps per span whose SNR is within 0.1 dB of LDBP's
+    (equal SNR).  When no setting reaches LDBP, the fewest steps per span within 0.1 dB of the best
+    FFT-DBP SNR, flagged as not at equal SNR.  Returns (steps per span, at_equal_snr)."""
+    keys = sorted(sweep)
+    for k in keys:
+        if sweep[k] >= snr_ldbp - 0.1:
+            return k, True
+    best = max(sweep.values())
+    return next(k for k in keys if sweep[k] >= best - 0.1), False
+
+
 def snr_db(TX, z, s, p):
     mse, _, _ = TX.rx_mse(z, s, p, RHO_D, RS)
     return 10.0 * math.log10(1.0 / float(mse.mean().item()))
@@ -710,7 +727,10 @@ def main():
     ap.add_argument("--one-stream", action="store_true",
                     help="fwd/pmc/bwd modes: keep every launch on one stream (the kernel's own per-launch time)")
     ap.add_argument("--plan", default=None,
-                    help="forward plan S,chunks,outputs_per_thread,symmetric (default: autotuned, folded)")
+                    help="forward plan S,chunks,outputs_per_thread,symmetric[,one_stream] (default: the fixed "
+                         "headline plan 10,1,7,1)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the forward autotuner's plans instead of the fixed ones")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (use --gpus 1)", file=sys.stderr)
@@ -817,16 +837,19 @@ def main():
         print(json.dumps(out), flush=True)
         return
     from paper_2010_14258_amd import autotune as AT
+    plan_gen = GENERAL_PLAN
     if args.plan:
         plan = tuple(int(v) for v in args.plan.split(","))
-        plan_gen, ms_gen_tuned = None, None
-    else:
-        # bring the GPU to its steady clock before the candidates are compared (about 0.2 s of work)
-        for _ in range(600):
-            L.ldbp_forward(r, taps, c, ntap, y=y, plan=(10, 1, 7, 1), stream=stream)
-        torch.cuda.synchronize()
+    elif args.autotune:
         plan, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=True, reps=10)
-        plan_gen, ms_gen_tuned, _ = AT.tune_forward(r, taps, c, ntap, symmetric=False, reps=10)
+        plan_gen, _, _ = AT.tune_forward(r, taps, c, ntap, symmetric=False, reps=10)
+    else:
+        plan = HEADLINE_PLAN
+    if args.mode != "pmc":
+        # bring the GPU to its steady clock before anything is timed (about 0.2 s of work)
+        for _ in range(600):
+            L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan, stream=stream)
+        torch.cuda.synchronize()
     folded = bool(plan[3])
     ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, plan=plan), 1), dtype=torch.uint8, device=dev)
 
@@ -902,7 +925,9 @@ def main():
                      "split_batch_frac": flops_fwd / (ms_fwd * 1e-3) / 1e12 / FP32_PEAK_TFLOPS},
     }
 
-    if plan_gen is not None:
+    if args.mode == "full":
+        ms_gen_tuned = event_time(torch, stream, lambda: L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan_gen,
+                                                                         stream=stream), args.steps, 2)
         fl_gen = nwave * n * sum(fwd_flops_per_sample_step(t) for t in ntap)
         out["general_taps_forward"] = {"value": ss / (ms_gen_tuned * 1e-3), "unit": "samples*steps/s",
                                        "ms_per_step": ms_gen_tuned, "plan": list(plan_gen),
@@ -958,14 +983,11 @@ def main():
         # equal-SNR comparison with FFT-DBP on the same waveforms
         snr_ldbp = snr_db(TX, z, W["s"], W["p"])
         sweep = {}
-        chosen = None
         for k in (1, 2, 3, 5, 10, 20):
             link = W["dbp_link"](k)
             zd = SS.fft_dbp(r, link)
             sweep[k] = snr_db(TX, zd, W["s"], W["p"])
-            if chosen is None and sweep[k] >= snr_ldbp - 0.1:
-                chosen = k
-        k = chosen if chosen is not None else max(sweep)
+        k, equal = pick_dbp_setting(sweep, snr_ldbp)
         link = W["dbp_link"](k)
         yd = torch.empty_like(r)
         dws = torch.empty(SS.ssm_workspace_size(r, link), dtype=torch.uint8, device=dev)
@@ -976,10 +998,10 @@ def main():
                              max(3, args.steps // 10), 1)
         out["equal_snr"] = {
             "ldbp_snr_db": snr_ldbp, "fft_dbp_snr_db_by_steps_per_span": sweep,
-            "fft_dbp_steps_per_span": k, "fft_dbp_reaches_ldbp_snr": chosen is not None,
+            "fft_dbp_steps_per_span": k, "fft_dbp_reaches_ldbp_snr": equal,
             "ldbp_equalised_samples_per_s": nwave * n / (ms_fwd * 1e-3),
             "fft_dbp_equalised_samples_per_s": nwave * n / (ms_dbp * 1e-3),
-            "ldbp_speedup_at_equal_snr": ms_dbp / ms_fwd,
+            ("ldbp_speedup_at_equal_snr" if equal else "ldbp_speedup_vs_best_fft_dbp_unequal_snr"): ms_dbp / ms_fwd,
             "fft_dbp_1stps_samples_steps_per_s": nwave * n * NSPAN / (ms_dbp1 * 1e-3),
             "fft_dbp_1stps_ms": ms_dbp1,
         }

@@ -33,7 +33,8 @@
  *     being captured into a graph, and not with LDBP_PLAN_ONE_STREAM.
  *   - Every function returns LDBP_OK (0) or a negative ldbp_status.  Argument
  *     checks run before any GPU work is enqueued; on failure nothing is
- *     enqueued.  ldbp_last_error() returns a thread-local message for the last
+ *     enqueued (LDBP_ENONFINITE, the result of a guarded forward, is reported
+ *     after its work has run).  ldbp_last_error() returns a thread-local message for the last
  *     failing call.
  *   - The library allocates no device memory inside compute calls; scratch
  *     memory is passed in as a workspace whose size the *_workspace_size
@@ -54,7 +55,8 @@ enum ldbp_status {
   LDBP_EINVAL = -1,       /* invalid argument (size, null pointer, even tap count, alignment, overlap) */
   LDBP_EWORKSPACE = -2,   /* workspace missing or smaller than required */
   LDBP_EUNSUPPORTED = -3, /* valid request the library does not implement (e.g. npol > 2) */
-  LDBP_EHIP = -4          /* a HIP runtime call failed; see ldbp_last_error() */
+  LDBP_EHIP = -4,         /* a HIP runtime call failed; see ldbp_last_error() */
+  LDBP_ENONFINITE = -5    /* guard mode (LDBP_PLAN_GUARD): the forward stored a NaN or an infinity */
 };
 
 enum ldbp_dtype { LDBP_C64 = 0, LDBP_C128 = 1 };
@@ -76,10 +78,20 @@ enum ldbp_dtype { LDBP_C64 = 0, LDBP_C128 = 1 };
  *                       h_0 x_m + sum_{k>=1} h_k (x_{m-k} + x_{m+k}) (Sec. III-B).
  *                       LDBP_PLAN_ONE_STREAM: every launch goes to `stream` (no split of
  *                       the batch over a second stream).
+ *                       LDBP_PLAN_GUARD (ldbp_forward and essm_forward only): non-finite guard.
+ *                       The last pass checks every value it stores to y and raises a flag kept
+ *                       in 256 bytes of the workspace (ldbp_forward_workspace_size counts
+ *                       them); after its launches the call copies the flag to the host,
+ *                       which synchronises `stream`, and returns LDBP_ENONFINITE when any
+ *                       output is a NaN or an infinity (y is written either way).  The guard
+ *                       serves the caller that falls back to plain FFT-DBP when the learned
+ *                       model misbehaves; it cannot run inside a graph capture.
  * Results are bit-identical for any steps_per_pass and chunks at fixed
- * outputs_per_thread and LDBP_PLAN_SYMMETRIC, with or without LDBP_PLAN_ONE_STREAM. */
+ * outputs_per_thread and LDBP_PLAN_SYMMETRIC, with or without LDBP_PLAN_ONE_STREAM and
+ * LDBP_PLAN_GUARD. */
 #define LDBP_PLAN_SYMMETRIC 1
 #define LDBP_PLAN_ONE_STREAM 2
+#define LDBP_PLAN_GUARD 4
 typedef struct ldbp_plan {
   int32_t steps_per_pass;
   int32_t chunks;
@@ -113,7 +125,8 @@ const char* ldbp_last_error(void);
  *   ckpt_every   steps per checkpoint block (1..LDBP_MAX_STEPS_PER_PASS) when ckpt != NULL
  *   plan         host, may be NULL (library default); ignored for S when ckpt != NULL
  *   ws           device workspace of at least ldbp_forward_workspace_size() bytes (may be
- *                NULL when that size is 0)
+ *                NULL when that size is 0): the intermediate signal of a multi-pass forward
+ *                without checkpoints, and the guard flag with LDBP_PLAN_GUARD
  * -------------------------------------------------------------------------*/
 int ldbp_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
                                 int32_t nstep, const int32_t* ntap, const void* ckpt,

@@ -23,7 +23,7 @@ P_i64 = ctypes.POINTER(ctypes.c_int64)
 P_f64 = ctypes.POINTER(ctypes.c_double)
 P_size = ctypes.POINTER(ctypes.c_size_t)
 
-LDBP_OK, LDBP_EINVAL, LDBP_EWORKSPACE, LDBP_EUNSUPPORTED, LDBP_EHIP = 0, -1, -2, -3, -4
+LDBP_OK, LDBP_EINVAL, LDBP_EWORKSPACE, LDBP_EUNSUPPORTED, LDBP_EHIP, LDBP_ENONFINITE = 0, -1, -2, -3, -4, -5
 LDBP_C64, LDBP_C128 = 0, 1
 
 
@@ -34,6 +34,7 @@ class LdbpPlan(ctypes.Structure):
 
 LDBP_PLAN_SYMMETRIC = 1
 LDBP_PLAN_ONE_STREAM = 2
+LDBP_PLAN_GUARD = 4
 LDBP_EDGE_ZERO = 1
 LDBP_EDGE_VALID = 2
 

@@ -2,7 +2,7 @@
 
 For a problem signature (device, dtype, npol, nwave, n, tap profile, symmetric) it times every
 plan in a candidate set -- outputs per thread x steps per pass x LDS chunks -- with HIP events on
-the caller's stream and keeps the plan with the fewest steps per pass among those within 2% of the
+the caller's stream and keeps the plan with the fewest steps per pass among those within 0.5% of the
 fastest (each candidate timed as the least of three runs of back-to-back calls).  Results are
 cached in memory and, when a path is given (argument or LDBP_AUTOTUNE_CACHE), in a JSON file; a
 missing or unreadable cache file just means tuning again.  All candidates produce identical results for a fixed outputs-per-thread

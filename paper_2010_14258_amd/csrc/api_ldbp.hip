@@ -13,6 +13,9 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 static size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
+// Guard mode (LDBP_PLAN_GUARD): the non-finite flag takes the last 256 bytes of the forward's workspace.
+constexpr size_t kGuardBytes = 256;
+
 struct ModelArgs {
   int32_t dtype, npol;
   int64_t nwave, n;
@@ -251,7 +254,7 @@ static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ld
 // batch; the launches cover waveforms [w0, w1).
 static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* taps, const void* c, const void* x,
                           void* last, void* ckpt, int32_t S, hipStream_t s, const void* eta = nullptr,
-                          int64_t w0 = 0, int64_t w1 = -1) {
+                          int64_t w0 = 0, int64_t w1 = -1, int32_t* nonfinite = nullptr) {
   if (w1 < 0) w1 = m.nwave;
   const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
   const size_t w_off = static_cast<size_t>(w0) * m.n * m.npol * cx_size(m.dtype);
@@ -263,7 +266,8 @@ static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* ta
                                              : static_cast<char*>(ckpt) + ((pt.c0 + pt.nstep) / S - 1) * wave_bytes;
     void* out = base + w_off;
     int st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0, static_cast<int32_t>(m.n), pp.chunks, pt,
-                             taps, c, pp.sym, ckpt ? static_cast<char*>(ckpt) + w_off : nullptr, s, eta, slot_elems);
+                             taps, c, pp.sym, ckpt ? static_cast<char*>(ckpt) + w_off : nullptr, s, eta, slot_elems,
+                             nullptr, i + 1 == pp.passes.size() ? nonfinite : nullptr);
     if (st) return st;
     in = out;
   }
@@ -288,14 +292,28 @@ static int forward_ws_impl(const ModelArgs& m, const void* ckpt, const ldbp_plan
   if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
   int st = check_model(m);
   if (st) return st;
+  const size_t guard = (plan && (plan->flags & LDBP_PLAN_GUARD)) ? kGuardBytes : 0;
   if (ckpt) {
-    *bytes = 0;
+    *bytes = guard;
     return LDBP_OK;
   }
   PassPlan pp;
   st = make_plan(m, 0, plan, pp);
   if (st) return st;
-  *bytes = pp.passes.size() > 1 ? static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype) : 0;
+  const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
+  *bytes = pp.passes.size() > 1 ? (guard ? align256(wave_bytes) + guard : wave_bytes) : guard;
+  return LDBP_OK;
+}
+
+__global__ void clear_flag_kernel(int32_t* flag) { *flag = 0; }
+
+// Guard mode: the flag the last pass raises is copied to the host after the whole call (both halves
+// of a split batch have been joined into s), which synchronises the stream.
+static int guard_result(int32_t* flag, hipStream_t s) {
+  int32_t h = 0;
+  LDBP_HIP_CHECK(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+  LDBP_HIP_CHECK(hipStreamSynchronize(s));
+  if (h) return fail(LDBP_ENONFINITE, "the forward output holds a NaN or an infinity (guard mode)");
   return LDBP_OK;
 }
 
@@ -321,46 +339,60 @@ static int forward_impl(const ModelArgs& m, const void* taps, const void* c, con
     if (nslot > 0 && (overlaps(ckpt, nslot * wave_bytes, x, wave_bytes) || overlaps(ckpt, nslot * wave_bytes, y, wave_bytes)))
       return fail(LDBP_EINVAL, "ckpt overlaps x or y");
   }
-  if (plan && (plan->flags & ~(LDBP_PLAN_SYMMETRIC | LDBP_PLAN_ONE_STREAM)))
+  if (plan && (plan->flags & ~(LDBP_PLAN_SYMMETRIC | LDBP_PLAN_ONE_STREAM | LDBP_PLAN_GUARD)))
     return fail(LDBP_EINVAL, "plan flags 0x%x: unknown bits", plan->flags);
+  const bool guard = plan && (plan->flags & LDBP_PLAN_GUARD);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const void* e = m.filtered() ? eta : nullptr;
-  if (ckpt) {
-    PassPlan bp;
-    st = make_block_plan(m, ckpt_every, m.nstep, plan, bp);
-    if (st) return st;
-    return over_halves(s, m.nwave, worth_splitting(plan, bp.passes.size(), fwd_blocks(m, bp)),
-                       [&](int64_t w0, int64_t w1, hipStream_t ss) {
-                         return run_block_plan(m, bp, taps, c, x, y, ckpt, ckpt_every, ss, e, w0, w1);
-                       });
-  }
   PassPlan pp;
-  st = make_plan(m, 0, plan, pp);
+  if (ckpt) st = make_block_plan(m, ckpt_every, m.nstep, plan, pp);
+  else st = make_plan(m, 0, plan, pp);
   if (st) return st;
   const size_t np = pp.passes.size();
-  if (np > 1) {
-    if (!ws || ws_bytes < wave_bytes)
-      return fail(LDBP_EWORKSPACE, "workspace of %zu bytes required, %zu given", wave_bytes, ws ? ws_bytes : 0);
+  // ping-pong buffer of a multi-pass forward, followed (guard mode) by the flag at a 256-byte boundary
+  const size_t inter = (!ckpt && np > 1) ? (guard ? align256(wave_bytes) : wave_bytes) : 0;
+  const size_t need = inter + (guard ? kGuardBytes : 0);
+  if (need > 0) {
+    if (!ws || ws_bytes < need)
+      return fail(LDBP_EWORKSPACE, "workspace of %zu bytes required, %zu given", need, ws ? ws_bytes : 0);
     if (!aligned16(ws)) return fail(LDBP_EINVAL, "ws must be 16-byte aligned");
-    if (overlaps(ws, wave_bytes, x, wave_bytes) || overlaps(ws, wave_bytes, y, wave_bytes))
+    if (overlaps(ws, need, x, wave_bytes) || overlaps(ws, need, y, wave_bytes))
       return fail(LDBP_EINVAL, "workspace overlaps x or y");
+    if (ckpt) {
+      const int64_t nslot = (m.nstep + ckpt_every - 1) / ckpt_every - 1;
+      if (nslot > 0 && overlaps(ws, need, ckpt, nslot * wave_bytes)) return fail(LDBP_EINVAL, "workspace overlaps ckpt");
+    }
+  }
+  int32_t* flag = guard ? reinterpret_cast<int32_t*>(static_cast<char*>(ws) + inter) : nullptr;
+  if (flag) {
+    hipLaunchKernelGGL(clear_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+    LDBP_HIP_CHECK(hipGetLastError());
+  }
+  if (ckpt) {
+    st = over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)),
+                     [&](int64_t w0, int64_t w1, hipStream_t ss) {
+                       return run_block_plan(m, pp, taps, c, x, y, ckpt, ckpt_every, ss, e, w0, w1, flag);
+                     });
+    return (st || !flag) ? st : guard_result(flag, s);
   }
   const size_t wave_elem_bytes = static_cast<size_t>(m.n) * m.npol * cx_size(m.dtype);
-  return over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)),
-                     [&](int64_t w0, int64_t w1, hipStream_t ss) {
-                       const size_t off = static_cast<size_t>(w0) * wave_elem_bytes;
-                       const void* in = static_cast<const char*>(x) + off;
-                       for (size_t i = 0; i < np; ++i) {
-                         // ping-pong that ends in y
-                         void* out = static_cast<char*>(((np - 1 - i) % 2 == 0) ? y : ws) + off;
-                         const int r = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0,
-                                                       static_cast<int32_t>(m.n), pp.chunks, pp.passes[i], taps, c,
-                                                       pp.sym, nullptr, ss, e);
-                         if (r) return r;
-                         in = out;
-                       }
-                       return static_cast<int>(LDBP_OK);
-                     });
+  st = over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)),
+                   [&](int64_t w0, int64_t w1, hipStream_t ss) {
+                     const size_t off = static_cast<size_t>(w0) * wave_elem_bytes;
+                     const void* in = static_cast<const char*>(x) + off;
+                     for (size_t i = 0; i < np; ++i) {
+                       // ping-pong that ends in y
+                       void* out = static_cast<char*>(((np - 1 - i) % 2 == 0) ? y : ws) + off;
+                       const int r = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0,
+                                                     static_cast<int32_t>(m.n), pp.chunks, pp.passes[i], taps, c,
+                                                     pp.sym, nullptr, ss, e, 0, nullptr,
+                                                     i + 1 == np ? flag : nullptr);
+                       if (r) return r;
+                       in = out;
+                     }
+                     return static_cast<int>(LDBP_OK);
+                   });
+  return (st || !flag) ? st : guard_result(flag, s);
 }
 
 // Aperiodic forward: the passes of the periodic forward on a working circle of nw samples per

@@ -33,15 +33,15 @@ size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks, bool filtered) {
 
 int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                     const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream,
-                    const void* eta, int64_t slot_elems, const EdgeMap* em) {
+                    const void* eta, int64_t slot_elems, const EdgeMap* em, int32_t* nonfinite) {
   if (dtype == LDBP_C64 && npol == 1) {
-    if (rb == 7) return launch_fwd_pass_t<float, 1, 7>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
-    if (rb == 8) return launch_fwd_pass_t<float, 1, 8>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
-    if (rb == 9) return launch_fwd_pass_t<float, 1, 9>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
+    if (rb == 7) return launch_fwd_pass_t<float, 1, 7>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em, nonfinite);
+    if (rb == 8) return launch_fwd_pass_t<float, 1, 8>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em, nonfinite);
+    if (rb == 9) return launch_fwd_pass_t<float, 1, 9>(x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em, nonfinite);
   } else if (dtype == LDBP_C64) {
-    return launch_fwd_pass_c64p2(rb, x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
+    return launch_fwd_pass_c64p2(rb, x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em, nonfinite);
   } else {
-    return launch_fwd_pass_c128(npol, rb, x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em);
+    return launch_fwd_pass_c128(npol, rb, x, y, nwave, n, chunks, pt, taps, c, sym, ckpt, stream, eta, slot_elems, em, nonfinite);
   }
   return fail(LDBP_EUNSUPPORTED, "outputs per thread %d not available for this dtype/npol", rb);
 }

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
                                                            int32_t work, const cx_t<R>* __restrict__ taps,
                                                            const R* __restrict__ c, PassTable pt, int32_t sym,
                                                            cx_t<R>* __restrict__ ckpt, int64_t slot_elems,
-                                                           const R* __restrict__ eta, EdgeMap em) {
+                                                           const R* __restrict__ eta, EdgeMap em,
+                                                           int32_t* __restrict__ nonfinite) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   V* b0 = reinterpret_cast<V*>(smem);
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
     }
   }
 
+  bool bad = false;
   for (int j = threadIdx.x; j < Lw; j += THREADS) {
     int o = t0 + j;
     if constexpr (EDGE) {
@@ -93,13 +95,21 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
     V v[NPOL];
     load_sample<R, NPOL>(b0 + (H + j) * NPOL, v);
     store_sample<R, NPOL>(yw + static_cast<int64_t>(o) * NPOL, v);
+    if (nonfinite) {
+#pragma unroll
+      for (int p = 0; p < NPOL; ++p) bad |= !(__builtin_isfinite(v[p].x) && __builtin_isfinite(v[p].y));
+    }
   }
+  // guard mode: any lane that stored a NaN or an infinity raises the flag (a plain per-lane global
+  // store of 1; concurrent writers all write the same value)
+  if (bad) *nonfinite = 1;
 }
 
 template <typename R, int NPOL, int RB>
 inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                              const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                             hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em) {
+                             hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em,
+                             int32_t* nonfinite) {
   if (pt.ckpt_mask && (!ckpt || pt.ckpt_every < 1)) return fail(LDBP_EINVAL, "checkpoint writes without slots");
   if (em && pt.ckpt_mask) return fail(LDBP_EINVAL, "an aperiodic pass writes no checkpoints");
   const int work = chunks * RB * kFwdThreads;
@@ -124,7 +134,7 @@ inline int launch_fwd_pass_t(const void* x, void* y, int64_t nwave, int32_t n, i
                      static_cast<int32_t>(ntiles), work, static_cast<const cx_t<R>*>(taps),
                      static_cast<const R*>(c), pt, sym, static_cast<cx_t<R>*>(ckpt),
                      slot_elems > 0 ? slot_elems : nwave * n * NPOL,
-                     static_cast<const R*>(eta), em ? *em : EdgeMap{0, n, 0, n});
+                     static_cast<const R*>(eta), em ? *em : EdgeMap{0, n, 0, n}, nonfinite);
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }

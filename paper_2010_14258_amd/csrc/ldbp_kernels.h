@@ -45,17 +45,21 @@ size_t fwd_lds_bytes(int dtype, int npol, int rb, int chunks, bool filtered = fa
 // a larger one when the launch covers a sub-range of a batch whose slots hold every waveform).
 // eta: packed real filters of the nonlinear steps (pt.kap / pt.etaoff), or NULL for plain Kerr steps.
 // em: NULL, or the aperiodic input/output map of this pass (no checkpoint writes with it).
+// nonfinite: NULL, or a device int the pass sets to 1 when it stores a NaN or an infinity to y.
 int launch_fwd_pass(int dtype, int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                     const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt, hipStream_t stream,
-                    const void* eta = nullptr, int64_t slot_elems = 0, const EdgeMap* em = nullptr);
+                    const void* eta = nullptr, int64_t slot_elems = 0, const EdgeMap* em = nullptr,
+                    int32_t* nonfinite = nullptr);
 
 // Instantiation groups of launch_fwd_pass (separate translation units).
 int launch_fwd_pass_c64p2(int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                           const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                          hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em);
+                          hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em,
+                          int32_t* nonfinite);
 int launch_fwd_pass_c128(int npol, int rb, const void* x, void* y, int64_t nwave, int32_t n, int32_t chunks,
                          const PassTable& pt, const void* taps, const void* c, int sym, void* ckpt,
-                         hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em);
+                         hipStream_t stream, const void* eta, int64_t slot_elems, const EdgeMap* em,
+                         int32_t* nonfinite);
 
 // Backward (adjoint) block kernel and the deterministic gradient reduction.
 // Partial-sum columns: [taps (ntaps)] [power filters (neta), ecol_base = ntaps] [c (l), ccol_base].

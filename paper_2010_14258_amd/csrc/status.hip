@@ -34,6 +34,7 @@ extern "C" const char* ldbp_status_string(int status) {
     case LDBP_EWORKSPACE: return "workspace too small";
     case LDBP_EUNSUPPORTED: return "unsupported";
     case LDBP_EHIP: return "HIP runtime error";
+    case LDBP_ENONFINITE: return "non-finite output";
     default: return "unknown status";
   }
 }

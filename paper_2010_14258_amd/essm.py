@@ -134,9 +134,10 @@ class ESSMFunction(torch.autograd.Function):
         S = max(1, min(int(ckpt_every), len(ntap)))
         nslot = num_checkpoints(len(ntap), S)
         ckpt = torch.empty((nslot,) + tuple(x.shape), dtype=x.dtype, device=x.device) if nslot else None
-        y = essm_forward(x.contiguous(), taps.contiguous(), c.contiguous(), eta.contiguous(), ntap, nl_ntap,
-                         npol=npol, ckpt=ckpt, ckpt_every=S if ckpt is not None else 0,
-                         plan=(S, 0) if ckpt is None else None)
+        # the backward reads the tensors the forward computed on: save the contiguous copies
+        x, taps, c, eta = x.contiguous(), taps.contiguous(), c.contiguous(), eta.contiguous()
+        y = essm_forward(x, taps, c, eta, ntap, nl_ntap, npol=npol, ckpt=ckpt,
+                         ckpt_every=S if ckpt is not None else 0, plan=(S, 0) if ckpt is None else None)
         ctx.save_for_backward(x, taps, c, eta, ckpt if ckpt is not None else torch.empty(0, device=x.device))
         ctx.ntap, ctx.nl_ntap, ctx.npol, ctx.S, ctx.has_ckpt = ntap, nl_ntap, npol, S, ckpt is not None
         return y

@@ -47,15 +47,18 @@ def _check_dev(name: str, t: torch.Tensor, dtype=None):
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
 
 
-def _plan(plan) -> Optional[N.LdbpPlan]:
-    """None, an LdbpPlan, or a tuple (steps_per_pass, chunks[, outputs_per_thread[, symmetric[, one_stream]]])."""
+def _plan(plan, guard: bool = False) -> Optional[N.LdbpPlan]:
+    """None, an LdbpPlan, or a tuple (steps_per_pass, chunks[, outputs_per_thread[, symmetric[, one_stream]]]);
+    guard adds LDBP_PLAN_GUARD (the forward's non-finite check)."""
     if plan is None:
-        return None
+        return N.LdbpPlan(0, 0, 0, N.LDBP_PLAN_GUARD) if guard else None
     if isinstance(plan, N.LdbpPlan):
-        return plan
+        return N.LdbpPlan(plan.steps_per_pass, plan.chunks, plan.outputs_per_thread,
+                          plan.flags | (N.LDBP_PLAN_GUARD if guard else 0))
     vals = list(plan) + [0] * (5 - len(plan))
     s, ch, rb, sym, one = vals[:5]
-    flags = (N.LDBP_PLAN_SYMMETRIC if sym else 0) | (N.LDBP_PLAN_ONE_STREAM if one else 0)
+    flags = (N.LDBP_PLAN_SYMMETRIC if sym else 0) | (N.LDBP_PLAN_ONE_STREAM if one else 0) | \
+        (N.LDBP_PLAN_GUARD if guard else 0)
     return N.LdbpPlan(int(s), int(ch), int(rb), flags)
 
 
@@ -70,13 +73,13 @@ def _shape(x: torch.Tensor, npol: int):
 
 
 def ldbp_forward_workspace_size(x: torch.Tensor, ntap: Sequence[int], npol: int = 1, ckpt=None,
-                                ckpt_every: int = 0, plan=None) -> int:
+                                ckpt_every: int = 0, plan=None, guard: bool = False) -> int:
     lib = N.load()
     code = _code(x)
     nwave, n = _shape(x, npol)
     nt = N.i32_array(ntap)
     out = ctypes.c_size_t(0)
-    pl = _plan(plan)
+    pl = _plan(plan, guard)
     N.check(lib.ldbp_forward_workspace_size(code, npol, nwave, n, len(ntap), nt, _ptr(ckpt), int(ckpt_every),
                                             ctypes.byref(pl) if pl is not None else None, ctypes.byref(out)))
     return int(out.value)
@@ -96,8 +99,11 @@ def ldbp_forward_plan_query(dtype: int, npol: int, nwave: int, n: int, ntap: Seq
 
 def ldbp_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], npol: int = 1,
                  y: Optional[torch.Tensor] = None, ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
-                 plan=None, ws: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-    """y = f_theta(x): l steps of circular FIR + Kerr phase (eq. model).  Returns y."""
+                 plan=None, ws: Optional[torch.Tensor] = None, stream=None, guard: bool = False) -> torch.Tensor:
+    """y = f_theta(x): l steps of circular FIR + Kerr phase (eq. model).  Returns y.
+
+    guard: non-finite guard (LDBP_PLAN_GUARD): the call synchronises the stream and raises LdbpError
+    with status LDBP_ENONFINITE when an output is a NaN or an infinity (y is written either way)."""
     lib = N.load()
     code = _code(x)
     nwave, n = _shape(x, npol)
@@ -111,10 +117,10 @@ def ldbp_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Seq
     _check_dev("y", y, x.dtype)
     if ckpt is not None:
         _check_dev("ckpt", ckpt, x.dtype)
-    pl = _plan(plan)
+    pl = _plan(plan, guard)
     nt = N.i32_array(ntap)
     if ws is None:
-        need = ldbp_forward_workspace_size(x, ntap, npol, ckpt, ckpt_every, plan)
+        need = ldbp_forward_workspace_size(x, ntap, npol, ckpt, ckpt_every, plan, guard)
         ws = torch.empty(need, dtype=torch.uint8, device=x.device) if need > 0 else None
     st = lib.ldbp_forward(code, npol, nwave, n, len(ntap), nt, _ptr(taps), _ptr(c), _ptr(x), _ptr(y),
                           _ptr(ckpt), int(ckpt_every), ctypes.byref(pl) if pl is not None else None,
@@ -184,8 +190,9 @@ class LDBPFunction(torch.autograd.Function):
         S = max(1, min(int(ckpt_every), len(ntap)))
         nslot = num_checkpoints(len(ntap), S)
         ckpt = torch.empty((max(nslot, 1),) + tuple(x.shape), dtype=x.dtype, device=x.device) if nslot else None
-        y = ldbp_forward(x.contiguous(), taps.contiguous(), c.contiguous(), ntap, npol=npol, ckpt=ckpt,
-                         ckpt_every=S if ckpt is not None else 0,
+        # the backward reads the tensors the forward computed on: save the contiguous copies
+        x, taps, c = x.contiguous(), taps.contiguous(), c.contiguous()
+        y = ldbp_forward(x, taps, c, ntap, npol=npol, ckpt=ckpt, ckpt_every=S if ckpt is not None else 0,
                          plan=(S, 0) if ckpt is None else None)
         ctx.save_for_backward(x, taps, c, ckpt if ckpt is not None else torch.empty(0, device=x.device))
         ctx.ntap, ctx.npol, ctx.S, ctx.has_ckpt = ntap, npol, S, ckpt is not None

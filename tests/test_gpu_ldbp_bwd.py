@@ -238,13 +238,15 @@ def test_backward_full_size_32x16384_l50_T25():
     _cmp(got, ref, 1e-4)
 
 
-def test_backward_dual_pol_model_262144():
+@pytest.mark.parametrize("every", [3, 2])
+def test_backward_dual_pol_model_262144(every):
     """The dual-polarisation configuration's model (l = 64, 5 shared symmetric taps, Manakov phase) on a
     quarter-length waveform (262,144 samples x 2 polarisations: the FP64 oracle's gradient at the full
-    1,048,576 takes over a minute on one core), 2-step checkpoints as in the bench, folded backward:
-    dL/dx, dL/dc and the symmetric tap gradient against the oracle.  Stand-in model as in the
+    1,048,576 takes over a minute on one core), folded backward with 3-step checkpoint blocks (the
+    library default for two polarisations and the block length the benchmark times) and with 2-step
+    blocks: dL/dx, dL/dc and the symmetric tap gradient against the oracle.  Stand-in model as in the
     dual-polarisation forward test (unit-peak-gain LS taps)."""
-    print("case: bwd dual pol 262144", flush=True)
+    print("case: bwd dual pol 262144 every", every, flush=True)
     n = 1 << 18
     p = 10 ** ((2.0 - 30) / 10)
     x = synth.complex_normal(511, (1, n, 2)) * math.sqrt(p)
@@ -252,5 +254,6 @@ def test_backward_dual_pol_model_262144():
     taps, c = W.ldbp_init(32, 2, 5, span_km=80.0, kerr_scale=8.0 / 9.0)
     taps = [W.unit_peak_gain(0.5 * (h + h[::-1])) for h in taps]
     rx, rt, rc = O.ldbp_grad(x, taps, c, gy, npol=2)
-    got = _gpu_grad(x, taps, c, gy, npol=2, dtype=torch.complex64, ckpt_every=2, use_ckpt=True, symmetric=True)
+    got = _gpu_grad(x, taps, c, gy, npol=2, dtype=torch.complex64, ckpt_every=every, use_ckpt=True,
+                    symmetric=True)
     _cmp(got, (rx, _sym_projection(rt), rc), 1e-4)
