@@ -111,4 +111,4 @@ def test_unknown_plan_flags_are_rejected():
     taps, c, ntap = _model(11, [5, 3], torch.complex64)
     from paper_2010_14258_amd import _native as N
     with pytest.raises(N.LdbpError):
-        G.ldbp_forward(x, taps, c, ntap, plan=N.LdbpPlan(0, 0, 0, 4))
+        G.ldbp_forward(x, taps, c, ntap, plan=N.LdbpPlan(0, 0, 0, 8))
