@@ -144,6 +144,28 @@ int ldbp_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
                             int32_t* tile_len, int32_t* max_steps_per_pass);
 
 /* ---------------------------------------------------------------------------
+ * Forward without allocation, for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation and kernels as ldbp_forward with the same arguments (results bit-identical to
+ * ldbp_forward with LDBP_PLAN_ONE_STREAM added to the plan), without ws / ws_bytes: the
+ * workspace ldbp_forward_workspace_size would ask for comes from a static device array of
+ * LDBP_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the process ends.
+ *   - Returns LDBP_EWORKSPACE, before any GPU work, when the call would need more than
+ *     LDBP_NOALLOC_SCRATCH_BYTES (a multi-pass forward without checkpoints needs one
+ *     intermediate signal, nwave*n*npol complex values, plus 256 bytes with LDBP_PLAN_GUARD).
+ *   - Always runs on `stream` alone (LDBP_PLAN_ONE_STREAM is implied).
+ *   - Calls no hipMalloc/hipFree; the first call on a device looks up the array's address
+ *     on that device (hipGetSymbolAddress) and keeps it.
+ *   - Every call on one device shares that device's array: calls that overlap in time on one
+ *     device (several streams or host threads) race and must be serialised by the caller.
+ * -------------------------------------------------------------------------*/
+#define LDBP_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int ldbp_forward_noalloc(int32_t dtype, int32_t npol, int64_t nwave, int64_t n,
+                         int32_t nstep, const int32_t* ntap, const void* taps, const void* c,
+                         const void* x, void* y, void* ckpt, int32_t ckpt_every,
+                         const ldbp_plan* plan, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Generalised enhanced SSM (Sec. III-D, eq. nl_filtered with a filter per step): LDBP whose
  * nonlinear steps filter the power before the phase.  Step i is
  *   u   = h^(i) * x                                        (as in ldbp_forward)

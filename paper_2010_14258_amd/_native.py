@@ -25,6 +25,7 @@ P_size = ctypes.POINTER(ctypes.c_size_t)
 
 LDBP_OK, LDBP_EINVAL, LDBP_EWORKSPACE, LDBP_EUNSUPPORTED, LDBP_EHIP, LDBP_ENONFINITE = 0, -1, -2, -3, -4, -5
 LDBP_C64, LDBP_C128 = 0, 1
+LDBP_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 
 class LdbpPlan(ctypes.Structure):
@@ -60,6 +61,8 @@ SIGNATURES = {
                                               c_int32, P_plan, P_size]),
     "ldbp_forward": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_int32, P_plan, c_void_p, c_size_t, c_void_p]),
+    "ldbp_forward_noalloc": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_void_p, c_void_p,
+                                       c_void_p, c_void_p, c_void_p, c_int32, P_plan, c_void_p]),
     "ldbp_forward_plan_query": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, c_int32, P_plan,
                                           P_i32, P_i32, P_i32]),
     "essm_forward_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, c_int32, P_i32, P_i32, c_void_p,

@@ -2,6 +2,7 @@
 // validation, planning, pass sequencing and the batch split over a second stream.
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -522,6 +523,65 @@ static int plan_query_impl(const ModelArgs& m, int32_t ckpt_every, const ldbp_pl
 }
 
 }  // namespace ldbp
+
+namespace ldbp {
+
+// ---------------------------------------------------------------- forward without allocation
+//
+// ldbp_forward_noalloc runs ldbp_forward with its workspace (the ping-pong buffer of a multi-pass
+// forward and the guard flag) taken from `scratch`, a static device array that every GPU the library
+// runs on holds until the process ends.  Host code never uses the array's name as an address: its
+// device address comes from hipGetSymbolAddress, once per device, on the first call with that
+// device current.  Every call on a device shares that device's array, so calls that overlap in time
+// on one device (other streams, other host threads) race; the guard flag is cleared by a kernel at
+// the start of each guarded call, and the ping-pong buffer is fully written before it is read.
+static __device__ __align__(256) unsigned char scratch[LDBP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(void** out) {
+  int dev = -1;
+  LDBP_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(LDBP_EUNSUPPORTED, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    LDBP_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(LDBP_EHIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LDBP_OK;
+}
+
+}  // namespace ldbp
+
+extern "C" int ldbp_forward_noalloc(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
+                                    const int32_t* ntap, const void* taps, const void* c, const void* x, void* y,
+                                    void* ckpt, int32_t ckpt_every, const ldbp_plan* plan, void* stream) {
+  const ModelArgs m{dtype, npol, nwave, n, nstep, ntap};
+  // always one stream: the batch split would create a second stream on first use
+  ldbp_plan p{0, 0, 0, LDBP_PLAN_ONE_STREAM};
+  if (plan)
+    p = ldbp_plan{plan->steps_per_pass, plan->chunks, plan->outputs_per_thread, plan->flags | LDBP_PLAN_ONE_STREAM};
+  size_t need = 0;
+  int st = forward_ws_impl(m, ckpt, &p, &need);
+  if (st) return st;
+  if (need > LDBP_NOALLOC_SCRATCH_BYTES)
+    return fail(LDBP_EWORKSPACE,
+                "ldbp_forward_noalloc needs %zu bytes of scratch; its static scratch holds %zu "
+                "(LDBP_NOALLOC_SCRATCH_BYTES): use ldbp_forward with a workspace, or a smaller batch",
+                need, static_cast<size_t>(LDBP_NOALLOC_SCRATCH_BYTES));
+  void* ws = nullptr;
+  if (need > 0) {
+    st = scratch_address(&ws);
+    if (st) return st;
+  }
+  return forward_impl(m, taps, c, nullptr, x, y, ckpt, ckpt_every, &p, ws,
+                      need > 0 ? static_cast<size_t>(LDBP_NOALLOC_SCRATCH_BYTES) : 0, stream);
+}
 
 extern "C" int ldbp_forward_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, int32_t nstep,
                                            const int32_t* ntap, const void* ckpt, int32_t ckpt_every,

@@ -129,6 +129,32 @@ def ldbp_forward(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Seq
     return y
 
 
+def ldbp_forward_noalloc(x: torch.Tensor, taps: torch.Tensor, c: torch.Tensor, ntap: Sequence[int], y: torch.Tensor,
+                         npol: int = 1, ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0, plan=None,
+                         stream=None, guard: bool = False) -> torch.Tensor:
+    """``ldbp_forward`` through the entry point that allocates nothing: the caller passes y (and ckpt), and
+    the intermediate signal comes from the library's static device scratch (at most
+    LDBP_NOALLOC_SCRATCH_BYTES; larger calls raise LdbpError with LDBP_EWORKSPACE).  Always one stream;
+    calls that overlap on one device share the scratch and race."""
+    lib = N.load()
+    code = _code(x)
+    nwave, n = _shape(x, npol)
+    _check_dev("x", x)
+    _check_dev("taps", taps, x.dtype)
+    _check_dev("c", c, _real_dtype(code))
+    _check_dev("y", y, x.dtype)
+    if taps.numel() != sum(int(t) for t in ntap) or c.numel() != len(ntap):
+        raise ValueError("taps/c sizes do not match ntap")
+    if ckpt is not None:
+        _check_dev("ckpt", ckpt, x.dtype)
+    pl = _plan(plan, guard)
+    st = lib.ldbp_forward_noalloc(code, npol, nwave, n, len(ntap), N.i32_array(ntap), _ptr(taps), _ptr(c), _ptr(x),
+                                  _ptr(y), _ptr(ckpt), int(ckpt_every), ctypes.byref(pl) if pl is not None else None,
+                                  stream_handle(stream, x.device))
+    N.check(st)
+    return y
+
+
 def ldbp_backward_workspace_size(x: torch.Tensor, ntap: Sequence[int], npol: int = 1, ckpt=None,
                                  ckpt_every: int = 0) -> int:
     lib = N.load()

@@ -212,3 +212,20 @@ def test_guarded_forward_checks_workspace_before_any_launch():
                           ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 21), None, 0, ctypes.byref(g),
                           ctypes.c_void_p(1 << 22), 128, None)
     assert st == N.LDBP_EWORKSPACE
+
+
+def test_noalloc_forward_rejects_batches_beyond_its_scratch_before_any_gpu_work():
+    """The forward without allocation checks its scratch need on the host: a multi-pass forward whose
+    intermediate signal exceeds LDBP_NOALLOC_SCRATCH_BYTES returns LDBP_EWORKSPACE (no GPU here, so a
+    HIP call would have failed with LDBP_EHIP instead)."""
+    lib = N.load()
+    ntap = N.i32_array([15] * 50)
+    n = N.LDBP_NOALLOC_SCRATCH_BYTES // 8 // 4 + 1            # 4 waveforms: one sample more than fits
+    st = lib.ldbp_forward_noalloc(0, 1, 4, n, 50, ntap, 16, 16, 4096, 8192, None, 0, None, None)
+    assert st == N.LDBP_EWORKSPACE
+    assert b"LDBP_NOALLOC_SCRATCH_BYTES" in lib.ldbp_last_error()
+    # argument errors come first, as for ldbp_forward
+    assert lib.ldbp_forward_noalloc(0, 1, 4, 64, 1, N.i32_array([4]), 16, 16, 4096, 8192, None, 0, None,
+                                    None) == N.LDBP_EINVAL
+    assert lib.ldbp_forward_noalloc(0, 3, 4, 64, 1, N.i32_array([5]), 16, 16, 4096, 8192, None, 0, None,
+                                    None) == N.LDBP_EUNSUPPORTED
