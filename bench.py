@@ -238,6 +238,42 @@ def big_batch(torch, dev, W, reps: int):
             "algorithmic_hbm_gbs": moved / (ms * 1e-3) / 1e9, "hbm_frac": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
+ROOF_STEPS_PER_PASS = (1, 2, 3, 4, 6, 10)
+
+
+def roof_sweep(torch, dev, W, reps: int, warmup: int):
+    """The 1,024-waveform forward (folded 15-tap filters, l = 50) at each steps-per-pass count of
+    ROOF_STEPS_PER_PASS, one stream: time per forward and per launch, algorithmic HBM bytes (read and
+    write every sample once per pass) and flops per second."""
+    from paper_2010_14258_amd import ldbp as L
+
+    r = W["r"].repeat(16, 1)
+    taps, c, ntap = W["taps"], W["c"], W["ntap"]
+    nwave, n = r.shape
+    stream = torch.cuda.current_stream(dev)
+    y = torch.empty_like(r)
+    rows = []
+    flops = nwave * n * sum(fwd_flops_per_sample_step(t, True) for t in ntap)
+    for S in ROOF_STEPS_PER_PASS:
+        plan = (S, 1, 7, 1, 1)
+        ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, plan=plan), 1), dtype=torch.uint8,
+                         device=dev)
+        ms = event_time(torch, stream, lambda: L.ldbp_forward(r, taps, c, ntap, y=y, plan=plan, ws=ws,
+                                                              stream=stream), reps, warmup)
+        npass, tile_len, _ = L.ldbp_forward_plan_query(0, 1, nwave, n, ntap, plan=plan)
+        moved = npass * nwave * n * 16
+        rows.append({"steps_per_pass": S, "plan": list(plan[:4]), "passes": npass, "tile_len": tile_len,
+                     "ms": ms, "us_per_launch": ms / npass * 1e3,
+                     "value": nwave * n * len(ntap) / (ms * 1e-3),
+                     "algorithmic_bytes_per_launch": nwave * n * 16,
+                     "algorithmic_hbm_gbs": moved / (ms * 1e-3) / 1e9,
+                     "hbm_frac": moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "achieved_tflops": flops / (ms * 1e-3) / 1e12,
+                     "alu_frac": flops / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS})
+        del ws
+    return {"nwave": nwave, "n": n, "steps_l": len(ntap), "taps": TAPS, "rows": rows}
+
+
 def manakov(torch, dev, reps: int):
     """Dual polarisation: 8 waveforms x 2^20 samples x 2 polarisations (524,288 16-QAM symbols per
     polarisation), 32 x 80 km, PMD-free Manakov channel (Kerr phase 8/9 gamma (|x|^2 + |y|^2)) with 10
@@ -673,6 +709,19 @@ def copy_probe(torch, dev):
     torch.cuda.synchronize()
 
 
+def streaming_probe(torch, dev, reps: int):
+    """What plain streaming kernels reach on this GPU (512 MiB in, 512 MiB out, beyond the last-level
+    cache): a device-to-device copy and an elementwise scaling, HIP-event timed; read + write bytes."""
+    x = torch.ones(COPY_PROBE_ELEMS, dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+    moved = 2 * COPY_PROBE_ELEMS * 8
+    ms_copy = event_time(torch, stream, lambda: y.copy_(x), reps, 2)
+    ms_scale = event_time(torch, stream, lambda: torch.mul(x, 2.0, out=y), reps, 2)
+    return {"bytes_moved": moved, "copy_ms": ms_copy, "copy_gbs": moved / (ms_copy * 1e-3) / 1e9,
+            "scale_ms": ms_scale, "scale_gbs": moved / (ms_scale * 1e-3) / 1e9}
+
+
 def pick_dbp_setting(sweep, snr_ldbp: float):
     """FFT-DBP setting to compare with: the fewest steps per span whose SNR is within 0.1 dB of LDBP's
     (equal SNR).  When no setting reaches LDBP, the fewest steps per span within 0.1 dB of the best
@@ -698,7 +747,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
     ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "variants", "dbp", "snr", "essm", "e1",
-                                       "init", "e8"],
+                                       "init", "e8", "roof"],
                     default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "bwd: the training step (checkpointed forward + backward) and a copy probe; "
@@ -709,7 +758,8 @@ def main():
                          "essm: train conventional and generalised ESSM (and LDBP) with one step per span; "
                          "e1: the 25 x 80 km scenario with Gaussian symbols and 9 -> 5/3-tap pruning; "
                          "init: least-squares, unit and random initialisation on that link; "
-                         "e8: the 32 GBd scenario (symmetric-SSM LDBP, 2 and 4 steps per span)")
+                         "e8: the 32 GBd scenario (symmetric-SSM LDBP, 2 and 4 steps per span); "
+                         "roof: the 1,024-waveform forward at 1-10 steps per pass (where the memory roof sits)")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
@@ -825,6 +875,15 @@ def main():
         print(json.dumps({"mode": "bwd", "fwd_bwd_ms": ms, "ckpt_every": S, "one_stream": args.one_stream,
                           "nwave": nwave, "n": n, "steps_l": ell, "taps": TAPS,
                           "copy_probe": "3 copies of 512 MiB"}), flush=True)
+        return
+    if args.mode == "roof":
+        # where the memory roof sits: the forward on 1,024 waveforms (512 MiB per buffer, beyond the
+        # last-level cache) at 1 to 10 steps per pass, every launch on one stream, then the copy probe
+        # that calibrates FETCH_SIZE / WRITE_SIZE in counter runs
+        out = {"mode": "roof", "plans": roof_sweep(torch, dev, W, args.steps, args.warmup),
+               "streaming": streaming_probe(torch, dev, args.steps)}
+        copy_probe(torch, dev)
+        print(json.dumps(out), flush=True)
         return
     if args.mode == "variants":
         # the generalised ESSM (forward; forward with checkpoints + backward) and overlap-save streaming

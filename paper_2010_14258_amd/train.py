@@ -21,8 +21,10 @@ unit filters and train with the rest; ``essm_shared`` ties them to one filter ap
 (the conventional ESSM, whose gradient is the sum of the per-step filter gradients), and
 ``train_taps = False`` keeps the linear steps at their initialisation.
 
-Batches are a pure function of (seed, iteration): a run resumed from a checkpoint continues
-bit for bit like an uninterrupted one.
+Batches are a pure function of (seed, iteration) -- with ``data_pool`` > 0, of (seed, iteration mod
+data_pool), a fixed training set of that many batches for configurations whose channel simulation
+would dominate every iteration -- so a run resumed from a checkpoint continues bit for bit like an
+uninterrupted one.
 """
 from __future__ import annotations
 
@@ -80,6 +82,8 @@ class TrainConfig:
     essm_shared: bool = False         # one filter in every nonlinear step (conventional ESSM)
     symbols: str = "qam16"            # "qam16", or "gauss": i.i.d. circularly-symmetric Gaussian symbols
     t_final_alt: int = 0              # > 0: odd-numbered layers prune to this length instead of t_final
+    peak_normalise: bool = False      # scale every initial filter to unit peak gain (non-expansive cascade)
+    data_pool: int = 0                # > 0: training batches cycle through this many fixed batches
 
 
 def pruning_plan(t_init: Sequence[int], t_final: Sequence[int], iters: int, frac: float):
@@ -126,6 +130,10 @@ class Trainer:
                                         random_seed=cfg.seed if cfg.random_init else None, method=cfg.init_method)
         if cfg.random_init and cfg.symmetric:
             raise ValueError("random filters are not symmetric: use symmetric=False with random_init")
+        if cfg.peak_normalise:
+            # least-squares filters whose gain exceeds one outside the signal band expand the out-of-band
+            # noise at every step; over many short steps the cascade blows up unless each is non-expansive
+            taps = [I.unit_peak_gain(h) for h in taps]
         if cfg.symmetric:
             # the least-squares fit of an even response is symmetric up to rounding; make it exact, since
             # the folded kernels read only one side of each filter
@@ -252,7 +260,7 @@ class Trainer:
         while self.events_done < len(self.plan) and self.plan[self.events_done][0] <= self.it:
             self._prune(self.plan[self.events_done][1])
             self.events_done += 1
-        r, s, p = self.batch(self.it)
+        r, s, p = self.batch(self.it % cfg.data_pool if cfg.data_pool > 0 else self.it)
         z, ck = self.forward(r, ckpt=True)
         S = max(1, min(cfg.ckpt_every, len(self.ntap)))
         mse, _, gz = TX.rx_mse(z, s, p, cfg.rho_d, cfg.rs, cfg.rolloff, npol=cfg.npol, want_grad=True)
