@@ -358,7 +358,7 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
         t0 = time.perf_counter()
         curve = []
         for it in range(iters):
-            loss = trn.step()
+            loss = trn.step(sync=(it + 1) % 250 == 0)
             if (it + 1) % 250 == 0:
                 curve.append([it + 1, loss, int(sum(trn.ntap))])
                 print(f"train {t_init}->{t_final} {it + 1}/{iters} loss {loss:.4e} taps {sum(trn.ntap)} "
@@ -402,6 +402,45 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
         torch.cuda.empty_cache()
     return {"workload": "64 waveforms x 65,536 c64 samples, 10 x 100 km, LDBP l = 50 (5 steps per span) trained",
             "train_iterations": iters, "models": out_models, "by_power": rows}
+
+
+def manakov_trained(torch, dev, iters: int, powers, pool: int = 4, channel_steps: int = 25):
+    """Training of the dual-polarisation configuration: 8 waveforms x 2^20 samples x 2 polarisations per
+    batch (independent 16-QAM per polarisation, 2 samples/symbol), 32 x 80 km PMD-free Manakov channel
+    simulated at 4 samples/symbol with `channel_steps` uniform steps per span and amplifier noise;
+    LDBP l = 64 (2 steps per span), 5 taps shared by both polarisations, least-squares filters at unit
+    peak gain.  The channel simulation of a batch costs about as much as 30 training iterations, so
+    training cycles through a fixed pool of `pool` batches (32 M symbols); SNRs are measured on held-out
+    batches.  Reports the initial and trained SNR per power, FFT-DBP at 1, 2 and 4 steps per span on
+    the same held-out waveforms, and the training time."""
+    from paper_2010_14258_amd import train as TRN
+
+    cfg = TRN.TrainConfig(nwave=8, nsym=524288, nspan=32, span_km=80.0, channel_steps=channel_steps,
+                          ldbp_steps=2, t_init=5, t_final=5, iters=iters, powers_dbm=tuple(powers), npol=2,
+                          peak_normalise=True, data_pool=pool, ckpt_every=3, seed=501)
+    trn = TRN.Trainer(cfg, device=dev)
+    init = {p_: trn.evaluate(nbatch=1, p_dbm=p_) for p_ in powers}
+    dbp = {p_: {k: trn.evaluate_fft_dbp(k, nbatch=1, p_dbm=p_) for k in (1, 2, 4)} for p_ in powers}
+    for it in range(pool):                # simulate the pool before the clock starts
+        trn.train_batch(it)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    curve = []
+    for it in range(iters):
+        loss = trn.step(sync=(it + 1) % 250 == 0)
+        if (it + 1) % 250 == 0:
+            curve.append([it + 1, loss])
+            print(f"manakov train {it + 1}/{iters} loss {loss:.4e} {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    trained = {p_: trn.evaluate(nbatch=1, p_dbm=p_) for p_ in powers}
+    return {"mode": "manakov_train",
+            "workload": "8 x 1,048,576 x 2 pol, 32 x 80 km Manakov, l = 64 (2 steps/span), 5 shared taps",
+            "iters": iters, "pool_batches": pool, "channel_steps_per_span": channel_steps,
+            "train_s": train_s, "ms_per_iteration": train_s / iters * 1e3,
+            "ls_unit_peak_init_snr_db": init, "trained_snr_db": trained, "fft_dbp_snr_db": dbp,
+            "loss_curve": curve, "held_out": "1 batch per power (8 x 524,288 x 2 symbols) from seeds not trained on"}
 
 
 def essm_timing(torch, dev, W, reps: int, kappa: int = 20, plan=None):
@@ -511,7 +550,7 @@ def essm_trained(torch, dev, iters: int, powers, kappa: int = 20, ntaps: int = 1
         t0 = time.perf_counter()
         curve = []
         for it in range(iters):
-            loss = trn.step()
+            loss = trn.step(sync=(it + 1) % 250 == 0)
             if (it + 1) % 250 == 0:
                 curve.append([it + 1, loss])
                 print(f"train {name} {it + 1}/{iters} loss {loss:.4e} {time.perf_counter() - t0:.0f} s",
@@ -576,7 +615,7 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
     end = iters if stop_at is None else min(stop_at, iters)
     t0 = time.perf_counter()
     while trn.it < end:
-        loss = trn.step()
+        loss = trn.step(sync=(trn.it + 1) % 500 == 0)
         if trn.it % 500 == 0:
             curve.append([trn.it, loss, int(sum(trn.ntap))])
             print(f"e1 train {trn.it}/{iters} loss {loss:.4e} taps {list(trn.ntap)[:4]}... "
@@ -632,7 +671,7 @@ def e8_reduced(torch, dev, iters: int, powers):
         t0 = time.perf_counter()
         curve = []
         while trn.it < iters:
-            loss = trn.step()
+            loss = trn.step(sync=(trn.it + 1) % 500 == 0)
             if trn.it % 500 == 0:
                 curve.append([trn.it, loss])
                 print(f"e8 {stps} StPS {trn.it}/{iters} loss {loss:.4e} {time.perf_counter() - t0:.0f} s",
@@ -682,7 +721,7 @@ def init_schemes(torch, dev, iters: int, every: int = 1000, schemes=("least_squa
         curve = [[0, trn.evaluate(nbatch=2, p_dbm=0.0)]]
         t0 = time.perf_counter()
         while trn.it < iters:
-            trn.step()
+            trn.step(sync=False)
             if trn.it % every == 0:
                 curve.append([trn.it, trn.evaluate(nbatch=2, p_dbm=0.0)])
                 print(f"init {name} {trn.it}/{iters} SNR {curve[-1][1]:.2f} dB {time.perf_counter() - t0:.0f} s",
@@ -747,7 +786,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
     ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "variants", "dbp", "snr", "essm", "e1",
-                                       "init", "e8", "roof"],
+                                       "init", "e8", "roof", "manakov_train"],
                     default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "bwd: the training step (checkpointed forward + backward) and a copy probe; "
@@ -759,7 +798,9 @@ def main():
                          "e1: the 25 x 80 km scenario with Gaussian symbols and 9 -> 5/3-tap pruning; "
                          "init: least-squares, unit and random initialisation on that link; "
                          "e8: the 32 GBd scenario (symmetric-SSM LDBP, 2 and 4 steps per span); "
-                         "roof: the 1,024-waveform forward at 1-10 steps per pass (where the memory roof sits)")
+                         "roof: the 1,024-waveform forward at 1-10 steps per pass (where the memory roof sits); "
+                         "manakov_train: train the dual-polarisation 8 x 2^20 x 2 configuration (--train-iters, "
+                         "--powers)")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
@@ -805,11 +846,11 @@ def main():
         from paper_2010_14258_amd import train as TRN
         trn = TRN.Trainer(TRN.TrainConfig(iters=5000), device=dev)
         for _ in range(max(1, args.warmup)):
-            trn.step()
+            trn.step(sync=False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(args.steps):
-            trn.step()
+            trn.step(sync=False)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "train", "iteration_ms": (time.perf_counter() - t1) / args.steps * 1e3,
                           "iterations": args.steps, "warmup": max(1, args.warmup)}), flush=True)
@@ -830,6 +871,10 @@ def main():
                          os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, not args.fixed_c,
                          args.lr_schedule, args.prune_frac)
         print(json.dumps(out), flush=True)
+        return
+    if args.mode == "manakov_train":
+        print(json.dumps(manakov_trained(torch, dev, args.train_iters,
+                                         [float(v) for v in args.powers.split(",")])), flush=True)
         return
     if args.mode == "e8":
         print(json.dumps(e8_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")])),
@@ -1067,11 +1112,11 @@ def main():
         # one iteration of the 32 x 16,384 training configuration (l = 50, 25 taps, channel 1,000 steps)
         from paper_2010_14258_amd import train as TRN
         trn = TRN.Trainer(TRN.TrainConfig(iters=5000), device=dev)
-        trn.step()
+        trn.step(sync=False)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(3):
-            trn.step()
+            trn.step(sync=False)
         torch.cuda.synchronize()
         out["train_iteration_ms"] = (time.perf_counter() - t1) / 3 * 1e3
         del trn

@@ -167,7 +167,9 @@ class Trainer:
             if any(t < cfg.t_init for t in targets) else []
         self.events_done = 0
         self._mirror = None
-        self.history: List[dict] = []
+        self._pool = {}
+        self._history: List[dict] = []
+        self._pending = []   # (iteration, loss on the GPU, taps) not yet copied to the host
 
     # ------------------------------------------------------------------ data
     def powers(self, it: int) -> torch.Tensor:
@@ -193,6 +195,16 @@ class Trainer:
         if cfg.symbols != "gauss":
             s = TX.qam16_symbols(words, dtype=self.cdt)
         return r, s, p
+
+    def train_batch(self, it: int):
+        """The batch of training iteration `it`: batch(it), or with a data pool the pool's batch
+        it mod data_pool, simulated once and kept on the GPU."""
+        if self.cfg.data_pool <= 0:
+            return self.batch(it)
+        k = it % self.cfg.data_pool
+        if k not in self._pool:
+            self._pool[k] = self.batch(k)
+        return self._pool[k]
 
     # ------------------------------------------------------------------ model
     def mirror(self) -> torch.Tensor:
@@ -254,13 +266,27 @@ class Trainer:
         f = min(1.0, (it - t0) / (cfg.iters - t0))
         return cfg.lr_final + 0.5 * (cfg.lr - cfg.lr_final) * (1.0 + math.cos(math.pi * f))
 
-    def step(self):
-        """One training iteration; returns the batch loss (mean MSE over frames)."""
+    @property
+    def history(self) -> List[dict]:
+        """{"it", "loss", "taps"} per training iteration (losses copied from the GPU in groups)."""
+        self._flush()
+        return self._history
+
+    def _flush(self):
+        if self._pending:
+            vals = torch.stack([v for _, v, _ in self._pending]).cpu().tolist()   # one synchronisation
+            for (it, _, nt), v in zip(self._pending, vals):
+                self._history.append({"it": it, "loss": float(v), "taps": nt})
+            self._pending = []
+
+    def step(self, sync: bool = True):
+        """One training iteration; returns the batch loss (mean MSE over frames): a float (sync=True), or
+        without synchronising the GPU, the loss as a device scalar (sync=False)."""
         cfg = self.cfg
         while self.events_done < len(self.plan) and self.plan[self.events_done][0] <= self.it:
             self._prune(self.plan[self.events_done][1])
             self.events_done += 1
-        r, s, p = self.batch(self.it % cfg.data_pool if cfg.data_pool > 0 else self.it)
+        r, s, p = self.train_batch(self.it)
         z, ck = self.forward(r, ckpt=True)
         S = max(1, min(cfg.ckpt_every, len(self.ntap)))
         mse, _, gz = TX.rx_mse(z, s, p, cfg.rho_d, cfg.rs, cfg.rolloff, npol=cfg.npol, want_grad=True)
@@ -282,17 +308,22 @@ class Trainer:
             TX.adam_(self.c, gc, self.m_c, self.v_c, self.t, lr=lr, mask=self.c_mask)
         if self.essm:
             TX.adam_(self.eta, ge, self.m_e, self.v_e, self.t, lr=lr)
-        loss = float(mse.mean().item())
-        self.history.append({"it": self.it, "loss": loss, "taps": int(sum(self.ntap))})
+        loss = mse.mean()
+        self._pending.append((self.it, loss, int(sum(self.ntap))))
+        if len(self._pending) >= 256:
+            self._flush()
         self.it += 1
+        if sync:
+            self._flush()
+            return self._history[-1]["loss"]
         return loss
 
     def train(self, iters: Optional[int] = None, log=None):
         n = self.cfg.iters - self.it if iters is None else iters
         for _ in range(n):
-            loss = self.step()
+            self.step(sync=log is not None)
             if log is not None:
-                log.write(json.dumps(self.history[-1]) + "\n")
+                log.write(json.dumps(self._history[-1]) + "\n")
         return self.history
 
     # ------------------------------------------------------------------ evaluation
