@@ -324,7 +324,9 @@ int ldbp_batch_forward_graph(ldbp_batch_plan* plan, const void* taps, const void
  *   Kerr step     N(z): x <- x exp(j kerr_scale gamma L_eff(z) |x|^2), L_eff(z) = (1 - e^{-alpha z}) / alpha
  *                 (|x|^2 summed over both polarisations for npol = 2; kerr_scale = 8/9 for Manakov)
  * A link has nspan spans of span_len metres, each cut into nstep steps.  The FFT
- * is hand written (power-of-two n, 2 <= n <= 2^24; with two polarisations n <= 2^22).
+ * is hand written for lengths n = 2^a 3^b 5^c, 2 <= n <= 2^24: powers of two in registers
+ * (with two polarisations n <= 2^22), other lengths above 4096 with mixed-radix passes in LDS
+ * (n = N1 N2 with N1 <= 4096 / npol; EUNSUPPORTED when no such split exists).
  * -------------------------------------------------------------------------*/
 typedef struct ssm_link {
   double fs;          /* sampling rate [Hz] */
@@ -361,6 +363,31 @@ int ssm_channel(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const ssm
  * equaliser.  r, y as x, y of ssm_channel. */
 int fft_dbp(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const ssm_link* link, const void* r,
             void* y, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Uneven batches of the split-step method (Sec. III-A; waveforms of different lengths and span
+ * counts over one link, e.g. the serving batch of FFT-based DBP): waveform b has wave_len[b]
+ * samples (2^a 3^b 5^c, 2 .. 2^24, all with the mixed-radix passes in LDS) and runs the program of
+ * ssm_channel (dbp = 0) or fft_dbp (dbp = 1) for wave_nspan[b] spans of `link` (link->nspan is
+ * ignored).  Launches are per program step over all waveforms that still have that step.
+ *   ssm_batch_plan_create  validates, builds the per-waveform geometry, programs and FP64 twiddle
+ *                          tables in device memory the plan owns (allocated here, once; synchronises
+ *                          the device).  Host arrays are copied.  The current device is the plan's.
+ *   ssm_batch_plan_info    total samples, total sample x linear steps, the largest number of
+ *                          linear steps, and the noise slots a channel plan reads (spans of the
+ *                          longest link when ase_var > 0, else 0)
+ *   ssm_batch_run          x, y device [sum wave_len][npol] complex, waveforms back to back; y may
+ *                          equal x.  noise device [noise_slots][sum wave_len][npol] (slot s = span s
+ *                          of every waveform), required when noise_slots > 0, else ignored.
+ *                          Asynchronous on `stream`; the plan must not be destroyed before it ends.
+ * -------------------------------------------------------------------------*/
+typedef struct ssm_batch_plan ssm_batch_plan;
+int ssm_batch_plan_create(int32_t dtype, int32_t npol, int32_t nwave, const int64_t* wave_len,
+                          const int32_t* wave_nspan, const ssm_link* link, int32_t dbp, ssm_batch_plan** out);
+int ssm_batch_plan_destroy(ssm_batch_plan* plan);
+int ssm_batch_plan_info(const ssm_batch_plan* plan, int64_t* total_samples, int64_t* total_sample_steps,
+                        int32_t* max_steps, int32_t* noise_slots);
+int ssm_batch_run(const ssm_batch_plan* plan, const void* x, void* y, const void* noise, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched FFT (hand written, power-of-two n in [2, 2^24]): y_k = sum_t x_t e^{-+2 pi i k t / n},

@@ -96,6 +96,11 @@ SIGNATURES = {
     "ssm_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, P_size]),
     "ssm_channel": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, c_void_p, c_void_p, c_void_p, c_void_p,
                               c_size_t, c_void_p]),
+    "ssm_batch_plan_create": (c_int32, [c_int32, c_int32, c_int32, P_i64, P_i32, P_link, c_int32,
+                                        ctypes.POINTER(c_void_p)]),
+    "ssm_batch_plan_destroy": (c_int32, [c_void_p]),
+    "ssm_batch_plan_info": (c_int32, [c_void_p, P_i64, P_i64, P_i32, P_i32]),
+    "ssm_batch_run": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "fft_dbp": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_link, c_void_p, c_void_p, c_void_p, c_size_t,
                           c_void_p]),
     "ldbp_fft_workspace_size": (c_int32, [c_int32, c_int32, c_int64, c_int64, P_size]),

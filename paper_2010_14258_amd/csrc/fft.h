@@ -1,13 +1,13 @@
-// In-LDS Stockham FFT building blocks (power-of-two lengths) for gfx950.
+// In-LDS Stockham FFT building blocks for gfx950: lengths whose prime factors are 2, 3 and 5.
 //
 // Data in LDS is laid out as [len][width]: element i of transform w sits at
-// i*width + w, so `width` independent transforms of length `len` are done
+// i*width + w, so `width` (a power of two) independent transforms of length `len` are done
 // together.  A stage of radix RAD with Ns = product of the earlier radices
 // reads v_r = in[j + r len/RAD], multiplies by the twiddles W_{Ns RAD}^{r (j mod Ns)},
 // takes an RAD-point DFT in registers and writes out[(j/Ns) Ns RAD + (j mod Ns) + r Ns]
 // (the self-sorting Stockham formulation; no bit reversal).  Stages ping-pong
-// between two buffers.  Twiddles come from a table W_len^k, k < len, computed
-// in FP64 and rounded once.
+// between two buffers; radices are taken as 16, 8, 4 or 2 while the remaining length is even,
+// then 3 and 5.  Twiddles come from a table W_len^k, k < len, computed in FP64 and rounded once.
 #pragma once
 
 #include "common.h"
@@ -36,58 +36,97 @@ __device__ __forceinline__ cx_t<R> w16(int k) {
   return V{cr, DIR > 0 ? -sr : sr};
 }
 
-// In-register DFT of RAD points (RAD = 2, 4, 8, 16), natural order in and out.
+// cos and sin of 2 pi / 5 and 4 pi / 5, and sin(2 pi / 3)
+__device__ constexpr double kC5_1 = 0.30901699437494742410, kC5_2 = -0.80901699437494742410;
+__device__ constexpr double kS5_1 = 0.95105651629515357212, kS5_2 = 0.58778525229247312917;
+__device__ constexpr double kS3 = 0.86602540378443864676;
+
+// (x + i y) times -i DIR: DIR (y - i x)
+template <typename V, int DIR>
+__device__ __forceinline__ V mul_mi(V a) {
+  return DIR > 0 ? V{a.y, -a.x} : V{-a.y, a.x};
+}
+
+// In-register DFT of RAD points (RAD = 2, 3, 4, 5, 8, 16), natural order in and out.
 // X_k = sum_r v_r W_RAD^{r k} with W = exp(-2 pi i DIR / RAD).
 template <typename R, int RAD, int DIR>
 __device__ __forceinline__ void dft_reg(cx_t<R>* v) {
   using V = cx_t<R>;
-  // decimation in time, iterative radix-2 with compile-time bit reversal of the input
-  constexpr int LOG = RAD == 2 ? 1 : RAD == 4 ? 2 : RAD == 8 ? 3 : 4;
-  V a[RAD];
+  if constexpr (RAD == 3) {
+    // X0 = a + (b + c); X1,2 = a - (b + c)/2 -+ i DIR sin(2 pi/3) (b - c)
+    const V a = v[0], b = v[1], c = v[2];
+    const V t1{b.x + c.x, b.y + c.y};
+    const V t2{a.x - static_cast<R>(0.5) * t1.x, a.y - static_cast<R>(0.5) * t1.y};
+    const R s = static_cast<R>(kS3);
+    const V t3 = mul_mi<V, DIR>(V{s * (b.x - c.x), s * (b.y - c.y)});
+    v[0] = V{a.x + t1.x, a.y + t1.y};
+    v[1] = V{t2.x + t3.x, t2.y + t3.y};
+    v[2] = V{t2.x - t3.x, t2.y - t3.y};
+  } else if constexpr (RAD == 5) {
+    // pairs (b, e) and (c, d) share the real parts of W^k; their differences carry the sines
+    const V a = v[0];
+    const V t1{v[1].x + v[4].x, v[1].y + v[4].y}, t3{v[1].x - v[4].x, v[1].y - v[4].y};
+    const V t2{v[2].x + v[3].x, v[2].y + v[3].y}, t4{v[2].x - v[3].x, v[2].y - v[3].y};
+    const R c1 = static_cast<R>(kC5_1), c2 = static_cast<R>(kC5_2);
+    const R s1 = static_cast<R>(kS5_1), s2 = static_cast<R>(kS5_2);
+    const V m1{a.x + c1 * t1.x + c2 * t2.x, a.y + c1 * t1.y + c2 * t2.y};
+    const V m2{a.x + c2 * t1.x + c1 * t2.x, a.y + c2 * t1.y + c1 * t2.y};
+    const V u1 = mul_mi<V, DIR>(V{s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y});
+    const V u2 = mul_mi<V, DIR>(V{s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y});
+    v[0] = V{a.x + t1.x + t2.x, a.y + t1.y + t2.y};
+    v[1] = V{m1.x + u1.x, m1.y + u1.y};
+    v[4] = V{m1.x - u1.x, m1.y - u1.y};
+    v[2] = V{m2.x + u2.x, m2.y + u2.y};
+    v[3] = V{m2.x - u2.x, m2.y - u2.y};
+  } else {
+    // powers of two: decimation in time, iterative radix-2 with compile-time bit reversal of the input
+    constexpr int LOG = RAD == 2 ? 1 : RAD == 4 ? 2 : RAD == 8 ? 3 : 4;
+    V a[RAD];
 #pragma unroll
-  for (int i = 0; i < RAD; ++i) {
-    int r = 0;
+    for (int i = 0; i < RAD; ++i) {
+      int r = 0;
 #pragma unroll
-    for (int b = 0; b < LOG; ++b) r |= ((i >> b) & 1) << (LOG - 1 - b);
-    a[r] = v[i];
-  }
+      for (int b = 0; b < LOG; ++b) r |= ((i >> b) & 1) << (LOG - 1 - b);
+      a[r] = v[i];
+    }
 #pragma unroll
-  for (int half = 1; half < RAD; half <<= 1) {
+    for (int half = 1; half < RAD; half <<= 1) {
 #pragma unroll
-    for (int g = 0; g < RAD; g += 2 * half) {
+      for (int g = 0; g < RAD; g += 2 * half) {
 #pragma unroll
-      for (int k = 0; k < half; ++k) {
-        const V w = w16<R, DIR>(k * (16 / (2 * half)));
-        V t;
-        const V o = a[g + k + half];
-        if (k == 0) {
-          t = o;
-        } else {
-          t.x = o.x * w.x - o.y * w.y;
-          t.y = o.x * w.y + o.y * w.x;
+        for (int k = 0; k < half; ++k) {
+          const V w = w16<R, DIR>(k * (16 / (2 * half)));
+          V t;
+          const V o = a[g + k + half];
+          if (k == 0) {
+            t = o;
+          } else {
+            t.x = o.x * w.x - o.y * w.y;
+            t.y = o.x * w.y + o.y * w.x;
+          }
+          const V e = a[g + k];
+          a[g + k] = V{e.x + t.x, e.y + t.y};
+          a[g + k + half] = V{e.x - t.x, e.y - t.y};
         }
-        const V e = a[g + k];
-        a[g + k] = V{e.x + t.x, e.y + t.y};
-        a[g + k + half] = V{e.x - t.x, e.y - t.y};
       }
     }
-  }
 #pragma unroll
-  for (int i = 0; i < RAD; ++i) v[i] = a[i];
+    for (int i = 0; i < RAD; ++i) v[i] = a[i];
+  }
 }
 
-// One Stockham stage over `width` interleaved transforms of length len.
+// One Stockham stage over `width` (a power of two, 2^wlog) interleaved transforms of length len.
 template <typename R, int RAD, int DIR, int THREADS>
 __device__ __forceinline__ void fft_stage(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int len,
-                                          int width, int Ns, const cx_t<R>* __restrict__ tw) {
+                                          int width, int wlog, int Ns, const cx_t<R>* __restrict__ tw) {
   using V = cx_t<R>;
   const int nbf = len / RAD;
   const int total = nbf * width;
   const int twstep = len / (Ns * RAD);
   for (int b = threadIdx.x; b < total; b += THREADS) {
-    const int j = b / width;
-    const int w = b - j * width;
-    const int jm = j % Ns;
+    const int j = b >> wlog;
+    const int w = b & (width - 1);
+    const int jm = static_cast<int>(static_cast<uint32_t>(j) % static_cast<uint32_t>(Ns));
     V v[RAD];
 #pragma unroll
     for (int r = 0; r < RAD; ++r) v[r] = in[(j + r * nbf) * width + w];
@@ -107,20 +146,24 @@ __device__ __forceinline__ void fft_stage(const cx_t<R>* __restrict__ in, cx_t<R
   }
 }
 
-// Full transform of `width` interleaved length-len sequences held in A; B is scratch of the same
-// size.  Returns the buffer holding the result.  Ends with a barrier.  len must be a power of two.
+// Full transform of `width` (a power of two) interleaved length-len sequences held in A; B is scratch
+// of the same size.  Returns the buffer holding the result.  Ends with a barrier.  len must be
+// 2^a 3^b 5^c (the host checks it).
 template <typename R, int DIR, int THREADS>
 __device__ cx_t<R>* lds_fft(cx_t<R>* A, cx_t<R>* B, int len, int width, const cx_t<R>* __restrict__ tw) {
   using V = cx_t<R>;
   V* in = A;
   V* out = B;
+  const int wlog = __builtin_ctz(static_cast<unsigned>(width));
   int Ns = 1;
   while (Ns < len) {
     const int rem = len / Ns;
-    if (rem >= 16) fft_stage<R, 16, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 16;
-    else if (rem == 8) fft_stage<R, 8, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 8;
-    else if (rem == 4) fft_stage<R, 4, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 4;
-    else fft_stage<R, 2, DIR, THREADS>(in, out, len, width, Ns, tw), Ns *= 2;
+    if (rem % 16 == 0) fft_stage<R, 16, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 16;
+    else if (rem % 8 == 0) fft_stage<R, 8, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 8;
+    else if (rem % 4 == 0) fft_stage<R, 4, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 4;
+    else if (rem % 2 == 0) fft_stage<R, 2, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 2;
+    else if (rem % 3 == 0) fft_stage<R, 3, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 3;
+    else fft_stage<R, 5, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 5;
     __syncthreads();
     V* t = in;
     in = out;

@@ -28,61 +28,11 @@
 #include "bufio.h"
 #include "team_fft.h"
 #include "ssm_kernels.h"
+#include "ssm_ops.h"
 
 namespace ldbp {
 
 constexpr int kSsmThreads = 256;
-
-// Pointwise operation of the program, as the kernels consume it.
-struct PwOp {
-  double ka, g, sigma, kb;
-  int32_t slot;  // noise slot or -1
-  int32_t pad;
-};
-
-// Per-sample Kerr phase for a time sample of NPOL complex values held at v[0..NPOL).
-template <typename R>
-__device__ __forceinline__ void kerr_rotate(cx_t<R>* v, int npol, double k) {
-  if (k == 0.0) return;
-  R p = 0;
-  for (int q = 0; q < npol; ++q) p += v[q].x * v[q].x + v[q].y * v[q].y;
-  R s, c;
-  phase_sincos(static_cast<R>(k) * phase_coef_scale<R>(), p, s, c);
-  for (int q = 0; q < npol; ++q) {
-    const cx_t<R> o = v[q];
-    v[q] = cx_t<R>{o.x * c - o.y * s, o.x * s + o.y * c};
-  }
-}
-
-template <typename R>
-__device__ __forceinline__ void apply_pw(cx_t<R>* v, int npol, const PwOp& op, const cx_t<R>* noise_at) {
-  kerr_rotate<R>(v, npol, op.ka);
-  if (op.g != 1.0) {
-    const R g = static_cast<R>(op.g);
-    for (int q = 0; q < npol; ++q) v[q] = cx_t<R>{v[q].x * g, v[q].y * g};
-  }
-  if (noise_at) {
-    const R s = static_cast<R>(op.sigma);
-    for (int q = 0; q < npol; ++q) v[q] = cx_t<R>{v[q].x + s * noise_at[q].x, v[q].y + s * noise_at[q].y};
-  }
-  kerr_rotate<R>(v, npol, op.kb);
-}
-
-// exp(z (j beta2 w^2/2 - alpha/2)) / n for FFT bin k of an n-point grid at rate fs.
-template <typename R>
-__device__ __forceinline__ cx_t<R> lin_response(int64_t k, int64_t n, double zrev, R amp) {
-  // zrev = z beta2 pi fs^2 / n^2: the phase in revolutions is zrev * m^2, m the signed bin index
-  const double m = static_cast<double>(k < (n + 1) / 2 ? k : k - n);
-  double rev = zrev * m * m;
-  rev -= rint(rev);
-  R s, c;
-  if constexpr (sizeof(R) == 4) {
-    Rot32::sincos_rev(static_cast<float>(rev), s, c);
-  } else {
-    sincos(6.283185307179586476925 * rev, &s, &c);
-  }
-  return cx_t<R>{amp * c, amp * s};
-}
 
 // amp * exp(2 pi i rev) for |rev| <= 1/2
 template <typename R>
@@ -433,6 +383,15 @@ SsmGeom make_geom(int dtype, int64_t nwave, int64_t n, int npol, double fs, doub
     g.resident = 1;
     g.N1 = static_cast<int32_t>(n);
     g.N2 = 1;
+  } else if ((n & (n - 1)) != 0) {
+    // not a power of two: mixed-radix passes, their own split (ssm_var.hip)
+    g.resident = 0;
+    g.mixed = 1;
+    VarWave w;
+    if (var_geometry(dtype, npol, n, w, nullptr) == LDBP_OK) {
+      g.N1 = w.N1;
+      g.N2 = w.N2;
+    }
   } else {
     // N2 = 256 columns of length 256 up to n = 2^16; beyond, rows grow to 4096 / npol elements
     // (the row pass holds one row of every polarisation in a 256-lane workgroup) and columns take the rest
@@ -448,6 +407,7 @@ SsmGeom make_geom(int dtype, int64_t nwave, int64_t n, int npol, double fs, doub
 
 size_t ssm_table_elems(const SsmGeom& g) {
   if (g.resident) return static_cast<size_t>(g.n);
+  if (g.mixed) return 0;
   return static_cast<size_t>(team_tw_entries(ilog2(g.N1))) + team_tw_entries(ilog2(g.N2)) +
          (int64_t(1) << g.lo_log) + (g.n >> g.lo_log);
 }
@@ -622,11 +582,13 @@ int ssm_run(int dtype, const SsmGeom& g, const void* x, void* y, const std::vect
     if (dtype == LDBP_C64) return run_resident<float>(g, x, y, lin_z, ops, noise, ws, s);
     return run_resident<double>(g, x, y, lin_z, ops, noise, ws, s);
   }
+  if (g.mixed) return ssm_run_var(dtype, g, x, y, lin_z, pw, noise, ws, s);
   if (dtype == LDBP_C64) return run_four_step<float>(g, x, y, lin_z, ops, noise, ws, s);
   return run_four_step<double>(g, x, y, lin_z, ops, noise, ws, s);
 }
 
 size_t ssm_workspace_bytes(int dtype, const SsmGeom& g, int32_t M) {
+  if (g.mixed) return ssm_var_workspace_bytes(dtype, g.npol, g.n);
   if (!g.resident) return ssm_table_elems(g) * elem_size(dtype);
   const size_t zbytes = (static_cast<size_t>(M) * sizeof(double) + 255) & ~size_t(255);
   const size_t obytes = ((static_cast<size_t>(M) + 1) * sizeof(PwOp) + 255) & ~size_t(255);
@@ -635,6 +597,7 @@ size_t ssm_workspace_bytes(int dtype, const SsmGeom& g, int32_t M) {
 
 size_t ssm_lds_bytes(int dtype, const SsmGeom& g) {
   if (g.resident) return 2 * static_cast<size_t>(g.n) * g.npol * elem_size(dtype);
+  if (g.mixed) return ssm_var_lds_bytes(dtype, g.npol, g.n);
   if (dtype == LDBP_C64) {
     FourStep<float> f;
     if (!four_step<float>(g, f)) return ~size_t(0);

@@ -82,3 +82,54 @@ def fft_dbp(r: torch.Tensor, link: Link, npol: int = 1, y: Optional[torch.Tensor
     N.check(lib.fft_dbp(_code(r), npol, nwave, n, ctypes.byref(st), _ptr(r), _ptr(y), _ptr(ws), ws.numel(),
                         stream_handle(stream, r.device)))
     return y
+
+
+class SsmBatchPlan:
+    """Owns a C ``ssm_batch_plan``: the split-step channel (dbp=False) or FFT-DBP (dbp=True) over
+    `link` for waveforms of lengths `wave_len` (2^a 3^b 5^c) with `wave_nspan` spans each, packed back
+    to back as one complex tensor [sum wave_len] (npol = 1) or [sum wave_len, 2] (npol = 2)."""
+
+    def __init__(self, wave_len: Sequence[int], wave_nspan: Sequence[int], link: Link, dbp: bool,
+                 dtype=torch.complex64, npol: int = 1):
+        lib = N.load()
+        self.dtype, self.npol = dtype, npol
+        self.wave_len = [int(v) for v in wave_len]
+        self.wave_nspan = [int(v) for v in wave_nspan]
+        lens = (ctypes.c_int64 * len(self.wave_len))(*self.wave_len)
+        st, keep = link.to_c()
+        h = ctypes.c_void_p(0)
+        code = N.LDBP_C64 if dtype == torch.complex64 else N.LDBP_C128
+        N.check(lib.ssm_batch_plan_create(code, npol, len(self.wave_len), lens, N.i32_array(self.wave_nspan),
+                                          ctypes.byref(st), int(bool(dbp)), ctypes.byref(h)))
+        self._h = h
+        a, b = ctypes.c_int64(0), ctypes.c_int64(0)
+        c, d = ctypes.c_int32(0), ctypes.c_int32(0)
+        N.check(lib.ssm_batch_plan_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)))
+        self.total_samples, self.total_sample_steps = a.value, b.value
+        self.max_steps, self.noise_slots = c.value, d.value
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            N.load().ssm_batch_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, noise: Optional[torch.Tensor] = None,
+            stream=None) -> torch.Tensor:
+        lib = N.load()
+        _check_dev("x", x, self.dtype)
+        if x.numel() != self.total_samples * self.npol:
+            raise ValueError("x does not hold the plan's samples")
+        y = torch.empty_like(x) if y is None else y
+        _check_dev("y", y, self.dtype)
+        if noise is not None:
+            _check_dev("noise", noise, self.dtype)
+            if noise.numel() < self.noise_slots * x.numel():
+                raise ValueError("noise must hold noise_slots x the plan's samples")
+        N.check(lib.ssm_batch_run(self._h, _ptr(x), _ptr(y), _ptr(noise), stream_handle(stream, x.device)))
+        return y

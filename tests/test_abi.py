@@ -229,3 +229,34 @@ def test_noalloc_forward_rejects_batches_beyond_its_scratch_before_any_gpu_work(
                                     None) == N.LDBP_EINVAL
     assert lib.ldbp_forward_noalloc(0, 3, 4, 64, 1, N.i32_array([5]), 16, 16, 4096, 8192, None, 0, None,
                                     None) == N.LDBP_EUNSUPPORTED
+
+
+def test_ssm_batch_plan_validation_before_any_gpu_work():
+    lib = N.load()
+    link = N.SsmLink(21.4e9, 4.6e-5, -2.17e-26, 1.3e-3, 1e5, 1.0, 0.0, 1, 2, None, 1, 0)
+    out = ctypes.c_void_p(0)
+
+    def create(lens, spans, dbp=1, dtype=0, npol=1):
+        return lib.ssm_batch_plan_create(dtype, npol, len(lens), (ctypes.c_int64 * len(lens))(*lens),
+                                         N.i32_array(spans), ctypes.byref(link), dbp, ctypes.byref(out))
+
+    assert create([4096, 4097], [1, 1]) == N.LDBP_EUNSUPPORTED      # 4097 = 17 x 241
+    assert create([4096, 7 * 1024], [1, 1]) == N.LDBP_EUNSUPPORTED  # factor 7
+    assert create([4096], [0]) == N.LDBP_EINVAL                     # no span
+    assert create([4096], [1], dbp=2) == N.LDBP_EINVAL
+    assert create([4096], [1], npol=3) == N.LDBP_EUNSUPPORTED
+    assert create([1 << 25], [1]) == N.LDBP_EUNSUPPORTED            # beyond 2^24
+    assert out.value is None
+    # lengths 2^a 3^b 5^c pass validation; without a GPU the plan's allocation then fails
+    assert create([4500, 6000], [2, 3]) == N.LDBP_EHIP
+
+
+def test_ssm_accepts_5_smooth_lengths_and_rejects_others():
+    lib = N.load()
+    link = N.SsmLink(21.4e9, 4.6e-5, -2.17e-26, 1.3e-3, 1e5, 1.0, 0.0, 2, 2, None, 1, 0)
+    b = ctypes.c_size_t(0)
+    for n in (3000, 4050, 6000, 162000, 259200):
+        assert lib.ssm_workspace_size(0, 1, 2, n, ctypes.byref(link), ctypes.byref(b)) == N.LDBP_OK, n
+        assert b.value > 0
+    for n in (4097, 7000, 3 * 11 * 256):
+        assert lib.ssm_workspace_size(0, 1, 2, n, ctypes.byref(link), ctypes.byref(b)) == N.LDBP_EUNSUPPORTED, n
