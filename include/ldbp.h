@@ -390,7 +390,7 @@ int ssm_batch_plan_info(const ssm_batch_plan* plan, int64_t* total_samples, int6
 int ssm_batch_run(const ssm_batch_plan* plan, const void* x, void* y, const void* noise, void* stream);
 
 /* ---------------------------------------------------------------------------
- * Batched FFT (hand written, power-of-two n in [2, 2^24]): y_k = sum_t x_t e^{-+2 pi i k t / n},
+ * Batched FFT (hand written, n = 2^a 3^b 5^c in [2, 2^24]): y_k = sum_t x_t e^{-+2 pi i k t / n},
  * unnormalised, natural order; inverse != 0 selects the + sign.  x, y device [nwave][n][npol];
  * y may equal x.  The DFT of eq. discretized_nlse (Sec. III-A).
  * -------------------------------------------------------------------------*/
@@ -399,7 +399,7 @@ int ldbp_fft(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, const void* 
              void* ws, size_t ws_bytes, void* stream);
 
 /* Transmitter (Sec. IV-A): x(t) = sqrt(P) sum_k s_k p(t - k/R_s) with a root-raised-cosine p of
- * roll-off `rolloff`, periodic frames, sampled at rho samples/symbol (rho and nsym powers of two):
+ * roll-off `rolloff`, periodic frames, sampled at rho samples/symbol (rho and nsym of the form 2^a 3^b 5^c):
  * symbol k sits at sample k*rho, the RRC is applied in the frequency domain and the waveform scaled
  * by sqrt(P) rho (mean power P for unit-energy symbols).  Symbols are 16-QAM,
  * s = (2 (i mod 4) - 3 + j (2 (i div 4) - 3)) / sqrt(10) from indices i in 0..15.

@@ -9,14 +9,12 @@ namespace ldbp {
 
 constexpr size_t kTxMaxLds = 160 * 1024;
 
-static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
-
 static int check_fft(int32_t dtype, int32_t npol, int64_t nwave, int64_t n) {
   if (dtype != LDBP_C64 && dtype != LDBP_C128) return fail(LDBP_EINVAL, "dtype %d invalid", dtype);
   if (npol != 1 && npol != 2) return fail(LDBP_EUNSUPPORTED, "npol %d not supported", npol);
   if (nwave < 1) return fail(LDBP_EINVAL, "nwave < 1");
-  if (!is_pow2(n) || n < 2 || n > (int64_t(1) << 24))
-    return fail(LDBP_EUNSUPPORTED, "length %lld: powers of two in [2, 2^24] are supported", (long long)n);
+  if (!smooth5(n) || n < 2 || n > (int64_t(1) << 24))
+    return fail(LDBP_EUNSUPPORTED, "length %lld: lengths 2^a 3^b 5^c in [2, 2^24] are supported", (long long)n);
   if (fft_lds_bytes(dtype, nwave, n, npol) > kTxMaxLds)
     return fail(LDBP_EUNSUPPORTED, "length %lld needs more LDS per workgroup than available", (long long)n);
   return LDBP_OK;
@@ -56,7 +54,7 @@ extern "C" int ldbp_fft(int32_t dtype, int32_t npol, int64_t nwave, int64_t n, c
 extern "C" int tx_shape_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho,
                                        size_t* bytes) {
   if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
-  if (rho < 1 || !is_pow2(rho)) return fail(LDBP_EUNSUPPORTED, "rho must be a power of two");
+  if (rho < 1 || !smooth5(rho)) return fail(LDBP_EUNSUPPORTED, "rho must be 2^a 3^b 5^c");
   int st = check_fft(dtype, npol, nwave, nsym);
   if (!st) st = check_fft(dtype, npol, nwave, nsym * rho);
   if (st) return st;
@@ -116,7 +114,7 @@ extern "C" int rx_lpf_decimate(int32_t dtype, int32_t npol, int64_t nwave, int64
 extern "C" int rx_mse_workspace_size(int32_t dtype, int32_t npol, int64_t nwave, int64_t nsym, int32_t rho,
                                      size_t* bytes) {
   if (!bytes) return fail(LDBP_EINVAL, "bytes is NULL");
-  if (rho < 1 || !is_pow2(rho)) return fail(LDBP_EUNSUPPORTED, "rho must be a power of two");
+  if (rho < 1 || !smooth5(rho)) return fail(LDBP_EUNSUPPORTED, "rho must be 2^a 3^b 5^c");
   int st = check_fft(dtype, npol, nwave, nsym);
   if (!st) st = check_fft(dtype, npol, nwave, nsym * rho);
   if (st) return st;

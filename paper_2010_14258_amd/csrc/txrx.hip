@@ -1,6 +1,8 @@
 // Transmitter and receiver DSP on the GPU (Sec. IV-A, IV-B), built on a batched natural-order FFT.
 //
-//   ldbp_fft        X_k = sum_t x_t e^{-+2 pi i k t / n}, unnormalised, natural order in and out.
+//   ldbp_fft        X_k = sum_t x_t e^{-+2 pi i k t / n}, unnormalised, natural order in and out, for
+//                   n = 2^a 3^b 5^c: in LDS in one pass up to 4096 samples, else column and row passes
+//                   of the four-step split (tiles of a power of two of columns or rows).
 //   tx_shape        16-QAM symbols -> periodic RRC-shaped waveform at rho samples/symbol:
 //                   X(m) = S(m mod N_sym) H_rrc(m) sqrt(P) rho, x = IDFT(X) / n, where S is the
 //                   N_sym-point DFT of the symbols (the DFT of the zero-inserted sequence is S
@@ -63,7 +65,8 @@ __global__ __launch_bounds__(kT) void fft_resident(const cx_t<R>* x, cx_t<R>* y,
   }
 }
 
-// Column FFT over t2 of columns [c0, c0 + C) with twiddle W_n^{t1 f2}; in -> out (same positions).
+// Column FFT over t2 of columns [c0, c0 + C) (C a power of two; columns past N1 of the last tile are
+// skipped) with twiddle W_n^{t1 f2}; in -> out (same positions).
 template <typename R>
 __global__ __launch_bounds__(kT) void fft_col(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, SsmGeom g,
                                               int C, int conj, const cx_t<R>* __restrict__ tw2,
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(kT) void fft_col(const cx_t<R>* __restrict__ in, cx
   const int np = g.npol, N1 = g.N1, N2 = g.N2, width = C * np;
   V* A = reinterpret_cast<V*>(smem);
   V* B = A + static_cast<size_t>(N2) * width;
-  const int nblk = N1 / C;
+  const int nblk = (N1 + C - 1) / C;
   const int cb = static_cast<int>(blockIdx.x % static_cast<uint32_t>(nblk));
   const int64_t wave = blockIdx.x / static_cast<uint32_t>(nblk);
   const int c0 = cb * C;
@@ -82,21 +85,26 @@ __global__ __launch_bounds__(kT) void fft_col(const cx_t<R>* __restrict__ in, cx
   const int tot = N2 * width;
   for (int e = threadIdx.x; e < tot; e += kT) {
     const int t2 = e / width, w = e - (e / width) * width;
-    V v = iw[(static_cast<int64_t>(t2) * N1 + c0) * np + w];
-    if (conj) v.y = -v.y;
+    V v{0, 0};
+    if (c0 + w / np < N1) {
+      v = iw[(static_cast<int64_t>(t2) * N1 + c0) * np + w];
+      if (conj) v.y = -v.y;
+    }
     A[e] = v;
   }
   __syncthreads();
   V* F = lds_fft<R, 1, kT>(A, B, N2, width, tw2);
   for (int e = threadIdx.x; e < tot; e += kT) {
     const int f2 = e / width, w = e - (e / width) * width;
+    if (c0 + w / np >= N1) continue;
     const int64_t ex = static_cast<int64_t>(c0 + w / np) * f2;
     const V t = cmulx(tlo[ex & ((int64_t(1) << g.lo_log) - 1)], thi[ex >> g.lo_log]);
     ow[(static_cast<int64_t>(f2) * N1 + c0) * np + w] = cmulx(F[e], t);
   }
 }
 
-// Row FFT over t1 of rows [f20, f20 + RW); result X[f2 + N2 f1] written in natural order.
+// Row FFT over t1 of rows [f20, f20 + RW) (RW a power of two; rows past N2 of the last tile are
+// skipped); result X[f2 + N2 f1] written in natural order.
 template <typename R>
 __global__ __launch_bounds__(kT) void fft_row(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, SsmGeom g,
                                               int RW, int conj, const cx_t<R>* __restrict__ tw1) {
@@ -105,7 +113,7 @@ __global__ __launch_bounds__(kT) void fft_row(const cx_t<R>* __restrict__ in, cx
   const int np = g.npol, N1 = g.N1, N2 = g.N2, width = RW * np;
   V* A = reinterpret_cast<V*>(smem);
   V* B = A + static_cast<size_t>(N1) * width;
-  const int nblk = N2 / RW;
+  const int nblk = (N2 + RW - 1) / RW;
   const int rb = static_cast<int>(blockIdx.x % static_cast<uint32_t>(nblk));
   const int64_t wave = blockIdx.x / static_cast<uint32_t>(nblk);
   const int f20 = rb * RW;
@@ -116,7 +124,7 @@ __global__ __launch_bounds__(kT) void fft_row(const cx_t<R>* __restrict__ in, cx
     const int r = e / (N1 * np);
     const int rem = e - r * N1 * np;
     const int t1 = rem / np, q = rem - (rem / np) * np;
-    A[t1 * width + r * np + q] = iw[static_cast<int64_t>(f20 + r) * N1 * np + rem];
+    A[t1 * width + r * np + q] = f20 + r < N2 ? iw[static_cast<int64_t>(f20 + r) * N1 * np + rem] : V{0, 0};
   }
   __syncthreads();
   V* F = lds_fft<R, 1, kT>(A, B, N1, width, tw1);
@@ -124,6 +132,7 @@ __global__ __launch_bounds__(kT) void fft_row(const cx_t<R>* __restrict__ in, cx
   for (int e = threadIdx.x; e < tot; e += kT) {
     const int f1 = e / width, w = e - (e / width) * width;
     const int r = w / np, q = w - (w / np) * np;
+    if (f20 + r >= N2) continue;
     V v = F[e];
     if (conj) v.y = -v.y;
     ow[(static_cast<int64_t>(f20 + r) + static_cast<int64_t>(N2) * f1) * np + q] = v;
@@ -146,12 +155,25 @@ static int fft_tile(int dtype, const SsmGeom& g) {
   return e;
 }
 
+// largest power of two <= max(1, v), capped at the power of two >= cap
+static int tile_pow2(int64_t v, int64_t cap) {
+  int p = 1;
+  while (2 * static_cast<int64_t>(p) <= v && p < cap) p *= 2;
+  return p;
+}
+
+// columns per column tile and rows per row tile of the four-step transform (powers of two)
+static void fft_tiles(int dtype, const SsmGeom& g, int& C, int& RW) {
+  const int E = fft_tile(dtype, g);
+  C = tile_pow2(E / (static_cast<int64_t>(g.N2) * g.npol), g.N1);
+  RW = tile_pow2(E / (static_cast<int64_t>(g.N1) * g.npol), g.N2);
+}
+
 size_t fft_lds_bytes(int dtype, int64_t nwave, int64_t n, int npol) {
   const SsmGeom g = make_geom(dtype, nwave, n, npol, 1.0, 0.0, 0.0);
   if (g.resident) return 2 * static_cast<size_t>(n) * npol * cx_size(dtype);
-  const int E = fft_tile(dtype, g);
-  const int C = std::max(1, std::min<int>(g.N1, E / (g.N2 * npol)));
-  const int RW = std::max(1, std::min<int>(g.N2, E / (g.N1 * npol)));
+  int C, RW;
+  fft_tiles(dtype, g, C, RW);
   return 2 * std::max(static_cast<size_t>(g.N2) * C, static_cast<size_t>(g.N1) * RW) * npol * cx_size(dtype);
 }
 
@@ -187,14 +209,14 @@ static int fft_run_t(int64_t nwave, int64_t n, int npol, const void* x, void* y,
   const size_t tabb = ((static_cast<size_t>(g.N1) + g.N2 + (int64_t(1) << g.lo_log) + (n >> g.lo_log) + 1) *
                        sizeof(V) + 255) & ~size_t(255);
   V* tmp = reinterpret_cast<V*>(static_cast<char*>(ws) + tabb);
+  const int64_t lo = int64_t(1) << g.lo_log;
   int st = gen(tw1, g.N1, 1, g.N1);
   if (!st) st = gen(tw2, g.N2, 1, g.N2);
-  if (!st) st = gen(tlo, int64_t(1) << g.lo_log, 1, n);
-  if (!st) st = gen(thi, n >> g.lo_log, int64_t(1) << g.lo_log, n);
+  if (!st) st = gen(tlo, lo, 1, n);
+  if (!st) st = gen(thi, (n + lo - 1) / lo, lo, n);
   if (st) return st;
-  const int E = fft_tile(dtype, g);
-  const int C = std::max(1, std::min<int>(g.N1, E / (g.N2 * npol)));
-  const int RW = std::max(1, std::min<int>(g.N2, E / (g.N1 * npol)));
+  int C, RW;
+  fft_tiles(dtype, g, C, RW);
   const size_t lc = 2 * static_cast<size_t>(g.N2) * C * npol * sizeof(V);
   const size_t lr = 2 * static_cast<size_t>(g.N1) * RW * npol * sizeof(V);
   if (lc > 65536)
@@ -203,10 +225,10 @@ static int fft_run_t(int64_t nwave, int64_t n, int npol, const void* x, void* y,
   if (lr > 65536)
     LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(fft_row<R>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lr)));
-  hipLaunchKernelGGL(fft_col<R>, dim3(static_cast<uint32_t>((g.N1 / C) * nwave)), dim3(kT), lc, s,
+  hipLaunchKernelGGL(fft_col<R>, dim3(static_cast<uint32_t>(((g.N1 + C - 1) / C) * nwave)), dim3(kT), lc, s,
                      static_cast<const V*>(x), tmp, g, C, inverse, tw2, tlo, thi);
   LDBP_HIP_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(fft_row<R>, dim3(static_cast<uint32_t>((g.N2 / RW) * nwave)), dim3(kT), lr, s, tmp,
+  hipLaunchKernelGGL(fft_row<R>, dim3(static_cast<uint32_t>(((g.N2 + RW - 1) / RW) * nwave)), dim3(kT), lr, s, tmp,
                      static_cast<V*>(y), g, RW, inverse, tw1);
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
