@@ -209,9 +209,135 @@ def uneven_batch(torch, dev, reps: int):
         if best is None or ms < best[1]:
             best = (plan, ms, bp.total_sample_steps, bp.total_samples, bp.nitems)
     plan, ms, ss, ns_tot, nitems = best
+    # plain FFT-DBP at 10 steps per span on the same inputs: one uneven split-step plan over the batch
+    from paper_2010_14258_amd import ssm as SS
+    dbp = SS.SsmBatchPlan(lengths, nspan, uneven_dbp_link(10), True)
+    yd = torch.empty_like(x)
+    stream = torch.cuda.current_stream(dev)
+    ms_dbp = event_time(torch, stream, lambda: dbp.run(x, y=yd, stream=stream), max(2, reps // 5), 1)
     return {"value": ss / (ms * 1e-3), "unit": "samples*steps/s", "ms_per_batch": ms, "plan": list(plan),
             "total_samples": ns_tot, "total_sample_steps": ss, "work_items": nitems,
-            "workload": "256 uneven waveforms (4,096-262,144 samples), 2-50 steps, 3-9 taps, one hipGraph launch"}
+            "equalised_samples_per_s": ns_tot / (ms * 1e-3),
+            "fft_dbp_10stps": {"ms_per_batch": ms_dbp, "equalised_samples_per_s": ns_tot / (ms_dbp * 1e-3),
+                               "sample_steps": dbp.total_sample_steps,
+                               "samples_steps_per_s": dbp.total_sample_steps / (ms_dbp * 1e-3),
+                               "ldbp_speedup": ms_dbp / ms},
+            "workload": "256 uneven waveforms (4,096-262,144 samples), 2-50 steps, 3-9 taps, one hipGraph launch; "
+                        "FFT-DBP at 10 steps/span on the same inputs (mixed-radix passes, one launch pair per step)"}
+
+
+def uneven_dbp_link(steps_per_span: int, fs: float = RHO_D * RS):
+    """FFT-DBP link of the uneven batch: 100 km SSMF spans, log step sizes (spans per waveform come
+    from the plan)."""
+    from paper_2010_14258_amd import init as I
+    from paper_2010_14258_amd import ssm as SS
+    alpha = I.db_per_km_to_alpha(0.2)
+    return SS.Link(fs=fs, alpha=alpha, beta2=I.ps2_per_km_to_beta2(-21.683), gamma=1.3e-3, span_len=1e5, nspan=1,
+                   nstep=steps_per_span, step_len=I.log_step_sizes(1e5, steps_per_span, alpha), edfa_gain=True)
+
+
+def uneven_serving(torch, dev, reps: int, train_iters: int, p_dbm: float = 2.0):
+    """The uneven serving batch at equal SNR.  256 waveforms (lengths log-uniform in [4,096, 262,144],
+    even 5-smooth; 1-25 spans of 100 km; 3/5/7/9 taps per waveform) of 16-QAM at 10.7 GBd and p_dbm,
+    simulated on the GPU: transmitter at 4 samples/symbol, the uneven split-step channel plan (50
+    uniform steps per span, amplifier noise), low-pass and decimation to 2 samples/symbol.  LDBP: for
+    each tap count one 2-step span model shared by every span, least-squares initialised at unit peak
+    gain and trained on a 25-span link (`train_iters` Adam iterations, 8 fixed batches); served as one
+    graph-captured launch over the batch.  FFT-DBP: the uneven plan at 1, 2, 3, 5, 10 steps per span.
+    Effective SNR pooled over all symbols of the batch."""
+    import synth
+    from paper_2010_14258_amd import batch as BT
+    from paper_2010_14258_amd import init as I
+    from paper_2010_14258_amd import ssm as SS
+    from paper_2010_14258_amd import train as TRN
+    from paper_2010_14258_amd import txrx as TX
+
+    lengths = [even_5smooth(v) for v in synth.log_uniform_lengths(401, 256, 4096, 262144)]
+    g = synth.rng(401, 9)
+    nspan = g.integers(1, 26, size=256).tolist()
+    taps_b = g.choice([3, 5, 7, 9], size=256).tolist()
+    alpha = I.db_per_km_to_alpha(0.2)
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.perf_counter()
+    models, train_info = {}, {}
+    for T in (3, 5, 7, 9):
+        cfg = TRN.TrainConfig(nwave=32, nsym=8192, nspan=25, span_km=100.0, channel_steps=50, ldbp_steps=2,
+                              t_init=T, t_final=T, iters=train_iters, powers_dbm=(p_dbm,), tie_spans=True,
+                              peak_normalise=True, data_pool=8, seed=410 + T)
+        trn = TRN.Trainer(cfg, device=dev)
+        snr0 = trn.evaluate(nbatch=1, p_dbm=p_dbm)
+        trn.train(train_iters)
+        snr1 = trn.evaluate(nbatch=1, p_dbm=p_dbm)
+        models[T] = (trn.taps.clone(), trn.c.clone())
+        train_info[T] = {"init_snr_db_25_spans": snr0, "trained_snr_db_25_spans": snr1}
+        del trn
+    train_s = time.perf_counter() - t0
+    # the received batch
+    fs_a = RHO_A * RS
+    xa = []
+    p_w = torch.full((1,), I.dbm_to_w(p_dbm), dtype=torch.float64, device=dev)
+    syms = []
+    for b, n in enumerate(lengths):
+        words = TX.randbits(n // 2, 402, b, device=dev).view(1, n // 2)
+        xa.append(TX.tx_shape(words, p_w, RHO_A, RS).view(-1))
+        syms.append(TX.qam16_symbols(words))
+    xa = torch.cat(xa)
+    ch_link = SS.Link(fs=fs_a, alpha=alpha, beta2=I.ps2_per_km_to_beta2(-21.683), gamma=1.3e-3, span_len=1e5,
+                      nspan=1, nstep=50, edfa_gain=True, ase_var=I.ase_variance(alpha, 1e5, 5.0, fs_a))
+    ch = SS.SsmBatchPlan([2 * n for n in lengths], nspan, ch_link, False)
+    noise = TX.randn((ch.noise_slots, xa.numel()), 403, 0, device=dev)
+    ch.run(xa, y=xa, noise=noise)
+    del noise, ch
+    r, off = [], 0
+    for n in lengths:
+        r.append(TX.rx_lpf_decimate(xa[off:off + 2 * n].view(1, 2 * n), n).view(-1))
+        off += 2 * n
+    r = torch.cat(r)
+    del xa
+    torch.cuda.empty_cache()
+
+    def snr(z):
+        err, cnt, o = 0.0, 0, 0
+        for n, s in zip(lengths, syms):
+            mse, _, _ = TX.rx_mse(z[o:o + n].view(1, n), s, p_w, RHO_D, RS)
+            err += float(mse.sum().item()) * (n // 2)
+            cnt += n // 2
+            o += n
+        return 10.0 * math.log10(cnt / err)
+
+    # LDBP serving plan with the trained span models
+    taps, cs, nsteps, ntap = [], [], [], []
+    for ns, T in zip(nspan, taps_b):
+        tt, cc = models[T]
+        taps.append(tt.repeat(ns))
+        cs.append(cc.repeat(ns))
+        nsteps.append(2 * ns)
+        ntap.extend([T] * (2 * ns))
+    tt, ct = torch.cat(taps), torch.cat(cs)
+    bp = BT.BatchPlan(lengths, nsteps, ntap, plan=(0, 0, 7, 1))
+    y = torch.empty_like(r)
+    ms_ldbp = event_time(torch, stream, lambda: bp.forward(tt, ct, r, y=y, graph=True, stream=stream), reps, 2)
+    snr_ldbp = snr(bp.forward(tt, ct, r, graph=False))
+    sweep, times = {}, {}
+    for k in (1, 2, 3, 5, 10):
+        dp = SS.SsmBatchPlan(lengths, nspan, uneven_dbp_link(k), True)
+        yd = dp.run(r)
+        sweep[k] = snr(yd)
+        times[k] = event_time(torch, stream, lambda: dp.run(r, y=yd, stream=stream), max(2, reps // 5), 1)
+        del dp
+    k, equal = pick_dbp_setting(sweep, snr_ldbp)
+    ns_tot = sum(lengths)
+    return {"mode": "uneven_snr", "launch_dbm": p_dbm, "total_samples": ns_tot,
+            "ldbp": {"snr_db": snr_ldbp, "ms_per_batch": ms_ldbp, "equalised_samples_per_s": ns_tot / (ms_ldbp * 1e-3),
+                     "sample_steps": bp.total_sample_steps, "plan": [0, 0, 7, 1]},
+            "fft_dbp": {str(kk): {"snr_db": sweep[kk], "ms_per_batch": times[kk],
+                                  "equalised_samples_per_s": ns_tot / (times[kk] * 1e-3)} for kk in sweep},
+            "fft_dbp_steps_per_span_at_equal_snr": k, "fft_dbp_reaches_ldbp_snr": equal,
+            ("ldbp_speedup_at_equal_snr" if equal else "ldbp_speedup_vs_best_fft_dbp_unequal_snr"): times[k] / ms_ldbp,
+            "ldbp_speedup_vs_fft_dbp_10stps": times[10] / ms_ldbp,
+            "span_models": train_info, "train_s": train_s, "train_iters": train_iters,
+            "workload": "256 uneven waveforms (4,096-262,144 samples, 1-25 x 100 km, 3/5/7/9 taps, 2 steps/span), "
+                        "GPU-simulated 16-QAM"}
 
 
 def big_batch(torch, dev, W, reps: int):
@@ -786,7 +912,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
     ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "variants", "dbp", "snr", "essm", "e1",
-                                       "init", "e8", "roof", "manakov_train"],
+                                       "init", "e8", "roof", "manakov_train", "uneven_snr"],
                     default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "bwd: the training step (checkpointed forward + backward) and a copy probe; "
@@ -800,7 +926,8 @@ def main():
                          "e8: the 32 GBd scenario (symmetric-SSM LDBP, 2 and 4 steps per span); "
                          "roof: the 1,024-waveform forward at 1-10 steps per pass (where the memory roof sits); "
                          "manakov_train: train the dual-polarisation 8 x 2^20 x 2 configuration (--train-iters, "
-                         "--powers)")
+                         "--powers); uneven_snr: the uneven serving batch on simulated inputs, trained span models, "
+                         "LDBP against FFT-DBP at 1-10 steps per span (--train-iters per tap count)")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
@@ -871,6 +998,9 @@ def main():
                          os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, not args.fixed_c,
                          args.lr_schedule, args.prune_frac)
         print(json.dumps(out), flush=True)
+        return
+    if args.mode == "uneven_snr":
+        print(json.dumps(uneven_serving(torch, dev, args.steps, args.train_iters)), flush=True)
         return
     if args.mode == "manakov_train":
         print(json.dumps(manakov_trained(torch, dev, args.train_iters,

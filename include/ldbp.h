@@ -461,6 +461,13 @@ int ldbp_adam(int32_t dtype, void* theta, const void* grad, void* m, void* v, co
               const int32_t* mirror, int64_t count, int32_t comps, double lr, double b1, double b2, double eps,
               int64_t t, void* stream);
 
+/* Sum of the rows of a [rows][cols] array of the dtype's real type (complex values as interleaved
+ * pairs: cols = 2 x complex count): out[c] = sum_r in[r cols + c], accumulated in FP64 in row order
+ * (deterministic).  The gradient of a parameter shared by several steps (one filter in every
+ * nonlinear step, Sec. III-D; one span's filters tied across spans) is the sum of the gradients of
+ * its copies.  in device [rows][cols], out device [cols], not overlapping; rows >= 1. */
+int ldbp_sum_rows(int32_t dtype, const void* in, void* out, int64_t rows, int64_t cols, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -120,6 +120,7 @@ SIGNATURES = {
     "qam16_symbols": (c_int32, [c_int32, c_int64, c_void_p, c_void_p, c_void_p]),
     "ldbp_randbits": (c_int32, [c_void_p, c_int64, c_uint64, c_uint64, c_void_p]),
     "ldbp_randn": (c_int32, [c_int32, c_void_p, c_int64, c_uint64, c_uint64, c_void_p]),
+    "ldbp_sum_rows": (c_int32, [c_int32, c_void_p, c_void_p, c_int64, c_int64, c_void_p]),
     "ldbp_adam": (c_int32, [c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64, c_int32,
                             c_double, c_double, c_double, c_double, c_int64, c_void_p]),
 }

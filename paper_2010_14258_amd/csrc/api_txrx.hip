@@ -169,3 +169,16 @@ extern "C" int ldbp_adam(int32_t dtype, void* theta, const void* grad, void* m, 
   return adam_run(dtype, theta, grad, m, v, mask, mirror, count, comps, lr, b1, b2, eps, t,
                   static_cast<hipStream_t>(stream));
 }
+
+extern "C" int ldbp_sum_rows(int32_t dtype, const void* in, void* out, int64_t rows, int64_t cols, void* stream) {
+  if (dtype != LDBP_C64 && dtype != LDBP_C128) return fail(LDBP_EINVAL, "dtype invalid");
+  if (rows < 1 || cols < 0) return fail(LDBP_EINVAL, "rows must be >= 1 and cols >= 0");
+  if (!in || !out) return fail(LDBP_EINVAL, "in and out must be non-NULL");
+  const size_t rb = real_size(dtype);
+  if (reinterpret_cast<uintptr_t>(in) % rb || reinterpret_cast<uintptr_t>(out) % rb)
+    return fail(LDBP_EINVAL, "in and out must be aligned to their real type");
+  if (overlaps(in, static_cast<size_t>(rows) * cols * rb, out, static_cast<size_t>(cols) * rb))
+    return fail(LDBP_EINVAL, "out overlaps in");
+  if (cols == 0) return LDBP_OK;
+  return sum_rows_run(dtype, in, out, rows, cols, static_cast<hipStream_t>(stream));
+}

@@ -49,4 +49,27 @@ int adam_run(int dtype, void* theta, const void* grad, void* m, void* v, const v
   return LDBP_OK;
 }
 
+// out[c] = sum over r of in[r cols + c], accumulated in FP64 in row order (deterministic): the gradient
+// of a parameter shared by several steps is the sum of the gradients of its copies.
+template <typename R>
+__global__ void sum_rows_kernel(const R* __restrict__ in, R* __restrict__ out, int64_t rows, int64_t cols) {
+  const int64_t c = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (c >= cols) return;
+  double acc = 0.0;
+  for (int64_t r = 0; r < rows; ++r) acc += static_cast<double>(in[r * cols + c]);
+  out[c] = static_cast<R>(acc);
+}
+
+int sum_rows_run(int dtype, const void* in, void* out, int64_t rows, int64_t cols, hipStream_t s) {
+  const dim3 grid(static_cast<uint32_t>((cols + 255) / 256));
+  if (dtype == LDBP_C64)
+    hipLaunchKernelGGL(sum_rows_kernel<float>, grid, dim3(256), 0, s, static_cast<const float*>(in),
+                       static_cast<float*>(out), rows, cols);
+  else
+    hipLaunchKernelGGL(sum_rows_kernel<double>, grid, dim3(256), 0, s, static_cast<const double*>(in),
+                       static_cast<double*>(out), rows, cols);
+  LDBP_HIP_CHECK(hipGetLastError());
+  return LDBP_OK;
+}
+
 }  // namespace ldbp

@@ -31,5 +31,6 @@ int randn_run(int dtype, void* out, int64_t count, uint64_t seed, uint64_t strea
 
 int adam_run(int dtype, void* theta, const void* grad, void* m, void* v, const void* mask, const int32_t* mirror,
              int64_t count, int32_t comps, double lr, double b1, double b2, double eps, int64_t t, hipStream_t s);
+int sum_rows_run(int dtype, const void* in, void* out, int64_t rows, int64_t cols, hipStream_t s);
 
 }  // namespace ldbp

@@ -84,6 +84,7 @@ class TrainConfig:
     t_final_alt: int = 0              # > 0: odd-numbered layers prune to this length instead of t_final
     peak_normalise: bool = False      # scale every initial filter to unit peak gain (non-expansive cascade)
     data_pool: int = 0                # > 0: training batches cycle through this many fixed batches
+    tie_spans: bool = False           # one span's filters and coefficients shared by every span
 
 
 def pruning_plan(t_init: Sequence[int], t_final: Sequence[int], iters: int, frac: float):
@@ -130,6 +131,15 @@ class Trainer:
                                         random_seed=cfg.seed if cfg.random_init else None, method=cfg.init_method)
         if cfg.random_init and cfg.symmetric:
             raise ValueError("random filters are not symmetric: use symmetric=False with random_init")
+        self.reps = 1
+        if cfg.tie_spans:
+            # every span of the backpropagation is the same operation (same step lengths and positions
+            # in the span), so one span's ldbp_steps layers serve all spans; their gradient is the sum
+            # over the copies
+            if cfg.ssm != "asymmetric" or cfg.essm_kappa >= 0 or cfg.t_final != cfg.t_init:
+                raise ValueError("tie_spans needs the asymmetric LDBP model without pruning")
+            self.reps = cfg.nspan
+            taps, c = taps[:cfg.ldbp_steps], c[:cfg.ldbp_steps]
         if cfg.peak_normalise:
             # least-squares filters whose gain exceeds one outside the signal band expand the out-of-band
             # noise at every step; over many short steps the cascade blows up unless each is non-expansive
@@ -236,19 +246,29 @@ class Trainer:
         """The filters of the nonlinear steps back to back (the shared one repeated in every step)."""
         return self.eta.repeat(len(self.ntap)) if self.cfg.essm_shared else self.eta
 
+    def model_taps(self) -> torch.Tensor:
+        """Packed taps of every layer of the model (the span's taps repeated when spans are tied)."""
+        return self.taps.repeat(self.reps) if self.reps > 1 else self.taps
+
+    def model_c(self) -> torch.Tensor:
+        return self.c.repeat(self.reps) if self.reps > 1 else self.c
+
+    def model_ntap(self) -> List[int]:
+        return list(self.ntap) * self.reps
+
     def _fwd(self, r, **kw):
         if self.essm:
             return E.essm_forward(r, self.taps, self.c, self.eta_per_step(), self.ntap, self.nl_ntap,
                                   npol=self.cfg.npol, **kw)
-        return L.ldbp_forward(r, self.taps, self.c, self.ntap, npol=self.cfg.npol, **kw)
+        return L.ldbp_forward(r, self.model_taps(), self.model_c(), self.model_ntap(), npol=self.cfg.npol, **kw)
 
     def forward(self, r: torch.Tensor, ckpt: bool = False):
         cfg = self.cfg
         sym = 1 if cfg.symmetric else 0
         if not ckpt:
             return self._fwd(r, plan=(0, 0, 0, sym)), None
-        S = max(1, min(cfg.ckpt_every, len(self.ntap)))
-        nslot = L.num_checkpoints(len(self.ntap), S)
+        S = max(1, min(cfg.ckpt_every, len(self.ntap) * self.reps))
+        nslot = L.num_checkpoints(len(self.ntap) * self.reps, S)
         ck = torch.empty((nslot,) + tuple(r.shape), dtype=r.dtype, device=r.device) if nslot else None
         z = self._fwd(r, ckpt=ck, ckpt_every=S if ck is not None else 0,
                       plan=(S, 0, 0, sym) if ck is None else (0, 0, 0, sym))
@@ -288,17 +308,19 @@ class Trainer:
             self.events_done += 1
         r, s, p = self.train_batch(self.it)
         z, ck = self.forward(r, ckpt=True)
-        S = max(1, min(cfg.ckpt_every, len(self.ntap)))
+        S = max(1, min(cfg.ckpt_every, len(self.ntap) * self.reps))
         mse, _, gz = TX.rx_mse(z, s, p, cfg.rho_d, cfg.rs, cfg.rolloff, npol=cfg.npol, want_grad=True)
         if self.essm:
             _, gt, gc, ge = E.essm_backward(r, self.taps, self.c, self.eta_per_step(), self.ntap, self.nl_ntap, gz,
                                             npol=cfg.npol, ckpt=ck, ckpt_every=S, need_gx=False,
                                             symmetric=cfg.symmetric)
             if cfg.essm_shared:
-                ge = ge.view(len(self.ntap), -1).sum(0)
+                ge = TX.sum_rows(ge, len(self.ntap))
         else:
-            _, gt, gc = L.ldbp_backward(r, self.taps, self.c, self.ntap, gz, npol=cfg.npol, ckpt=ck, ckpt_every=S,
-                                        need_gx=False, symmetric=cfg.symmetric)
+            _, gt, gc = L.ldbp_backward(r, self.model_taps(), self.model_c(), self.model_ntap(), gz, npol=cfg.npol,
+                                        ckpt=ck, ckpt_every=S, need_gx=False, symmetric=cfg.symmetric)
+            if self.reps > 1:
+                gt, gc = TX.sum_rows(gt, self.reps), TX.sum_rows(gc, self.reps)
         self.t += 1
         lr = self.learning_rate(self.it)
         if cfg.train_taps:
@@ -309,7 +331,7 @@ class Trainer:
         if self.essm:
             TX.adam_(self.eta, ge, self.m_e, self.v_e, self.t, lr=lr)
         loss = mse.mean()
-        self._pending.append((self.it, loss, int(sum(self.ntap))))
+        self._pending.append((self.it, loss, int(sum(self.ntap)) * self.reps))
         if len(self._pending) >= 256:
             self._flush()
         self.it += 1

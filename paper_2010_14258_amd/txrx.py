@@ -118,6 +118,22 @@ def randn(shape, seed: int, stream_id: int, dtype=torch.complex64, device="cuda"
     return out
 
 
+def sum_rows(x: torch.Tensor, rows: int, stream=None) -> torch.Tensor:
+    """Sum over `rows` equal consecutive blocks of x (real or complex, contiguous), in the library's
+    fixed order: returns x.view(rows, -1) summed over the first axis."""
+    lib = N.load()
+    rx = torch.view_as_real(x) if x.is_complex() else x
+    _check_dev("x", rx)
+    if rx.numel() % rows:
+        raise ValueError("x does not split into rows")
+    cols = rx.numel() // rows
+    out = torch.empty(x.numel() // rows, dtype=x.dtype, device=x.device)
+    ro = torch.view_as_real(out) if out.is_complex() else out
+    code = N.LDBP_C64 if rx.dtype == torch.float32 else N.LDBP_C128
+    N.check(lib.ldbp_sum_rows(code, _ptr(rx), _ptr(ro), rows, cols, stream_handle(stream, x.device)))
+    return out
+
+
 def adam_(theta: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, t: int, lr: float = 1e-3,
           b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8, mask: Optional[torch.Tensor] = None,
           mirror: Optional[torch.Tensor] = None, stream=None):

@@ -172,8 +172,10 @@ def test_tx_shape_symbols_validation():
     args = (0, 1, 2, 64, 2, 10.7e9, 0.1)
     assert lib.tx_shape_symbols(*args, None, ctypes.c_void_p(16), ctypes.c_void_p(4096), None, 0,
                                 None) == N.LDBP_EINVAL                       # no symbols
+    assert lib.tx_shape_symbols(0, 1, 2, 64, 7, 10.7e9, 0.1, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                ctypes.c_void_p(4096), None, 0, None) == N.LDBP_EUNSUPPORTED   # rho 7
     assert lib.tx_shape_symbols(0, 1, 2, 64, 3, 10.7e9, 0.1, ctypes.c_void_p(16), ctypes.c_void_p(16),
-                                ctypes.c_void_p(4096), None, 0, None) == N.LDBP_EUNSUPPORTED   # rho 3
+                                ctypes.c_void_p(4096), None, 0, None) == N.LDBP_EWORKSPACE     # rho 3 is valid
     assert lib.tx_shape_symbols(*args, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(4096), None, 0,
                                 None) == N.LDBP_EWORKSPACE
 

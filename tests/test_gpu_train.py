@@ -254,3 +254,39 @@ def test_symmetric_ssm_model_keeps_its_last_step_linear():
     c = tr.c.cpu().numpy()
     assert c[-1] == 0.0 and np.all(c[:-1] != 0.0)
     assert all(np.isfinite(h["loss"]) for h in tr.history)
+
+
+def test_library_row_sum_matches_numpy():
+    from paper_2010_14258_amd import txrx as TX
+    for dt in (torch.float32, torch.float64, torch.complex64, torch.complex128):
+        x = torch.randn(7, 33, dtype=dt, device="cuda:0")
+        got = TX.sum_rows(x.reshape(-1), 7).cpu().numpy()
+        ref = x.cpu().numpy().astype(np.complex128 if x.is_complex() else np.float64).sum(axis=0)
+        assert _rel(got, ref) <= (1e-6 if dt in (torch.float32, torch.complex64) else 1e-14)
+
+
+def test_tied_span_gradient_is_the_sum_over_spans():
+    """One span's filters and coefficients shared by all spans (every span of backpropagation is the same
+    operation): the gradient of a tied parameter is the sum of the oracle gradients of its copies."""
+    print("case: tied spans gradient", flush=True)
+    from paper_2010_14258_amd import ldbp as L, txrx as TX
+    tr = T.Trainer(_small(t_init=7, t_final=7, ldbp_steps=2, complex128=True, tie_spans=True, symmetric=False))
+    assert tr.taps.numel() == 14 and tr.model_taps().numel() == 42 and tr.model_ntap() == [7] * 6
+    r, s, p = tr.batch(5)
+    z, ck = tr.forward(r, ckpt=True)
+    mse, _, gz = TX.rx_mse(z, s, p, 2, tr.cfg.rs, want_grad=True)
+    S = min(tr.cfg.ckpt_every, 6)
+    _, gt, gc = L.ldbp_backward(r, tr.model_taps(), tr.model_c(), tr.model_ntap(), gz, ckpt=ck, ckpt_every=S,
+                                need_gx=False)
+    gts, gcs = TX.sum_rows(gt, 3), TX.sum_rows(gc, 3)
+    torch.cuda.synchronize()
+    tp = tr.model_taps().cpu().numpy()
+    taps = [tp[7 * i:7 * i + 7] for i in range(6)]
+    y = O.ldbp_forward(r.cpu().numpy(), taps, tr.model_c().cpu().numpy())
+    loss, gy = X.rx_loss_and_grad(y, s.cpu().numpy(), 2, p.cpu().numpy(), tr.cfg.rs)
+    _, gtr, gcr = O.ldbp_grad(r.cpu().numpy(), taps, tr.model_c().cpu().numpy(), gy)
+    assert abs(float(mse.mean()) - loss) <= 1e-9 * loss
+    assert _rel(gts.cpu().numpy(), np.concatenate(gtr).reshape(3, -1).sum(0)) <= 1e-9
+    assert _rel(gcs.cpu().numpy(), np.asarray(gcr).reshape(3, -1).sum(0)) <= 1e-9
+    tr.train(5)
+    assert tr.taps.numel() == 14 and all(np.isfinite(h["loss"]) for h in tr.history)
