@@ -466,7 +466,7 @@ def manakov(torch, dev, reps: int):
                     "steps), so the LS-initialised SNR is not a quality figure"}
 
 
-def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 3),)):
+def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 3),), data_pool: int = 0):
     """The equal-SNR comparison with a trained model: LDBP (l = 50, 5 steps per span) trained by the
     training recipe (32 x 16,384 waveforms per batch simulated on the GPU, launch powers {2, 3, 4} dBm,
     filters pruned from 25 to 3 taps, Adam), then evaluated at each launch power on the 64 x 65,536
@@ -480,7 +480,8 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
 
     models = []
     for t_init, t_final in variants:
-        trn = TRN.Trainer(TRN.TrainConfig(iters=iters, t_init=t_init, t_final=t_final), device=dev)
+        trn = TRN.Trainer(TRN.TrainConfig(iters=iters, t_init=t_init, t_final=t_final, data_pool=data_pool),
+                          device=dev)
         t0 = time.perf_counter()
         curve = []
         for it in range(iters):
@@ -494,6 +495,12 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
                        "loss_curve": curve, "taps": trn.taps.contiguous(), "c": trn.c.contiguous(),
                        "ntap": list(trn.ntap)})
         del trn
+    # the least-squares models (the method without learning) at each model's initial and final length
+    ls = {}
+    for T in sorted({t for v in variants for t in v}):
+        trn = TRN.Trainer(TRN.TrainConfig(iters=1, t_init=T, t_final=T), device=dev)
+        ls[T] = (trn.taps.contiguous(), trn.c.contiguous(), list(trn.ntap))
+        del trn
     stream = torch.cuda.current_stream(dev)
     out_models = [{k: v for k, v in m.items() if k not in ("taps", "c", "ntap")} | {"total_taps": int(sum(m["ntap"]))}
                   for m in models]
@@ -506,6 +513,8 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
         z = L.ldbp_forward(r, taps, c, ntap, plan=(0, 0, 0, 1))
         snr_tr = snr_db(TX, z, W["s"], W["p"])
         snr_ls = snr_db(TX, L.ldbp_forward(r, W["taps"], W["c"], W["ntap"], plan=(0, 0, 0, 1)), W["s"], W["p"])
+        snr_ls_init = {str(T): snr_db(TX, L.ldbp_forward(r, *ls[T], plan=(0, 0, 0, 1)), W["s"], W["p"])
+                       for T in (m["taps_init"], m["taps_final"])}
         sweep = {}
         for k in (1, 2, 3, 5, 10, 20):
             sweep[k] = snr_db(TX, SS.fft_dbp(r, W["dbp_link"](k)), W["s"], W["p"])
@@ -518,6 +527,7 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
         dws = torch.empty(SS.ssm_workspace_size(r, link), dtype=torch.uint8, device=dev)
         ms_d = event_time(torch, stream, lambda: SS.fft_dbp(r, link, y=y, ws=dws, stream=stream), max(3, reps // 3), 1)
         rows.append({"model": mi, "launch_dbm": p_dbm, "ldbp_trained_snr_db": snr_tr, "ldbp_ls_init_snr_db": snr_ls,
+                     "ldbp_ls_snr_db_by_taps": snr_ls_init,
                      "fft_dbp_snr_db_by_steps_per_span": sweep, "fft_dbp_steps_per_span": k,
                      "fft_dbp_reaches_ldbp_snr": equal, "ldbp_ms": ms_l, "fft_dbp_ms": ms_d,
                      "ldbp_plan": list(plan),
@@ -940,6 +950,8 @@ def main():
     ap.add_argument("--schemes", default="least_squares,unit,random",
                     help="--mode init: initialisations (least_squares, unit, random, multiobjective)")
     ap.add_argument("--init-taps", type=int, default=9, help="--mode init: taps per step")
+    ap.add_argument("--data-pool", type=int, default=0,
+                    help="--mode snr: training batches cycle through this many fixed batches (0: fresh batches)")
     ap.add_argument("--train-taps", default="25:3",
                     help="models of --mode snr: initial:final taps per step, comma separated (pruned in training)")
     ap.add_argument("--one-stream", action="store_true",
@@ -990,7 +1002,7 @@ def main():
     if args.mode == "snr":
         variants = [tuple(int(t) for t in v.split(":")) for v in args.train_taps.split(",")]
         out = equal_snr_trained(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")], 20,
-                                variants)
+                                variants, args.data_pool)
         print(json.dumps(out), flush=True)
         return
     if args.mode == "e1":

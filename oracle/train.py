@@ -56,7 +56,7 @@ def pruning_events(t_init: Sequence[int], t_final: Sequence[int]) -> list[int]:
     return events
 
 
-def pruning_iterations(n_events: int, total_iters: int, frac: float = 0.6) -> list[int]:
+def pruning_iterations(n_events: int, total_iters: int, frac: float = 0.2) -> list[int]:
     """Iteration at which each event fires: floor(I_p (e/E)^2), e = 1..E, I_p = frac * total_iters."""
     ip = frac * total_iters
     return [int(np.floor(ip * (e / n_events) ** 2)) for e in range(1, n_events + 1)]

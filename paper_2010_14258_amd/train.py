@@ -58,7 +58,7 @@ class TrainConfig:
     t_init: int = 25
     t_final: int = 3
     iters: int = 5000
-    prune_frac: float = 0.6
+    prune_frac: float = 0.2           # pruning events fall in the first prune_frac of the iterations
     lr: float = 1e-3
     lr_schedule: str = "constant"     # "cosine": after the last pruning event, decay to lr_final by a half cosine
     lr_final: float = 1e-4

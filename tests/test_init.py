@@ -37,11 +37,14 @@ def test_ldbp_parameters_match_oracle_init():
 
 
 def test_pruning_plan_matches_oracle_schedule():
-    plan = T.pruning_plan([25] * 50, [3] * 50, 5000, 0.6)
     ev = OT.pruning_events([25] * 50, [3] * 50)
-    its = OT.pruning_iterations(len(ev), 5000, 0.6)
-    assert [l for _, l in plan] == ev
-    assert [w for w, _ in plan] == its
+    for frac in (0.2, 0.6):
+        plan = T.pruning_plan([25] * 50, [3] * 50, 5000, frac)
+        its = OT.pruning_iterations(len(ev), 5000, frac)
+        assert [l for _, l in plan] == ev
+        assert [w for w, _ in plan] == its
+    # the default schedule: all 550 events within the first 1,000 of 5,000 iterations
+    assert T.TrainConfig().prune_frac == 0.2 and OT.pruning_iterations(len(ev), 5000)[-1] == 1000
 
 
 def test_inband_taps_match_oracle_reading():
