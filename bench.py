@@ -297,13 +297,16 @@ def uneven_serving(torch, dev, reps: int, train_iters: int, p_dbm: float = 2.0):
     torch.cuda.empty_cache()
 
     def snr(z):
-        err, cnt, o = 0.0, 0, 0
-        for n, s in zip(lengths, syms):
+        """Pooled SNR over the batch and per tap count of the LDBP models (waveforms grouped as served)."""
+        err, cnt, o = {}, {}, 0
+        for n, s, T in zip(lengths, syms, taps_b):
             mse, _, _ = TX.rx_mse(z[o:o + n].view(1, n), s, p_w, RHO_D, RS)
-            err += float(mse.sum().item()) * (n // 2)
-            cnt += n // 2
+            e = float(mse.sum().item()) * (n // 2)
+            for key in ("all", str(T)):
+                err[key] = err.get(key, 0.0) + e
+                cnt[key] = cnt.get(key, 0) + n // 2
             o += n
-        return 10.0 * math.log10(cnt / err)
+        return {key: 10.0 * math.log10(cnt[key] / err[key]) for key in err}
 
     # LDBP serving plan with the trained span models
     taps, cs, nsteps, ntap = [], [], [], []
@@ -317,12 +320,14 @@ def uneven_serving(torch, dev, reps: int, train_iters: int, p_dbm: float = 2.0):
     bp = BT.BatchPlan(lengths, nsteps, ntap, plan=(0, 0, 7, 1))
     y = torch.empty_like(r)
     ms_ldbp = event_time(torch, stream, lambda: bp.forward(tt, ct, r, y=y, graph=True, stream=stream), reps, 2)
-    snr_ldbp = snr(bp.forward(tt, ct, r, graph=False))
-    sweep, times = {}, {}
+    snr_ldbp_groups = snr(bp.forward(tt, ct, r, graph=False))
+    snr_ldbp = snr_ldbp_groups["all"]
+    sweep, sweep_groups, times = {}, {}, {}
     for k in (1, 2, 3, 5, 10):
         dp = SS.SsmBatchPlan(lengths, nspan, uneven_dbp_link(k), True)
         yd = dp.run(r)
-        sweep[k] = snr(yd)
+        sweep_groups[k] = snr(yd)
+        sweep[k] = sweep_groups[k]["all"]
         times[k] = event_time(torch, stream, lambda: dp.run(r, y=yd, stream=stream), max(2, reps // 5), 1)
         del dp
     k, equal = pick_dbp_setting(sweep, snr_ldbp)
@@ -330,7 +335,9 @@ def uneven_serving(torch, dev, reps: int, train_iters: int, p_dbm: float = 2.0):
     return {"mode": "uneven_snr", "launch_dbm": p_dbm, "total_samples": ns_tot,
             "ldbp": {"snr_db": snr_ldbp, "ms_per_batch": ms_ldbp, "equalised_samples_per_s": ns_tot / (ms_ldbp * 1e-3),
                      "sample_steps": bp.total_sample_steps, "plan": [0, 0, 7, 1]},
+            "ldbp_snr_db_by_taps": {g: v for g, v in snr_ldbp_groups.items() if g != "all"},
             "fft_dbp": {str(kk): {"snr_db": sweep[kk], "ms_per_batch": times[kk],
+                                  "snr_db_by_taps_group": {g: v for g, v in sweep_groups[kk].items() if g != "all"},
                                   "equalised_samples_per_s": ns_tot / (times[kk] * 1e-3)} for kk in sweep},
             "fft_dbp_steps_per_span_at_equal_snr": k, "fft_dbp_reaches_ldbp_snr": equal,
             ("ldbp_speedup_at_equal_snr" if equal else "ldbp_speedup_vs_best_fft_dbp_unequal_snr"): times[k] / ms_ldbp,

@@ -85,6 +85,7 @@ class TrainConfig:
     peak_normalise: bool = False      # scale every initial filter to unit peak gain (non-expansive cascade)
     data_pool: int = 0                # > 0: training batches cycle through this many fixed batches
     tie_spans: bool = False           # one span's filters and coefficients shared by every span
+    channel_group: int = 4            # training batches simulated by one channel call (same data)
 
 
 def pruning_plan(t_init: Sequence[int], t_final: Sequence[int], iters: int, frac: float):
@@ -178,6 +179,7 @@ class Trainer:
         self.events_done = 0
         self._mirror = None
         self._pool = {}
+        self._group, self._group_at = None, -1   # batches simulated together (channel_group)
         self._history: List[dict] = []
         self._pending = []   # (iteration, loss on the GPU, taps) not yet copied to the host
 
@@ -206,11 +208,46 @@ class Trainer:
             s = TX.qam16_symbols(words, dtype=self.cdt)
         return r, s, p
 
+    def batches(self, its: Sequence[int]):
+        """batch(it) for every it of `its`, their channel simulations run as one call over all their
+        waveforms (the split-step kernels treat every waveform alike, so each batch is bit for bit the
+        one batch(it) returns; one call over several batches keeps more of the GPU busy)."""
+        cfg = self.cfg
+        if len(its) == 1:
+            return [self.batch(its[0])]
+        shape = (cfg.nwave, cfg.nsym) if cfg.npol == 1 else (cfg.nwave, cfg.nsym, 2)
+        xs, noises, syms, ps = [], [], [], []
+        for it in its:
+            p = self.powers(it)
+            if cfg.symbols == "gauss":
+                s = TX.randn(shape, cfg.seed, 2 * it, dtype=self.cdt, device=self.dev)
+                xs.append(TX.tx_shape_symbols(s, p, cfg.rho_a, cfg.rs, cfg.rolloff, npol=cfg.npol))
+            else:
+                words = TX.randbits(int(np.prod(shape)), cfg.seed, 2 * it, device=self.dev).view(shape)
+                xs.append(TX.tx_shape(words, p, cfg.rho_a, cfg.rs, cfg.rolloff, npol=cfg.npol, dtype=self.cdt))
+                s = TX.qam16_symbols(words, dtype=self.cdt)
+            noises.append(TX.randn((cfg.nspan,) + tuple(xs[-1].shape), cfg.seed, 2 * it + 1, dtype=self.cdt,
+                                   device=self.dev))
+            syms.append(s)
+            ps.append(p)
+        x = torch.cat(xs, 0)
+        noise = torch.stack(noises, 1).reshape((cfg.nspan, x.shape[0]) + tuple(x.shape[1:]))
+        del xs, noises
+        y = SS.ssm_channel(x, self.channel, noise=noise, npol=cfg.npol, y=x)
+        del noise
+        r = TX.rx_lpf_decimate(y, self.n_d, npol=cfg.npol)
+        return [(r[k * cfg.nwave:(k + 1) * cfg.nwave], syms[k], ps[k]) for k in range(len(its))]
+
     def train_batch(self, it: int):
-        """The batch of training iteration `it`: batch(it), or with a data pool the pool's batch
-        it mod data_pool, simulated once and kept on the GPU."""
+        """The batch of training iteration `it`: batch(it) (simulated `channel_group` iterations at a
+        time), or with a data pool the pool's batch it mod data_pool, simulated once and kept on the GPU."""
         if self.cfg.data_pool <= 0:
-            return self.batch(it)
+            G = max(1, self.cfg.channel_group)
+            g0 = it - it % G
+            if self._group_at != g0:
+                self._group = self.batches(list(range(g0, g0 + G)))
+                self._group_at = g0
+            return self._group[it - g0]
         k = it % self.cfg.data_pool
         if k not in self._pool:
             self._pool[k] = self.batch(k)

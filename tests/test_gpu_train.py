@@ -315,3 +315,15 @@ def test_training_recipe_gains_at_the_training_shapes():
               flush=True)
         assert snr[p] >= snr3[p] + 10.0
         assert snr[p] >= snr25[p] - 1.0
+
+
+@pytest.mark.parametrize("npol,symbols", [(1, "qam16"), (2, "qam16"), (1, "gauss")])
+def test_grouped_channel_simulation_is_bitwise_the_single_batches(npol, symbols):
+    """Training batches simulated together (one channel call over several iterations' waveforms) are bit
+    for bit the batches simulated one at a time."""
+    print("case: grouped batches", npol, symbols, flush=True)
+    tr = T.Trainer(_small(npol=npol, symbols=symbols))
+    group = tr.batches([3, 4, 5])
+    for it, (r, s, p) in zip((3, 4, 5), group):
+        r1, s1, p1 = tr.batch(it)
+        assert torch.equal(r, r1) and torch.equal(s, s1) and torch.equal(p, p1)

@@ -126,7 +126,10 @@ def test_example2_pruning_event_count():
 def test_pruning_schedule_front_loaded_and_masks():
     ev = TR.pruning_events([25] * 50, [3] * 50)
     assert len(ev) == 550
-    its = TR.pruning_iterations(len(ev), 5000)
+    its = TR.pruning_iterations(len(ev), 5000)             # events in the first 20% (reading R9)
+    assert its == sorted(its) and its[-1] == 1000
+    assert sum(1 for t in its if t < 500) > sum(1 for t in its if t >= 500)
+    its = TR.pruning_iterations(len(ev), 5000, 0.6)
     assert its == sorted(its) and its[-1] == 3000
     assert sum(1 for t in its if t < 1500) > sum(1 for t in its if t >= 1500)
     h = [np.arange(1, 8, dtype=np.complex128)]
