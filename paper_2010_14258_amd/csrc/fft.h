@@ -115,18 +115,22 @@ __device__ __forceinline__ void dft_reg(cx_t<R>* v) {
   }
 }
 
-// One Stockham stage over `width` (a power of two, 2^wlog) interleaved transforms of length len.
+// One Stockham stage over `width` (a power of two, 2^wlog) interleaved transforms of length len; Ns is
+// the product of the earlier radices, rem = len / Ns, inv_ns a float approximation of 1 / Ns used to
+// split j into j div Ns and j mod Ns (exact after one correction step: j and Ns are below 2^13).
 template <typename R, int RAD, int DIR, int THREADS>
 __device__ __forceinline__ void fft_stage(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int len,
-                                          int width, int wlog, int Ns, const cx_t<R>* __restrict__ tw) {
+                                          int width, int wlog, int Ns, int rem, float inv_ns,
+                                          const cx_t<R>* __restrict__ tw) {
   using V = cx_t<R>;
   const int nbf = len / RAD;
   const int total = nbf * width;
-  const int twstep = len / (Ns * RAD);
+  const int twstep = rem / RAD;
   for (int b = threadIdx.x; b < total; b += THREADS) {
     const int j = b >> wlog;
     const int w = b & (width - 1);
-    const int jm = static_cast<int>(static_cast<uint32_t>(j) % static_cast<uint32_t>(Ns));
+    int jm = j - static_cast<int>(static_cast<float>(j) * inv_ns) * Ns;
+    jm = jm < 0 ? jm + Ns : (jm >= Ns ? jm - Ns : jm);
     V v[RAD];
 #pragma unroll
     for (int r = 0; r < RAD; ++r) v[r] = in[(j + r * nbf) * width + w];
@@ -146,30 +150,61 @@ __device__ __forceinline__ void fft_stage(const cx_t<R>* __restrict__ in, cx_t<R
   }
 }
 
-// Full transform of `width` (a power of two) interleaved length-len sequences held in A; B is scratch
-// of the same size.  Returns the buffer holding the result.  Ends with a barrier.  len must be
-// 2^a 3^b 5^c (the host checks it).
-template <typename R, int DIR, int THREADS>
-__device__ cx_t<R>* lds_fft(cx_t<R>* A, cx_t<R>* B, int len, int width, const cx_t<R>* __restrict__ tw) {
+// The stage radices of a length 2^a 3^b 5^c, four bits per stage from the low end (radix 16 coded as
+// 1, 0 ends the plan): 16 (if r16), 8, 4 or 2 while the remaining length is even, then 3s, then 5s.
+__host__ __device__ inline uint64_t fft_radix_plan(int len, bool r16 = true) {
+  uint64_t plan = 0;
+  int sh = 0, rem = len;
+  while (rem > 1 && sh < 64) {
+    const int r = (r16 && rem % 16 == 0) ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : rem % 2 == 0 ? 2
+                  : rem % 3 == 0 ? 3 : 5;
+    plan |= static_cast<uint64_t>(r == 16 ? 1 : r) << sh;
+    sh += 4;
+    rem /= r;
+  }
+  return plan;
+}
+
+// Full transform of `width` (a power of two) interleaved length-len sequences held in A, with the
+// stages of `plan` (fft_radix_plan(len, R16)); B is scratch of the same size.  Returns the buffer
+// holding the result.  Ends with a barrier.  Without R16 the radix-16 stage is not compiled in (fewer
+// registers for kernels whose lengths are mostly odd).
+template <typename R, int DIR, int THREADS, bool R16 = true>
+__device__ cx_t<R>* lds_fft_plan(cx_t<R>* A, cx_t<R>* B, int len, int width, const cx_t<R>* __restrict__ tw,
+                                 uint64_t plan) {
   using V = cx_t<R>;
   V* in = A;
   V* out = B;
   const int wlog = __builtin_ctz(static_cast<unsigned>(width));
-  int Ns = 1;
-  while (Ns < len) {
-    const int rem = len / Ns;
-    if (rem % 16 == 0) fft_stage<R, 16, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 16;
-    else if (rem % 8 == 0) fft_stage<R, 8, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 8;
-    else if (rem % 4 == 0) fft_stage<R, 4, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 4;
-    else if (rem % 2 == 0) fft_stage<R, 2, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 2;
-    else if (rem % 3 == 0) fft_stage<R, 3, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 3;
-    else fft_stage<R, 5, DIR, THREADS>(in, out, len, width, wlog, Ns, tw), Ns *= 5;
+  int Ns = 1, rem = len;
+  for (; plan != 0; plan >>= 4) {
+    const float inv = 1.0f / static_cast<float>(Ns);
+    switch (static_cast<int>(plan & 15)) {
+      case 1:
+        if constexpr (R16) {
+          fft_stage<R, 16, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw);
+          Ns *= 16;
+          rem /= 16;
+        }
+        break;
+      case 8: fft_stage<R, 8, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 8; rem /= 8; break;
+      case 4: fft_stage<R, 4, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 4; rem /= 4; break;
+      case 2: fft_stage<R, 2, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 2; rem /= 2; break;
+      case 3: fft_stage<R, 3, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 3; rem /= 3; break;
+      default: fft_stage<R, 5, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 5; rem /= 5; break;
+    }
     __syncthreads();
     V* t = in;
     in = out;
     out = t;
   }
   return in;
+}
+
+// lds_fft_plan with the plan of len (2^a 3^b 5^c; the host checks it).
+template <typename R, int DIR, int THREADS>
+__device__ cx_t<R>* lds_fft(cx_t<R>* A, cx_t<R>* B, int len, int width, const cx_t<R>* __restrict__ tw) {
+  return lds_fft_plan<R, DIR, THREADS>(A, B, len, width, tw, fft_radix_plan(len));
 }
 
 }  // namespace ldbp

@@ -111,11 +111,20 @@ __global__ __launch_bounds__(kSsmThreads) void ssm_resident_kernel(const cx_t<R>
     const PwOp op = ops[i];
     const V* nz = (op.slot >= 0 && noise) ? noise + (static_cast<int64_t>(op.slot) * g.nwave + wave) * g.n * np
                                            : nullptr;
-    for (int t = threadIdx.x; t < n; t += kSsmThreads) {
-      V v[2];
-      for (int q = 0; q < np; ++q) v[q] = A[t * np + q];
-      apply_pw<R>(v, np, op, nz ? nz + static_cast<int64_t>(t) * np : nullptr);
-      for (int q = 0; q < np; ++q) A[t * np + q] = v[q];
+    // (the polarisation count is a literal in each branch, so the sample stays in registers)
+    if (np == 1) {
+      for (int t = threadIdx.x; t < n; t += kSsmThreads) {
+        V v[1] = {A[t]};
+        apply_pw<R>(v, 1, op, nz ? nz + t : nullptr);
+        A[t] = v[0];
+      }
+    } else {
+      for (int t = threadIdx.x; t < n; t += kSsmThreads) {
+        V v[2] = {A[2 * t], A[2 * t + 1]};
+        apply_pw<R>(v, 2, op, nz ? nz + static_cast<int64_t>(t) * 2 : nullptr);
+        A[2 * t] = v[0];
+        A[2 * t + 1] = v[1];
+      }
     }
     __syncthreads();
     if (i == M) break;

@@ -31,6 +31,7 @@ struct VarWave {
   int64_t n;
   int32_t N1, N2, C, RW, ctiles, rtiles, lo_log, M, prog, prog_op;
   int64_t tw1, tw2, tlo, thi;
+  uint64_t plan1, plan2;  // radix plans of the N1- and N2-point transforms (fft_radix_plan)
 };
 struct VarItem {
   int32_t wave, tile;

@@ -29,7 +29,10 @@
 namespace ldbp {
 
 constexpr int kVarThreads = 256;
-constexpr int kVarTileElems = 4096;   // complex values per LDS buffer of a tile (two buffers per tile)
+// complex values per LDS buffer of a tile (two buffers per tile, plus the twiddle table of the pass's
+// transform length): the smallest of these that admits a split n = N1 N2 with N1, N2 <= E / npol, so
+// that two or three workgroups fit on a compute unit
+constexpr int kVarTileElems[] = {2048, 4096};
 constexpr size_t kVarMaxLds = 160 * 1024;
 
 struct VarArgs {
@@ -87,8 +90,10 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_col(const cx_t<R>* src, c
   const bool do_ifft = step > 0, do_fft = step < w.M;
   V* A = reinterpret_cast<V*>(smem);
   V* B = A + static_cast<size_t>(N2) * width;
+  V* tw = B + static_cast<size_t>(N2) * width;   // W_N2^k, k < N2, staged from the table buffer
   const int tot = N2 * width;
   const int64_t base = w.off + static_cast<int64_t>(c0) * np;
+  for (int k = threadIdx.x; k < N2; k += kVarThreads) tw[k] = tab[w.tw2 + k];
   for (int e = threadIdx.x; e < tot; e += kVarThreads) {
     const int t2 = e >> wlog, q = e & (width - 1);
     V v{0, 0};
@@ -105,23 +110,34 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_col(const cx_t<R>* src, c
   V* cur = A;
   V* oth = B;
   if (do_ifft) {
-    cur = lds_fft<R, -1, kVarThreads>(A, B, N2, width, tab + w.tw2);
+    cur = lds_fft_plan<R, -1, kVarThreads, false>(A, B, N2, width, tw, w.plan2);
     oth = (cur == A) ? B : A;
   }
   // pointwise operation on every time sample (t2, t1) of the tile, all polarisations together
   const int clog = wlog - plog;
   const V* nz = nullptr;
   if (op.slot >= 0 && a.noise) nz = static_cast<const V*>(a.noise) + op.slot * a.noise_slot;
-  for (int e = threadIdx.x; e < N2 * C; e += kVarThreads) {
-    const int t2 = e >> clog, cc = e & (C - 1);
-    if (c0 + cc >= N1) continue;
-    V v[2];
-    for (int q = 0; q < np; ++q) v[q] = cur[e * np + q];
-    apply_pw<R>(v, np, op, nz ? nz + base + (static_cast<int64_t>(t2) * N1 + cc) * np : nullptr);
-    for (int q = 0; q < np; ++q) cur[e * np + q] = v[q];
+  // (the polarisation count is a literal in each branch, so the sample stays in registers)
+  if (np == 1) {
+    for (int e = threadIdx.x; e < N2 * C; e += kVarThreads) {
+      const int t2 = e >> clog, cc = e & (C - 1);
+      if (c0 + cc >= N1) continue;
+      V v[1] = {cur[e]};
+      apply_pw<R>(v, 1, op, nz ? nz + base + static_cast<int64_t>(t2) * N1 + cc : nullptr);
+      cur[e] = v[0];
+    }
+  } else {
+    for (int e = threadIdx.x; e < N2 * C; e += kVarThreads) {
+      const int t2 = e >> clog, cc = e & (C - 1);
+      if (c0 + cc >= N1) continue;
+      V v[2] = {cur[2 * e], cur[2 * e + 1]};
+      apply_pw<R>(v, 2, op, nz ? nz + base + (static_cast<int64_t>(t2) * N1 + cc) * 2 : nullptr);
+      cur[2 * e] = v[0];
+      cur[2 * e + 1] = v[1];
+    }
   }
   __syncthreads();
-  if (do_fft) cur = lds_fft<R, 1, kVarThreads>(cur, oth, N2, width, tab + w.tw2);
+  if (do_fft) cur = lds_fft_plan<R, 1, kVarThreads, false>(cur, oth, N2, width, tw, w.plan2);
   for (int e = threadIdx.x; e < tot; e += kVarThreads) {
     const int f2 = e >> wlog, q = e & (width - 1);
     if (c0 + (q >> plog) >= N1) continue;
@@ -147,6 +163,8 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_row(cx_t<R>* data, VarArg
   const double z = a.ops ? a.z[w.prog + step] : a.zstep;
   V* A = reinterpret_cast<V*>(smem);
   V* B = A + static_cast<size_t>(N1) * width;
+  V* tw = B + static_cast<size_t>(N1) * width;   // W_N1^k, k < N1, staged from the table buffer
+  for (int k = threadIdx.x; k < N1; k += kVarThreads) tw[k] = tab[w.tw1 + k];
   const int rowlen = N1 * np;
   V* row0 = data + w.off + static_cast<int64_t>(r0) * rowlen;
   for (int r = 0; r < RW; ++r) {
@@ -154,7 +172,7 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_row(cx_t<R>* data, VarArg
       A[(e >> plog) * width + r * np + (e & plog)] = r < rows ? row0[static_cast<int64_t>(r) * rowlen + e] : V{0, 0};
   }
   __syncthreads();
-  V* F = lds_fft<R, 1, kVarThreads>(A, B, N1, width, tab + w.tw1);
+  V* F = lds_fft_plan<R, 1, kVarThreads, false>(A, B, N1, width, tw, w.plan1);
   V* oth = (F == A) ? B : A;
   const double n = static_cast<double>(w.n);
   const double zrev = z * a.beta2 * M_PI * a.fs * a.fs / (n * n);
@@ -165,7 +183,7 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_row(cx_t<R>* data, VarArg
     F[e] = cmul(F[e], lin_response<R>(k, w.n, zrev, amp));
   }
   __syncthreads();
-  V* T = lds_fft<R, -1, kVarThreads>(F, oth, N1, width, tab + w.tw1);
+  V* T = lds_fft_plan<R, -1, kVarThreads, false>(F, oth, N1, width, tw, w.plan1);
   for (int r = 0; r < rows; ++r) {
     for (int e = threadIdx.x; e < rowlen; e += kVarThreads)
       row0[static_cast<int64_t>(r) * rowlen + e] = T[(e >> plog) * width + r * np + (e & plog)];
@@ -196,29 +214,37 @@ static int floor_pow2(int64_t v) {
 int var_geometry(int dtype, int npol, int64_t n, VarWave& w, size_t* lds_bytes) {
   if (!smooth5(n) || n < 2)
     return fail(LDBP_EUNSUPPORTED, "n = %lld: FFT lengths must be 2^a 3^b 5^c >= 2", (long long)n);
-  // rows of N1 <= 4096 / npol values per polarisation; N2 the smallest divisor that allows it, so that
+  // rows of N1 <= E / npol values per polarisation; N2 the smallest divisor that allows it, so that
   // column tiles read long runs of every row
-  const int64_t max1 = kVarTileElems / npol;
-  int64_t N2 = 0;
-  for (int64_t d = 1; d <= max1 && d <= n; ++d)
-    if (n % d == 0 && n / d <= max1) {
-      N2 = d;
+  int64_t N2 = 0, E = 0;
+  for (int e : kVarTileElems) {
+    const int64_t max1 = e / npol;
+    for (int64_t d = 1; d <= max1 && d <= n; ++d)
+      if (n % d == 0 && n / d <= max1) {
+        N2 = d;
+        break;
+      }
+    if (N2) {
+      E = e;
       break;
     }
-  if (N2 == 0) return fail(LDBP_EUNSUPPORTED, "n = %lld has no split into rows and columns of <= %lld", (long long)n,
-                           (long long)max1);
+  }
+  if (N2 == 0) return fail(LDBP_EUNSUPPORTED, "n = %lld has no split into rows and columns of <= %d", (long long)n,
+                           kVarTileElems[1] / npol);
   const int64_t N1 = n / N2;
   w = VarWave{};
   w.n = n;
   w.N1 = static_cast<int32_t>(N1);
   w.N2 = static_cast<int32_t>(N2);
-  w.C = std::min<int>(floor_pow2(std::max<int64_t>(1, kVarTileElems / (N2 * npol))), 1 << ceil_log2(N1));
-  w.RW = std::min<int>(floor_pow2(std::max<int64_t>(1, kVarTileElems / (N1 * npol))), 1 << ceil_log2(N2));
+  w.C = std::min<int>(floor_pow2(std::max<int64_t>(1, E / (N2 * npol))), 1 << ceil_log2(N1));
+  w.RW = std::min<int>(floor_pow2(std::max<int64_t>(1, E / (N1 * npol))), 1 << ceil_log2(N2));
   w.ctiles = static_cast<int32_t>((N1 + w.C - 1) / w.C);
   w.rtiles = static_cast<int32_t>((N2 + w.RW - 1) / w.RW);
   w.lo_log = (ceil_log2(n) + 1) / 2;
-  const size_t lds = 2 * std::max<size_t>(static_cast<size_t>(N2) * w.C, static_cast<size_t>(N1) * w.RW) * npol *
-                     cx_size(dtype);
+  w.plan1 = fft_radix_plan(static_cast<int>(N1), false);
+  w.plan2 = fft_radix_plan(static_cast<int>(N2), false);
+  const size_t lds = (2 * std::max<size_t>(static_cast<size_t>(N2) * w.C, static_cast<size_t>(N1) * w.RW) * npol +
+                      static_cast<size_t>(std::max(N1, N2))) * cx_size(dtype);
   if (lds > kVarMaxLds)
     return fail(LDBP_EUNSUPPORTED, "n = %lld with npol = %d needs %zu bytes of LDS per tile (at most %zu)",
                 (long long)n, npol, lds, kVarMaxLds);
