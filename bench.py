@@ -226,6 +226,32 @@ def uneven_batch(torch, dev, reps: int):
                         "FFT-DBP at 10 steps/span on the same inputs (mixed-radix passes, one launch pair per step)"}
 
 
+FFT_LENGTHS = ((65536, 64), (64800, 64), (16384, 256), (15000, 279), (262144, 16), (259200, 16))
+
+
+def fft_lengths(torch, dev, reps: int):
+    """FFT-DBP (10 x 100 km, one step per span) on about 4 M samples per batch at power-of-two lengths
+    (register-resident team passes) and at nearby lengths with factors 3 and 5 (mixed-radix passes in
+    LDS): time per split step and sample x steps per second."""
+    from paper_2010_14258_amd import ssm as SS
+    from paper_2010_14258_amd import txrx as TX
+
+    stream = torch.cuda.current_stream(dev)
+    link = uneven_dbp_link(1)
+    link.nspan = 10
+    rows = []
+    for n, nw in FFT_LENGTHS:
+        x = TX.randn((nw, n), 1, 0, device=dev) * 0.05
+        ws = torch.empty(SS.ssm_workspace_size(x, link), dtype=torch.uint8, device=dev)
+        y = torch.empty_like(x)
+        ms = event_time(torch, stream, lambda: SS.fft_dbp(x, link, y=y, ws=ws, stream=stream), reps, 2)
+        rows.append({"n": n, "nwave": nw, "ms": ms, "us_per_step": ms / 10 * 1e3,
+                     "sample_steps_per_s": nw * n * 10 / (ms * 1e-3),
+                     "algorithmic_tbs": nw * n * 32 * 10 / (ms * 1e-3) / 1e12})
+        del x, y, ws
+    return {"mode": "fft_lengths", "rows": rows}
+
+
 def uneven_dbp_link(steps_per_span: int, fs: float = RHO_D * RS):
     """FFT-DBP link of the uneven batch: 100 km SSMF spans, log step sizes (spans per waveform come
     from the plan)."""
@@ -733,7 +759,8 @@ def essm_trained(torch, dev, iters: int, powers, kappa: int = 20, ntaps: int = 1
 
 
 def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_at=None, train_c: bool = True,
-               lr_schedule: str = "constant", prune_frac: float = 0.6):
+               lr_schedule: str = "constant", prune_frac=None, rho_a: int = 4, data_pool: int = 0,
+               eval_batches: int = 4):
     """The paper's first scenario (Sec. V-A) at reduced training length: 10.7 GBd over 25 x 80 km,
     LDBP on the asymmetric split-step with one step per span (l = 25), symmetric filters pruned from 9
     taps to alternating 5 and 3 taps (overall impulse response 13 * 4 + 12 * 2 + 1 = 77 taps),
@@ -744,13 +771,19 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
     SNR per launch power on held-out batches (4 x 32 x 8,192 symbols) for the trained model, its
     least-squares initialisation, FFT-DBP with 1 and 2 steps per span and linear equalisation.
     resume: a trainer checkpoint of the same configuration to continue from (training resumes bit for
-    bit); stop_at: save a checkpoint at that iteration and return without evaluating."""
+    bit); stop_at: save a checkpoint at that iteration and return without evaluating.
+    rho_a: analog oversampling of the simulation (the paper's is 6); data_pool > 0: training cycles
+    through that many simulated batches; eval_batches: held-out batches of 32 x 8,192 symbols per power
+    (39 give the paper's >= 10^7 symbols per SNR), every method evaluated on the same batches."""
     from paper_2010_14258_amd import train as TRN
+    from paper_2010_14258_amd import ssm as SS
+    from paper_2010_14258_amd import txrx as TX
 
-    cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=4, rho_d=2, nspan=25, span_km=80.0, channel_steps=50,
+    extra = {} if prune_frac is None else {"prune_frac": prune_frac}
+    cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=rho_a, rho_d=2, nspan=25, span_km=80.0, channel_steps=50,
                           ldbp_steps=1, t_init=9, t_final=5, t_final_alt=3, iters=iters,
                           powers_dbm=(-2.0, -1.0, 0.0, 1.0), symbols="gauss", seed=1101, train_c=train_c,
-                          lr_schedule=lr_schedule, prune_frac=prune_frac)
+                          lr_schedule=lr_schedule, data_pool=data_pool, **extra)
     trn = TRN.Trainer(cfg, device=dev)
     if resume:
         trn.load(resume)
@@ -772,21 +805,36 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
     if trn.it < iters:
         return {"checkpoint": ck, "iteration": trn.it, "train_seconds": train_s}
     init_model = TRN.Trainer(cfg, device=dev)
-    init = {p_: init_model.evaluate(nbatch=4, p_dbm=p_) for p_ in powers}
-    del init_model
+    links = {"fft_dbp_1stps_snr_db": trn.dbp_link(1), "fft_dbp_2stps_snr_db": trn.dbp_link(2)}
+    lin = trn.dbp_link(1)
+    lin.gamma = 0.0
+    links["linear_eq_snr_db"] = lin
     rows = []
+    t_eval = time.perf_counter()
     for p_ in powers:
-        row = {"launch_dbm": p_, "ldbp_trained_snr_db": trn.evaluate(nbatch=4, p_dbm=p_),
-               "ldbp_ls_init_snr_db": init[p_],
-               "fft_dbp_1stps_snr_db": trn.evaluate_fft_dbp(1, nbatch=4, p_dbm=p_),
-               "fft_dbp_2stps_snr_db": trn.evaluate_fft_dbp(2, nbatch=4, p_dbm=p_),
-               "linear_eq_snr_db": trn.evaluate_fft_dbp(1, nbatch=4, p_dbm=p_, gamma_zero=True)}
+        err, cnt = {}, 0
+        pw = torch.full((cfg.nwave,), 10.0 ** (p_ / 10.0 - 3.0), dtype=torch.float64, device=dev)
+        for b in range(eval_batches):
+            r, s_, pp = trn.batch(1_000_000 + b, pw)     # the same held-out batch for every method
+            outs = {"ldbp_trained_snr_db": trn.forward(r)[0], "ldbp_ls_init_snr_db": init_model.forward(r)[0]}
+            for k, lk in links.items():
+                outs[k] = SS.fft_dbp(r, lk, npol=cfg.npol)
+            for k, z in outs.items():
+                mse, _, _ = TX.rx_mse(z, s_, pp, cfg.rho_d, cfg.rs, cfg.rolloff, npol=cfg.npol)
+                err[k] = err.get(k, 0.0) + float(mse.sum().item())
+            cnt += cfg.nwave
+        row = {"launch_dbm": p_, "symbols": cnt * cfg.nsym}
+        row.update({k: 10.0 * math.log10(cnt / v) for k, v in err.items()})
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
+    eval_s = time.perf_counter() - t_eval
+    del init_model
     resp = 1 + sum(t - 1 for t in trn.ntap)
     peak = {k: max(r[k] for r in rows) for k in rows[0] if k.endswith("_snr_db")}
     return {"workload": "10.7 GBd, 25 x 80 km SSMF, Gaussian symbols, LDBP l = 25 (1 step per span), 9 -> 5/3 taps",
-            "train_kerr_coefficients": train_c, "lr_schedule": lr_schedule, "prune_frac": prune_frac,
+            "train_kerr_coefficients": train_c, "lr_schedule": lr_schedule, "prune_frac": cfg.prune_frac,
+            "analog_oversampling": rho_a, "data_pool": data_pool, "eval_batches_per_power": eval_batches,
+            "eval_seconds": eval_s,
             "train_iterations": iters, "train_seconds_last_call": train_s, "final_ntap": list(trn.ntap),
             "impulse_response_taps": resp, "loss_curve": curve, "by_power": rows, "peak_snr_db": peak,
             "paper_context": {"ldbp_peak_snr_db": 23.5, "penalty_vs_fd_dbp_1stps_db": 2.0,
@@ -929,7 +977,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
     ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "variants", "dbp", "snr", "essm", "e1",
-                                       "init", "e8", "roof", "manakov_train", "uneven_snr"],
+                                       "init", "e8", "roof", "manakov_train", "uneven_snr", "fft_lengths"],
                     default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "bwd: the training step (checkpointed forward + backward) and a copy probe; "
@@ -944,13 +992,18 @@ def main():
                          "roof: the 1,024-waveform forward at 1-10 steps per pass (where the memory roof sits); "
                          "manakov_train: train the dual-polarisation 8 x 2^20 x 2 configuration (--train-iters, "
                          "--powers); uneven_snr: the uneven serving batch on simulated inputs, trained span models, "
-                         "LDBP against FFT-DBP at 1-10 steps per span (--train-iters per tap count)")
+                         "LDBP against FFT-DBP at 1-10 steps per span (--train-iters per tap count); "
+                         "fft_lengths: FFT-DBP step time at power-of-two and 5-smooth lengths")
     ap.add_argument("--train-iters", type=int, default=5000, help="training iterations of --mode snr")
     ap.add_argument("--powers", default="-4,-2,0,1,2,3,4,5,6", help="launch powers (dBm) of --mode snr")
     ap.add_argument("--resume", default=None, help="--mode e1: trainer checkpoint to continue from")
     ap.add_argument("--fixed-c", action="store_true", help="--mode e1: keep the Kerr coefficients fixed")
-    ap.add_argument("--prune-frac", type=float, default=0.6,
-                    help="--mode e1: fraction of the iterations over which the pruning events fall")
+    ap.add_argument("--prune-frac", type=float, default=None,
+                    help="--mode e1: fraction of the iterations over which the pruning events fall "
+                         "(default: the trainer's)")
+    ap.add_argument("--rho-a", type=int, default=4, help="--mode e1: analog oversampling of the simulation")
+    ap.add_argument("--eval-batches", type=int, default=4,
+                    help="--mode e1: held-out batches of 32 x 8,192 symbols per launch power")
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"],
                     help="--mode e1: Adam step size; cosine: decay to 1e-4 after the last pruning event")
     ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
@@ -1015,8 +1068,11 @@ def main():
     if args.mode == "e1":
         out = e1_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
                          os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, not args.fixed_c,
-                         args.lr_schedule, args.prune_frac)
+                         args.lr_schedule, args.prune_frac, args.rho_a, args.data_pool, args.eval_batches)
         print(json.dumps(out), flush=True)
+        return
+    if args.mode == "fft_lengths":
+        print(json.dumps(fft_lengths(torch, dev, args.steps)), flush=True)
         return
     if args.mode == "uneven_snr":
         print(json.dumps(uneven_serving(torch, dev, args.steps, args.train_iters)), flush=True)
