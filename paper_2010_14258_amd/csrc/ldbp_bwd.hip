@@ -347,15 +347,20 @@ __device__ __forceinline__ void tapgrad_generic(const cx_t<R>* __restrict__ gu, 
   }
 }
 
-template <typename R, int NPOL, int RB, int RB2, int THREADS, bool SYM>
+template <typename R, int NPOL, int RB, int RB2, int THREADS, bool SYM, int KMAX>
 __device__ __forceinline__ void adj_step_dispatch_t(const cx_t<R>* gb, cx_t<R>* ga, int lo, int hi, int K,
                                                     const cx_t<R>* h, int own_lo, int Lw, const cx_t<R>* yprev,
                                                     int yshift, double2* red, int ldr, int col0) {
   switch (K) {
-#define LDBP_BWD_CASE(k)                                                                         \
-  case k:                                                                                        \
-    fir_adj_fixed<R, NPOL, RB, THREADS, k, SYM>(gb, ga, lo, hi, h);                              \
-    tapgrad_fixed<R, NPOL, RB2, THREADS, k, SYM>(gb, own_lo, Lw, yprev, yshift, red, ldr, col0); \
+#define LDBP_BWD_CASE(k)                                                                             \
+  case k:                                                                                            \
+    if constexpr (k <= KMAX) {                                                                       \
+      fir_adj_fixed<R, NPOL, RB, THREADS, k, SYM>(gb, ga, lo, hi, h);                                \
+      tapgrad_fixed<R, NPOL, RB2, THREADS, k, SYM>(gb, own_lo, Lw, yprev, yshift, red, ldr, col0);   \
+    } else {                                                                                         \
+      fir_adj_generic<R, NPOL, RB, THREADS>(gb, ga, lo, hi, K, h);                                   \
+      tapgrad_generic<R, NPOL, RB2, THREADS>(gb, own_lo, Lw, K, yprev, yshift, red, ldr, col0, SYM); \
+    }                                                                                                \
     break;
     LDBP_BWD_CASE(0) LDBP_BWD_CASE(1) LDBP_BWD_CASE(2) LDBP_BWD_CASE(3)
     LDBP_BWD_CASE(4) LDBP_BWD_CASE(5) LDBP_BWD_CASE(6) LDBP_BWD_CASE(7)
@@ -369,16 +374,16 @@ __device__ __forceinline__ void adj_step_dispatch_t(const cx_t<R>* gb, cx_t<R>* 
   }
 }
 
-template <typename R, int NPOL, int RB, int RB2, int THREADS>
+template <typename R, int NPOL, int RB, int RB2, int THREADS, int KMAX>
 __device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga, int lo, int hi, int K,
                                                   const cx_t<R>* h, int own_lo, int Lw, const cx_t<R>* yprev,
                                                   int yshift, double2* red, int ldr, int col0, bool sym) {
   if (sym)
-    adj_step_dispatch_t<R, NPOL, RB, RB2, THREADS, true>(gb, ga, lo, hi, K, h, own_lo, Lw, yprev, yshift, red, ldr,
-                                                         col0);
+    adj_step_dispatch_t<R, NPOL, RB, RB2, THREADS, true, KMAX>(gb, ga, lo, hi, K, h, own_lo, Lw, yprev, yshift, red,
+                                                               ldr, col0);
   else
-    adj_step_dispatch_t<R, NPOL, RB, RB2, THREADS, false>(gb, ga, lo, hi, K, h, own_lo, Lw, yprev, yshift, red, ldr,
-                                                          col0);
+    adj_step_dispatch_t<R, NPOL, RB, RB2, THREADS, false, KMAX>(gb, ga, lo, hi, K, h, own_lo, Lw, yprev, yshift, red,
+                                                                ldr, col0);
 }
 
 // Buffer margin of Y_s (block output of step s within the tile's recompute): the forward starts from
@@ -585,8 +590,9 @@ __device__ __forceinline__ void eta_grad_dispatch(const R* Q, const R* PP, int o
 }
 
 // FILT: the block's nonlinear steps filter the power (generalised ESSM, eta != NULL); a separate
-// instantiation keeps the plain LDBP kernel unchanged.
-template <typename R, int NPOL, int RB, int RB2, int THREADS, bool FILT>
+// instantiation keeps the plain LDBP kernel unchanged.  KMAX: the largest filter half-length of the
+// block with fixed-window code compiled in (the host picks the smallest variant that covers the block).
+template <typename R, int NPOL, int RB, int RB2, int THREADS, bool FILT, int KMAX = 12>
 __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const cx_t<R>* __restrict__ xb, const cx_t<R>* __restrict__ gout, cx_t<R>* __restrict__ gin, int32_t n,
     int32_t tile_len, int32_t ntiles, const cx_t<R>* __restrict__ taps, const R* __restrict__ c, PassTable pt,
@@ -658,7 +664,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
       __syncthreads();
       nl_filter_dispatch<R, NPOL, RB, THREADS>(ynext, PP, kp, wout - kp, kp, eta + pt.etaoff[s - 1], coef);
     } else {
-      fir_kerr_dispatch<R, NPOL, RB, THREADS>(ycur + K * NPOL, ynext, 0, bwd_y_width(Lw, H, hs + K), K,
+      fir_kerr_dispatch<R, NPOL, RB, THREADS, KMAX>(ycur + K * NPOL, ynext, 0, bwd_y_width(Lw, H, hs + K), K,
                                               taps + pt.tapoff[s - 1], coef, sym != 0);
     }
     __syncthreads();
@@ -742,7 +748,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     __syncthreads();
     // FIR adjoint into GA over [H - h_{s-1}, H + Lw + h_{s-1}); tap gradient over the owned range.  Y_{s-1}
     // index = GA index + (H - h_{s-1} + kappa_{s-1})
-    adj_step_dispatch<R, NPOL, RB, RB2, THREADS>(GB, GA, H - hprev, H + Lw + hprev, K, taps + pt.tapoff[s - 1], H,
+    adj_step_dispatch<R, NPOL, RB, RB2, THREADS, KMAX>(GB, GA, H - hprev, H + Lw + hprev, K, taps + pt.tapoff[s - 1], H,
                                                  Lw, yprev, H - hprev + kpp, red, ldr,
                                                  pt.tapoff[s - 1] - pt.tapoff[0], sym != 0);
     __syncthreads();
@@ -886,8 +892,16 @@ static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64
   const int64_t nblocks = ntiles * nwave;
   if (nblocks > 0x7fffffffLL) return fail(LDBP_EUNSUPPORTED, "grid too large");
   const size_t lds = bwd_lds_bytes(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL, tile_len, pt, eta != nullptr);
+  int kmax = 0;
+  for (int s = 0; s < pt.nstep; ++s) kmax = std::max(kmax, pt.K[s]);
   auto kern = eta ? ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS, true>
                   : ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS, false>;
+  // complex64 LDBP blocks of short filters: the variants with fewer fixed-window cases use fewer
+  // registers (more waves per SIMD)
+  if constexpr (sizeof(R) == 4) {
+    if (!eta && kmax <= 2) kern = ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS, false, 2>;
+    else if (!eta && kmax <= 7) kern = ldbp_bwd_kernel<R, NPOL, Cfg::RB, Cfg::RB2, Cfg::THREADS, false, 7>;
+  }
   if (lds > 65536)
     LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));

@@ -158,12 +158,17 @@ __device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in,
   }
 }
 
-template <typename R, int NPOL, int RB, int THREADS, bool SYM, bool LIN = false>
+// KMAX: the largest half-length with a fixed-window variant compiled in (longer filters take the generic
+// loop), so that a kernel instantiated for short filters does not reserve the registers of long ones.
+template <typename R, int NPOL, int RB, int THREADS, bool SYM, bool LIN = false, int KMAX = 12>
 __device__ __forceinline__ void fir_kerr_dispatch_t(const cx_t<R>* in, cx_t<R>* out, int lo, int hi, int K,
                                                     const cx_t<R>* h, R coef, R* pw = nullptr) {
   switch (K) {
-#define LDBP_FWD_CASE(k) \
-  case k: fir_kerr_fixed<R, NPOL, RB, THREADS, k, SYM, LIN>(in, out, lo, hi, h, coef, pw); break;
+#define LDBP_FWD_CASE(k)                                                                     \
+  case k:                                                                                    \
+    if constexpr (k <= KMAX) fir_kerr_fixed<R, NPOL, RB, THREADS, k, SYM, LIN>(in, out, lo, hi, h, coef, pw); \
+    else fir_kerr_generic<R, NPOL, RB, THREADS, LIN>(in, out, lo, hi, K, h, coef, pw);     \
+    break;
     LDBP_FWD_CASE(0) LDBP_FWD_CASE(1) LDBP_FWD_CASE(2) LDBP_FWD_CASE(3)
     LDBP_FWD_CASE(4) LDBP_FWD_CASE(5) LDBP_FWD_CASE(6) LDBP_FWD_CASE(7)
     LDBP_FWD_CASE(8) LDBP_FWD_CASE(9) LDBP_FWD_CASE(10) LDBP_FWD_CASE(11)
@@ -289,11 +294,11 @@ __device__ __forceinline__ void nl_filter_dispatch(cx_t<R>* u, const R* pw, int 
   }
 }
 
-template <typename R, int NPOL, int RB, int THREADS>
+template <typename R, int NPOL, int RB, int THREADS, int KMAX = 12>
 __device__ __forceinline__ void fir_kerr_dispatch(const cx_t<R>* in, cx_t<R>* out, int lo, int hi, int K,
                                                   const cx_t<R>* h, R coef, bool sym = false) {
-  if (sym) fir_kerr_dispatch_t<R, NPOL, RB, THREADS, true>(in, out, lo, hi, K, h, coef);
-  else fir_kerr_dispatch_t<R, NPOL, RB, THREADS, false>(in, out, lo, hi, K, h, coef);
+  if (sym) fir_kerr_dispatch_t<R, NPOL, RB, THREADS, true, false, KMAX>(in, out, lo, hi, K, h, coef);
+  else fir_kerr_dispatch_t<R, NPOL, RB, THREADS, false, false, KMAX>(in, out, lo, hi, K, h, coef);
 }
 
 // Loads samples [t0 - H, t0 + Lw + H) of one waveform (circularly) into LDS.  Each thread issues a
