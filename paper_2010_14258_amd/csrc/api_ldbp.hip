@@ -628,23 +628,24 @@ extern "C" int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwav
 
 namespace ldbp {
 
-constexpr size_t kBwdLdsBudget = 53 * 1024;   // three workgroups per CU
-// Two workgroups per CU, each with half the LDS (longer tiles, less per-tile work).  Filtered steps:
-// the kernel's registers allow two workgroups per CU anyway (measured 1.5x faster than 53 KiB at
-// kappa = 20).  Two polarisations: a sample takes twice the LDS, so at 53 KiB a tile holds half as
-// many samples and the per-tile work (barriers, tap reductions, partial sums) dominates; 80 KiB
-// measured 14% faster on 8 x 2^20 x 2 (a sweep from 32 to 160 KiB; one workgroup per CU is slower).
-constexpr size_t kBwdLdsBudgetWide = 80 * 1024;
+// Three workgroups per CU.  Two polarisations as well: with the short-filter kernel variants (84
+// registers at 5 taps) 53 KiB measured 7% faster than 80 KiB on 8 x 2^20 x 2 (l = 64, 5 taps, 3 steps
+// per checkpoint block: 6.42 against 6.94 ms for forward with checkpoints + backward; 40 KiB 6.55,
+// 64 KiB 7.82).
+constexpr size_t kBwdLdsBudget = 53 * 1024;
+// Filtered steps: two workgroups per CU, each with half the LDS (longer tiles, less per-tile work); the
+// kernel's registers allow two workgroups per CU anyway (measured 1.5x faster than 53 KiB at kappa = 20).
+constexpr size_t kBwdLdsBudgetFilt = 80 * 1024;
 
 // LDS budget of one backward workgroup; LDBP_BWD_LDS_KIB overrides it (a tuning knob: a smaller
 // budget gives more workgroups per CU, a larger one longer tiles and less halo recompute).
-static size_t bwd_lds_budget(bool filtered, int npol) {
+static size_t bwd_lds_budget(bool filtered) {
   const char* e = std::getenv("LDBP_BWD_LDS_KIB");
   if (e) {
     const long v = std::strtol(e, nullptr, 10);
     if (v >= 16 && v <= 160) return static_cast<size_t>(v) * 1024;
   }
-  return (filtered || npol == 2) ? kBwdLdsBudgetWide : kBwdLdsBudget;
+  return filtered ? kBwdLdsBudgetFilt : kBwdLdsBudget;
 }
 
 
@@ -672,7 +673,7 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
   int st = make_plan(m, L.S, nullptr, L.blocks);
   if (st) return st;
   // tile length: the largest multiple of 64 whose LDS footprint fits the budget for every block
-  size_t budget = bwd_lds_budget(m.filtered(), m.npol);
+  size_t budget = bwd_lds_budget(m.filtered());
   int best = 0;
   for (; budget <= kMaxLdsBytes && best == 0; budget += 32 * 1024) {
     for (int Lw = 4096; Lw >= 64; Lw -= 64) {

@@ -246,15 +246,14 @@ __device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, in
     V win[W][NPOL];
 #pragma unroll
     for (int j = 0; j < W; ++j) load_sample<R, NPOL>(yprev + (jb + yshift - K + j) * NPOL, win[j]);
+    // The window of the last chunk reaches up to RB2 - 1 samples past the computed part of yprev (LDS
+    // that may hold anything, NaN included), so samples past own_hi are skipped rather than weighted
+    // by zero.
 #pragma unroll
     for (int r = 0; r < RB2; ++r) {
+      if (jb + r >= own_hi) continue;
       V g[NPOL];
-      if (jb + r < own_hi) {
-        load_sample<R, NPOL>(gu + (jb + r) * NPOL, g);
-      } else {
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) g[p] = V{0, 0};
-      }
+      load_sample<R, NPOL>(gu + (jb + r) * NPOL, g);
 #pragma unroll
       for (int p = 0; p < NPOL; ++p) {
         if constexpr (SYM) {
