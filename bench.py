@@ -977,7 +977,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-waves", type=int, default=48, help="waveforms in the oracle's bounded sample")
     ap.add_argument("--mode", choices=["full", "fwd", "pmc", "bwd", "train", "variants", "dbp", "snr", "essm", "e1",
-                                       "init", "e8", "roof", "manakov_train", "uneven_snr", "fft_lengths"],
+                                       "init", "e8", "roof", "manakov", "manakov_train", "uneven_snr", "fft_lengths"],
                     default="full",
                     help="fwd: forward timing only (for kernel traces); pmc: a few forwards and a copy probe; "
                          "bwd: the training step (checkpointed forward + backward) and a copy probe; "
@@ -990,6 +990,8 @@ def main():
                          "init: least-squares, unit and random initialisation on that link; "
                          "e8: the 32 GBd scenario (symmetric-SSM LDBP, 2 and 4 steps per span); "
                          "roof: the 1,024-waveform forward at 1-10 steps per pass (where the memory roof sits); "
+                         "manakov: dual-polarisation forward and forward + backward on 8 x 2^20 x 2 and a copy "
+                         "probe (for kernel traces and counters); "
                          "manakov_train: train the dual-polarisation 8 x 2^20 x 2 configuration (--train-iters, "
                          "--powers); uneven_snr: the uneven serving batch on simulated inputs, trained span models, "
                          "LDBP against FFT-DBP at 1-10 steps per span (--train-iters per tap count); "
@@ -1125,6 +1127,13 @@ def main():
         print(json.dumps({"mode": "bwd", "fwd_bwd_ms": ms, "ckpt_every": S, "one_stream": args.one_stream,
                           "nwave": nwave, "n": n, "steps_l": ell, "taps": TAPS,
                           "copy_probe": "3 copies of 512 MiB"}), flush=True)
+        return
+    if args.mode == "manakov":
+        out = manakov(torch, dev, max(3, args.steps))
+        copy_probe(torch, dev)
+        out["mode"] = "manakov"
+        out["copy_probe"] = "3 copies of 512 MiB"
+        print(json.dumps(out), flush=True)
         return
     if args.mode == "roof":
         # where the memory roof sits: the forward on 1,024 waveforms (512 MiB per buffer, beyond the
@@ -1284,7 +1293,7 @@ def main():
                           "backward_roofline": {
                               "bound": "alu", "achieved": b_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                               "frac": b_tflops / FP32_PEAK_TFLOPS, "traffic": b_traffic,
-                              "kernel": "ldbp_bwd_kernel<float,1,5,5,256> folded", "launch_ms": b_launch_ms,
+                              "kernel": "ldbp_bwd_kernel<float,1,5,5,256,false,7> folded", "launch_ms": b_launch_ms,
                               "launches": nblk, "one_stream_backward_ms": ms_b,
                               "flops_per_sample_step": bwd_flops_per_sample_step(TAPS, True),
                               "flops_per_launch": b_flops_launch, "algorithmic_bytes_per_launch": b_bytes_launch,
