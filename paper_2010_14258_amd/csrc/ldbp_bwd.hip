@@ -16,7 +16,9 @@
 //   2. load the block-output gradient over [t0-H, t0+L+H);
 //   3. for s = S..1: Kerr adjoint over [t0-h_s, t0+L+h_s), FIR adjoint down to
 //      [t0-h_{s-1}, t0+L+h_{s-1}), tap and Kerr-coefficient gradients summed over
-//      the tile's own positions only (each position is owned by one tile);
+//      the tile's own positions only (each position is owned by one tile; the tap
+//      correlation of filters up to 25 taps is taken in the FIR adjoint's pass as
+//      sum_{owned p} G_u,(p+k) conj(x_p));
 //   4. write the block-input gradient over [t0, t0+L) and the tile's partial
 //      sums (one FP64 value per tap and step) to a [tile][column] buffer that a
 //      second kernel reduces in a fixed order, so results are deterministic.
@@ -145,54 +147,6 @@ __host__ __device__ constexpr int pow2_at_least(int v) {
   return p;
 }
 
-// out[j] = sum_k conj(h_k) in[j+k] for j in [lo, hi); reads in[lo-K, hi+RB+K-2].  SYM: folded.
-template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM>
-__device__ __forceinline__ void fir_adj_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
-                                              int hi, const cx_t<R>* __restrict__ h) {
-  using V = cx_t<R>;
-  constexpr int W = RB + 2 * K;
-  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
-    V win[W][NPOL];
-#pragma unroll
-    for (int j = 0; j < W; ++j) load_sample<R, NPOL>(in + (base - K + j) * NPOL, win[j]);
-    V acc[RB][NPOL];
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int p = 0; p < NPOL; ++p) acc[r][p] = V{0, 0};
-    if constexpr (SYM) {
-      const V h0 = h[K];
-#pragma unroll
-      for (int r = 0; r < RB; ++r)
-#pragma unroll
-        for (int p = 0; p < NPOL; ++p) cmac_conj(acc[r][p], h0, win[r + K][p]);
-#pragma unroll
-      for (int k = 1; k <= K; ++k) {
-        const V hk = h[K + k];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-          for (int p = 0; p < NPOL; ++p) {
-            const V a = win[r + K + k][p], b = win[r + K - k][p];
-            cmac_conj(acc[r][p], hk, V{a.x + b.x, a.y + b.y});
-          }
-      }
-    } else {
-#pragma unroll
-      for (int k = -K; k <= K; ++k) {
-        const V hk = h[K + k];
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-#pragma unroll
-          for (int p = 0; p < NPOL; ++p) cmac_conj(acc[r][p], hk, win[r + k + K][p]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-      if (base + r < hi) store_sample<R, NPOL>(out + (base + r) * NPOL, acc[r]);
-  }
-}
-
 // Long filters (K > 12): direct form (symmetric taps give the same values unfolded).
 template <typename R, int NPOL, int RB, int THREADS>
 __device__ __forceinline__ void fir_adj_generic(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
@@ -226,50 +180,12 @@ __device__ __forceinline__ void cmac_yconj(V& acc, V g, V y) {
   acc.y = fma(-g.x, y.y, acc.y);
 }
 
-// Tap gradient of one step: for each k, sum over owned j in [own_lo, own_lo+Lw) of
-// gu[j] conj(yprev[j + yshift - k]); per-wave sums land in red[wave * ldr + col0 + K + k].
-// SYM: the K + 1 folded sums g_k (see the top of the file); columns K + k and K - k both receive g_k / 2.
-template <typename R, int NPOL, int RB2, int THREADS, int K, bool SYM>
-__device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, int own_lo, int Lw,
-                                              const cx_t<R>* __restrict__ yprev, int yshift,
-                                              double2* __restrict__ red, int ldr, int col0) {
-  using V = cx_t<R>;
-  constexpr int T = 2 * K + 1;
-  constexpr int NA = SYM ? K + 1 : T;  // accumulators: folded k = 0..K, or k = -K..K
-  constexpr int W = RB2 + 2 * K;
-  V acc[NA];
-#pragma unroll
-  for (int k = 0; k < NA; ++k) acc[k] = V{0, 0};
-  const int own_hi = own_lo + Lw;
-  for (int jb = own_lo + static_cast<int>(threadIdx.x) * RB2; jb < own_hi; jb += THREADS * RB2) {
-    // both polarisations of a time sample in one load (one 16-byte LDS access for two complex64)
-    V win[W][NPOL];
-#pragma unroll
-    for (int j = 0; j < W; ++j) load_sample<R, NPOL>(yprev + (jb + yshift - K + j) * NPOL, win[j]);
-    // The window of the last chunk reaches up to RB2 - 1 samples past the computed part of yprev (LDS
-    // that may hold anything, NaN included), so samples past own_hi are skipped rather than weighted
-    // by zero.
-#pragma unroll
-    for (int r = 0; r < RB2; ++r) {
-      if (jb + r >= own_hi) continue;
-      V g[NPOL];
-      load_sample<R, NPOL>(gu + (jb + r) * NPOL, g);
-#pragma unroll
-      for (int p = 0; p < NPOL; ++p) {
-        if constexpr (SYM) {
-          cmac_yconj(acc[0], g[p], win[r + K][p]);
-#pragma unroll
-          for (int k = 1; k <= K; ++k) {
-            const V a = win[r - k + K][p], b = win[r + k + K][p];
-            cmac_yconj(acc[k], g[p], V{a.x + b.x, a.y + b.y});
-          }
-        } else {
-#pragma unroll
-          for (int k = -K; k <= K; ++k) cmac_yconj(acc[K + k], g[p], win[r - k + K][p]);
-        }
-      }
-    }
-  }
+// Stores the wave totals of a thread's tap accumulators as FP64 partials red[wave * ldr + col0 + K + k]:
+// SYM, the K + 1 folded sums g_k (see the top of the file), columns K + k and K - k both receiving
+// g_k / 2 (g_0 whole); otherwise the 2K + 1 sums of k = -K..K.
+template <typename R, int K, bool SYM>
+__device__ __forceinline__ void tap_wave_sums(const cx_t<R>* acc, double2* __restrict__ red, int ldr, int col0) {
+  constexpr int NA = SYM ? K + 1 : 2 * K + 1;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   double* redd = reinterpret_cast<double*>(red);
@@ -313,8 +229,73 @@ __device__ __forceinline__ void tapgrad_fixed(const cx_t<R>* __restrict__ gu, in
   }
 }
 
-// Long filters (K > 12): one tap at a time; with sym the mirrored pair is summed and halved as in
-// tapgrad_fixed.
+// FIR adjoint and tap correlation of one step in a single pass, RB outputs per thread from one register
+// window of G_u (reads in[lo-K, hi+RB+K-2]):
+//   G_x,p = sum_k conj(h_k) G_u,(p+k)                               for p in [lo, hi), into out
+//   a_k  += G_u,(p+k) conj(y_p), k = -K..K                          for p in [own_lo, own_hi)
+// with y_p = yprev[p + yshift].  Over all tiles, sum_{owned p} G_u,(p+k) conj(y_p) is the tap
+// correlation sum_m G_u,m conj(y_(m-k)) (every position of the circle is owned by one tile; only the
+// grouping of the terms differs).  SYM: both products take the pair sums G_u,(p+k) + G_u,(p-k) once,
+// a_k being the folded sum g_k.  Halo positions weight finite G_u by y = 0; positions past hi, whose
+// windows reach LDS past the computed range, are skipped.
+template <typename R, int NPOL, int RB, int THREADS, int K, bool SYM>
+__device__ __forceinline__ void fir_adj_tap_fixed(const cx_t<R>* __restrict__ in, cx_t<R>* __restrict__ out, int lo,
+                                                  int hi, const cx_t<R>* __restrict__ h, int own_lo, int own_hi,
+                                                  const cx_t<R>* __restrict__ yprev, int yshift,
+                                                  double2* __restrict__ red, int ldr, int col0) {
+  using V = cx_t<R>;
+  constexpr int W = RB + 2 * K;
+  constexpr int NA = SYM ? K + 1 : 2 * K + 1;
+  V ta[NA];
+#pragma unroll
+  for (int k = 0; k < NA; ++k) ta[k] = V{0, 0};
+  for (int base = lo + static_cast<int>(threadIdx.x) * RB; base < hi; base += THREADS * RB) {
+    V win[W][NPOL];
+#pragma unroll
+    for (int j = 0; j < W; ++j) load_sample<R, NPOL>(in + (base - K + j) * NPOL, win[j]);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int p = base + r;
+      if (p >= hi) continue;
+      V y[NPOL];
+      if (p >= own_lo && p < own_hi) {
+        load_sample<R, NPOL>(yprev + (p + yshift) * NPOL, y);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NPOL; ++q) y[q] = V{0, 0};
+      }
+      V o[NPOL];
+#pragma unroll
+      for (int q = 0; q < NPOL; ++q) {
+        o[q] = V{0, 0};
+        if constexpr (SYM) {
+          const V g0 = win[r + K][q];
+          cmac_conj(o[q], h[K], g0);
+          cmac_yconj(ta[0], g0, y[q]);
+#pragma unroll
+          for (int k = 1; k <= K; ++k) {
+            const V a = win[r + K + k][q], b = win[r + K - k][q];
+            const V ps{a.x + b.x, a.y + b.y};
+            cmac_conj(o[q], h[K + k], ps);
+            cmac_yconj(ta[k], ps, y[q]);
+          }
+        } else {
+#pragma unroll
+          for (int k = -K; k <= K; ++k) {
+            const V g = win[r + K + k][q];
+            cmac_conj(o[q], h[K + k], g);
+            cmac_yconj(ta[K + k], g, y[q]);
+          }
+        }
+      }
+      store_sample<R, NPOL>(out + p * NPOL, o);
+    }
+  }
+  tap_wave_sums<R, K, SYM>(ta, red, ldr, col0);
+}
+
+// Long filters (K > 12): one tap at a time over the owned positions j, sum_j G_u,j conj(y_(j-k)); with
+// sym the mirrored pair is summed and halved as in tap_wave_sums.
 template <typename R, int NPOL, int RB2, int THREADS>
 __device__ __forceinline__ void tapgrad_generic(const cx_t<R>* __restrict__ gu, int own_lo, int Lw, int K,
                                                 const cx_t<R>* __restrict__ yprev, int yshift,
@@ -354,8 +335,8 @@ __device__ __forceinline__ void adj_step_dispatch_t(const cx_t<R>* gb, cx_t<R>* 
 #define LDBP_BWD_CASE(k)                                                                             \
   case k:                                                                                            \
     if constexpr (k <= KMAX) {                                                                       \
-      fir_adj_fixed<R, NPOL, RB, THREADS, k, SYM>(gb, ga, lo, hi, h);                                \
-      tapgrad_fixed<R, NPOL, RB2, THREADS, k, SYM>(gb, own_lo, Lw, yprev, yshift, red, ldr, col0);   \
+      fir_adj_tap_fixed<R, NPOL, RB, THREADS, k, SYM>(gb, ga, lo, hi, h, own_lo, own_lo + Lw, yprev, yshift, \
+                                                     red, ldr, col0);                                \
     } else {                                                                                         \
       fir_adj_generic<R, NPOL, RB, THREADS>(gb, ga, lo, hi, K, h);                                   \
       tapgrad_generic<R, NPOL, RB2, THREADS>(gb, own_lo, Lw, K, yprev, yshift, red, ldr, col0, SYM); \
