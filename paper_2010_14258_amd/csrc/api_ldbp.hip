@@ -672,11 +672,11 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
   L.S = ckpt_every > 0 ? ckpt_every : default_bwd_S(m);
   int st = make_plan(m, L.S, nullptr, L.blocks);
   if (st) return st;
-  // tile length: the largest multiple of 64 whose LDS footprint fits the budget for every block
+  // tile length: the largest multiple of 8 whose LDS footprint fits the budget for every block
   size_t budget = bwd_lds_budget(m.filtered());
   int best = 0;
   for (; budget <= kMaxLdsBytes && best == 0; budget += 32 * 1024) {
-    for (int Lw = 4096; Lw >= 64; Lw -= 64) {
+    for (int Lw = 4096; Lw >= 64; Lw -= 8) {
       bool ok = true;
       for (const auto& pt : L.blocks.passes)
         if (bwd_lds_bytes(m.dtype, m.npol, Lw, pt, m.filtered()) > budget) { ok = false; break; }
@@ -686,6 +686,36 @@ static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_ever
   if (best == 0)
     return fail(LDBP_EUNSUPPORTED, "checkpoint blocks of %d steps do not fit in LDS for the backward; use fewer",
                 L.S);
+  // The widest chunked pass, the first recompute step, covers Lw + 4H - 2K_1 samples in rounds of q
+  // (outputs per thread x threads).  When its last round would be short, a tile that ends the pass on a
+  // whole round does fewer rounds per sample: e.g. 64 x 65,536, l = 50, 15 taps, blocks of 2 steps,
+  // q = 1280: 1,256 samples take 2 rounds (1,298 wide), 1,232 one; measured tiles of 1,216 / 1,240 took
+  // 1.64 / 1.69 ms per backward, 1,256 2.36 ms.  With one round per pass a tile takes about the same time
+  // at any length, so the tiles of a waveform are then made equal (1,216 there); on 8 x 2^20 x 2, 5 taps,
+  // blocks of 3 steps, tiles of 632 against 576 took 5.59 against 5.85 ms for forward + backward.
+  {
+    const int q = bwd_chunk_capacity(m.dtype, m.npol);
+    int over = 0;
+    for (const auto& pt : L.blocks.passes) over = std::max(over, 4 * pt.halo - 2 * pt.K[0]);
+    const int rounds = (best + over + q - 1) / q;
+    const int shorter = ((rounds - 1) * q - over) / 8 * 8;
+    // rounds per sample: (rounds - 1) / shorter against rounds / best
+    if (rounds > 1 && shorter >= 64 && static_cast<int64_t>(rounds - 1) * best < static_cast<int64_t>(rounds) * shorter)
+      best = shorter;
+    // the same number of tiles per waveform, of equal length (no short last tile)
+    const int64_t nt = (m.n + best - 1) / best;
+    const int64_t bal = ((m.n + nt - 1) / nt + 7) / 8 * 8;
+    if (bal >= 64 && bal < best) best = static_cast<int>(bal);
+  }
+  // LDBP_BWD_TILE (a tuning knob): an exact tile length, used when it is a multiple of 8 whose LDS
+  // footprint fits the largest workgroup allocation
+  if (const char* e = std::getenv("LDBP_BWD_TILE")) {
+    const long v = std::strtol(e, nullptr, 10);
+    bool ok = v >= 64 && v <= 4096 && v % 8 == 0;
+    for (const auto& pt : L.blocks.passes)
+      if (ok && bwd_lds_bytes(m.dtype, m.npol, static_cast<int>(v), pt, m.filtered()) > kMaxLdsBytes) ok = false;
+    if (ok) best = static_cast<int>(v);
+  }
   L.tile_len = best;
   L.ntiles = m.nwave * ((m.n + best - 1) / best);
   if (grad_reduce_chunks(L.ntiles) > 65535)

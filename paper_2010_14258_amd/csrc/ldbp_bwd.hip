@@ -366,6 +366,44 @@ __device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga
                                                                 ldr, col0);
 }
 
+// The block input over [t0 - Ha, t0 - Ha + Wa) into bufa and the block-output gradient over
+// [t0 - Hb, t0 - Hb + Wb) into bufb (circular indices), both batches of global loads in flight before the
+// first LDS store, so the tile waits for one round trip instead of two.
+template <typename R, int NPOL, int THREADS>
+__device__ __forceinline__ void load_two_tiles(const cx_t<R>* __restrict__ xa, cx_t<R>* __restrict__ bufa, int Ha,
+                                               int Wa, const cx_t<R>* __restrict__ xb, cx_t<R>* __restrict__ bufb,
+                                               int Hb, int Wb, int n, int t0) {
+  using V = cx_t<R>;
+  constexpr int kLoadBatch = 64 / static_cast<int>(sizeof(V) * NPOL);
+  // one addition or subtraction brings t0 - H + j onto the circle unless the halo exceeds n (2 Ha >= n,
+  // tiny waveforms), which takes the remainder
+  const bool general = 2 * Ha >= n;
+  auto wrap = [n, general](int g) {
+    if (general) {
+      g %= n;
+      return g < 0 ? g + n : g;
+    }
+    return g < 0 ? g + n : (g >= n ? g - n : g);
+  };
+  const int W = max(Wa, Wb);
+  for (int j0 = threadIdx.x; j0 < W; j0 += kLoadBatch * THREADS) {
+    V va[kLoadBatch][NPOL], vb[kLoadBatch][NPOL];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      // past the end: reload the last sample, not stored
+      const int ja = min(j0 + u * THREADS, Wa - 1), jb = min(j0 + u * THREADS, Wb - 1);
+      load_sample<R, NPOL>(xa + static_cast<int64_t>(wrap(t0 - Ha + ja)) * NPOL, va[u]);
+      load_sample<R, NPOL>(xb + static_cast<int64_t>(wrap(t0 - Hb + jb)) * NPOL, vb[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int j = j0 + u * THREADS;
+      if (j < Wa) store_sample<R, NPOL>(bufa + j * NPOL, va[u]);
+      if (j < Wb) store_sample<R, NPOL>(bufb + j * NPOL, vb[u]);
+    }
+  }
+}
+
 // Buffer margin of Y_s (block output of step s within the tile's recompute): the forward starts from
 // a margin of 2H and each step shrinks the valid margin by K_s + kappa_s; a filtered step keeps its
 // FIR output (margin V_{s-1} - K_s) in place and rotates only the inner part, so the buffer margin of
@@ -624,8 +662,8 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
   const V* xw = xb + wave * static_cast<int64_t>(n) * NPOL;
   const V* gw = gout + wave * static_cast<int64_t>(n) * NPOL;
 
-  // 1. block input and forward recompute
-  load_tile<R, NPOL, THREADS>(xw, Y0, n, t0, 2 * H, Lw + 4 * H, (2 * H >= n) ? 1 : 0);
+  // 1. block input (and the block-output gradient of step 2), forward recompute
+  load_two_tiles<R, NPOL, THREADS>(xw, Y0, 2 * H, Lw + 4 * H, gw, GA, H, Lw + 2 * H, n, t0);
   __syncthreads();
   hs = 0;
   V* ycur = Y0;
@@ -652,9 +690,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     kprev = kp;
     ycur = ynext;
   }
-  // 2. block-output gradient
-  load_tile<R, NPOL, THREADS>(gw, GA, n, t0, H, Lw + 2 * H, (H >= n) ? 1 : 0);
-  __syncthreads();
+  // 2. the block-output gradient is in GA (loaded with the block input)
 
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -840,6 +876,13 @@ static int bwd_pad(int dtype, int npol) {
 static int bwd_waves(int dtype, int npol) {
   if (dtype == LDBP_C64) return (npol == 2 ? BwdCfg<float, 2>::THREADS : BwdCfg<float, 1>::THREADS) / 64;
   return (npol == 2 ? BwdCfg<double, 2>::THREADS : BwdCfg<double, 1>::THREADS) / 64;
+}
+
+int bwd_chunk_capacity(int dtype, int npol) {
+  if (dtype == LDBP_C64)
+    return npol == 2 ? BwdCfg<float, 2>::RB * BwdCfg<float, 2>::THREADS : BwdCfg<float, 1>::RB * BwdCfg<float, 1>::THREADS;
+  return npol == 2 ? BwdCfg<double, 2>::RB * BwdCfg<double, 2>::THREADS
+                   : BwdCfg<double, 1>::RB * BwdCfg<double, 1>::THREADS;
 }
 
 size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt, bool filtered) {

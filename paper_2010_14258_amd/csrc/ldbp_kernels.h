@@ -65,6 +65,9 @@ int launch_fwd_pass_c128(int npol, int rb, const void* x, void* y, int64_t nwave
 // Partial-sum columns: [taps (ntaps)] [power filters (neta), ecol_base = ntaps] [c (l), ccol_base].
 // eta: packed power filters of filtered steps (generalised ESSM), or NULL.
 size_t bwd_lds_bytes(int dtype, int npol, int Lw, const PassTable& pt, bool filtered = false);
+// Samples one round of a backward workgroup's threads covers in the chunked passes (outputs per thread x
+// threads).
+int bwd_chunk_capacity(int dtype, int npol);
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
                      int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream, const void* eta = nullptr,
