@@ -206,7 +206,10 @@ int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
  *   (dtype .. c)  as for ldbp_forward
  *   x            device [nwave][n][npol] complex: the forward input
  *   ckpt         device checkpoints written by ldbp_forward with the same ckpt_every,
- *                or NULL: the backward recomputes them into its workspace
+ *                or NULL: the backward recomputes them into its workspace.  With
+ *                ckpt_every = 1 (every step's output stored; complex64, ldbp_backward only)
+ *                the backward reads the stored outputs in blocks of the default length
+ *                instead of recomputing each step (more HBM traffic, fewer instructions)
  *   ckpt_every   block length S (1..LDBP_MAX_STEPS_PER_PASS); 0 = library default
  *                (only with ckpt == NULL: 2 steps for complex64 with one polarisation,
  *                3 otherwise, or nstep if smaller).  Long blocks may not fit in LDS

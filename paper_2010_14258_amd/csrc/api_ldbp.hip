@@ -658,7 +658,12 @@ struct BwdLayout {
   int32_t ntaps;     // sum T
   int32_t neta;      // sum of the power-filter lengths (0 for LDBP)
   size_t off_ckpt, off_g0, off_g1, off_part, off_chunks, total;
+  bool stored;       // the caller's checkpoints hold every step's output (ckpt_every = 1): blocks of S steps
+                     // read their step outputs instead of recomputing them
 };
+
+// Longest block whose stored step outputs the backward kernel loads with its inputs.
+constexpr int kMaxStoredSteps = 3;
 
 // Block length of the backward when the caller gives none.  complex64: 2 steps for one polarisation,
 // 3 for two (forward with checkpoints + backward on 64 x 65,536, l = 50, 15 taps: S = 1-5 took 2.44,
@@ -670,6 +675,11 @@ static int default_bwd_S(const ModelArgs& m) {
 
 static int make_bwd_layout(const ModelArgs& m, bool have_ckpt, int32_t ckpt_every, BwdLayout& L) {
   L.S = ckpt_every > 0 ? ckpt_every : default_bwd_S(m);
+  // Every step's output given (unfiltered complex64 steps): the backward reads them in blocks of the default length
+  // instead of recomputing each step from its checkpoint, trading HBM traffic (S + 3 arrays per block of S
+  // steps instead of 3) for the forward FIR and Kerr phase of every step.
+  L.stored = have_ckpt && ckpt_every == 1 && !m.filtered() && m.dtype == LDBP_C64 && m.nstep > 1;
+  if (L.stored) L.S = std::min(default_bwd_S(m), kMaxStoredSteps);
   int st = make_plan(m, L.S, nullptr, L.blocks);
   if (st) return st;
   // tile length: the largest multiple of 8 whose LDS footprint fits the budget for every block
@@ -830,10 +840,19 @@ static int backward_impl(const ModelArgs& m, const void* taps, const void* c, co
     const char* gcur = static_cast<const char*>(gy) + off;
     for (size_t bi = nb; bi-- > 0;) {
       const char* xb = (bi == 0 ? static_cast<const char*>(x) : ck + (bi - 1) * wave_bytes) + off;
+      const char* ys = nullptr;
+      int32_t nstored = 0;
+      if (L.stored) {
+        // checkpoint j holds the output of step j + 1; the last step's output is not stored (recomputed)
+        const int32_t sb = L.blocks.passes[bi].c0;
+        xb = (sb == 0 ? static_cast<const char*>(x) : ck + static_cast<size_t>(sb - 1) * wave_bytes) + off;
+        ys = ck + static_cast<size_t>(sb) * wave_bytes + off;
+        nstored = std::min<int32_t>(L.blocks.passes[bi].nstep, m.nstep - 1 - sb);
+      }
       char* gin = static_cast<char*>((bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0)) + off;
       const int r = launch_bwd_block(dtype, npol, xb, gcur, gin, w1 - w0, static_cast<int32_t>(n), L.tile_len,
                                      L.blocks.passes[bi], taps, c, prt, L.ncols, L.ntaps + L.neta, sym, ss, e,
-                                     L.ntaps);
+                                     L.ntaps, ys, static_cast<int64_t>(nwave) * n * npol, nstored);
       if (r) return r;
       gcur = gin;
     }

@@ -366,18 +366,26 @@ __device__ __forceinline__ void adj_step_dispatch(const cx_t<R>* gb, cx_t<R>* ga
                                                                 ldr, col0);
 }
 
-// The block input over [t0 - Ha, t0 - Ha + Wa) into bufa and the block-output gradient over
-// [t0 - Hb, t0 - Hb + Wb) into bufb (circular indices), both batches of global loads in flight before the
-// first LDS store, so the tile waits for one round trip instead of two.
-template <typename R, int NPOL, int THREADS>
-__device__ __forceinline__ void load_two_tiles(const cx_t<R>* __restrict__ xa, cx_t<R>* __restrict__ bufa, int Ha,
-                                               int Wa, const cx_t<R>* __restrict__ xb, cx_t<R>* __restrict__ bufb,
-                                               int Hb, int Wb, int n, int t0) {
+// Up to kMaxBwdTiles tiles of the block's inputs loaded with all their global loads in flight before the
+// first LDS store, so the tile waits for one round trip instead of one per buffer: tile i is
+// src[i] over the circular positions [t0 - halo[i], t0 - halo[i] + width[i]) into dst[i].
+constexpr int kMaxBwdTiles = 5;   // block input, output gradient and up to 3 stored step outputs
+template <typename R>
+struct BwdTile {
+  const cx_t<R>* src;
+  cx_t<R>* dst;
+  int halo, width;
+};
+
+template <typename R, int NPOL, int THREADS, int NT>
+__device__ __forceinline__ void load_bwd_tiles(const BwdTile<R> (&t)[kMaxBwdTiles], int cnt, int n, int t0,
+                                               bool general) {
   using V = cx_t<R>;
-  constexpr int kLoadBatch = 64 / static_cast<int>(sizeof(V) * NPOL);
-  // one addition or subtraction brings t0 - H + j onto the circle unless the halo exceeds n (2 Ha >= n,
-  // tiny waveforms), which takes the remainder
-  const bool general = 2 * Ha >= n;
+  // 64 bytes of samples per tile and thread in flight; with more than two tiles, 32 bytes for samples of
+  // 16 bytes or more (the registers stay under 48)
+  constexpr int kLoadBatch = 64 / static_cast<int>(sizeof(V) * NPOL) / (NT > 2 && sizeof(V) * NPOL >= 16 ? 2 : 1);
+  // one addition or subtraction brings t0 - halo + j onto the circle unless the halo exceeds n (tiny
+  // waveforms), which takes the remainder
   auto wrap = [n, general](int g) {
     if (general) {
       g %= n;
@@ -385,21 +393,31 @@ __device__ __forceinline__ void load_two_tiles(const cx_t<R>* __restrict__ xa, c
     }
     return g < 0 ? g + n : (g >= n ? g - n : g);
   };
-  const int W = max(Wa, Wb);
-  for (int j0 = threadIdx.x; j0 < W; j0 += kLoadBatch * THREADS) {
-    V va[kLoadBatch][NPOL], vb[kLoadBatch][NPOL];
+  int W = 0;
 #pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
-      // past the end: reload the last sample, not stored
-      const int ja = min(j0 + u * THREADS, Wa - 1), jb = min(j0 + u * THREADS, Wb - 1);
-      load_sample<R, NPOL>(xa + static_cast<int64_t>(wrap(t0 - Ha + ja)) * NPOL, va[u]);
-      load_sample<R, NPOL>(xb + static_cast<int64_t>(wrap(t0 - Hb + jb)) * NPOL, vb[u]);
+  for (int i = 0; i < NT; ++i)
+    if (i < cnt) W = max(W, t[i].width);
+  for (int j0 = threadIdx.x; j0 < W; j0 += kLoadBatch * THREADS) {
+    V v[NT][kLoadBatch][NPOL];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {
+      if (i < cnt) {
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+          const int j = min(j0 + u * THREADS, t[i].width - 1);  // past the end: reload the last sample, not stored
+          load_sample<R, NPOL>(t[i].src + static_cast<int64_t>(wrap(t0 - t[i].halo + j)) * NPOL, v[i][u]);
+        }
+      }
     }
 #pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
-      const int j = j0 + u * THREADS;
-      if (j < Wa) store_sample<R, NPOL>(bufa + j * NPOL, va[u]);
-      if (j < Wb) store_sample<R, NPOL>(bufb + j * NPOL, vb[u]);
+    for (int i = 0; i < NT; ++i) {
+      if (i < cnt) {
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+          const int j = j0 + u * THREADS;
+          if (j < t[i].width) store_sample<R, NPOL>(t[i].dst + j * NPOL, v[i][u]);
+        }
+      }
     }
   }
 }
@@ -615,7 +633,8 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const cx_t<R>* __restrict__ xb, const cx_t<R>* __restrict__ gout, cx_t<R>* __restrict__ gin, int32_t n,
     int32_t tile_len, int32_t ntiles, const cx_t<R>* __restrict__ taps, const R* __restrict__ c, PassTable pt,
     int32_t pad, double2* __restrict__ part, int32_t ncols, int32_t ccol_base, int32_t sym,
-    const R* __restrict__ eta, int32_t ecol_base) {
+    const R* __restrict__ eta, int32_t ecol_base, const cx_t<R>* __restrict__ ys, int64_t ys_stride,
+    int32_t nstored) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = THREADS / 64;
@@ -662,8 +681,35 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
   const V* xw = xb + wave * static_cast<int64_t>(n) * NPOL;
   const V* gw = gout + wave * static_cast<int64_t>(n) * NPOL;
 
-  // 1. block input (and the block-output gradient of step 2), forward recompute
-  load_two_tiles<R, NPOL, THREADS>(xw, Y0, 2 * H, Lw + 4 * H, gw, GA, H, Lw + 2 * H, n, t0);
+  // 1. block input, block-output gradient (used in step 3) and, when the forward stored them, the
+  // outputs of the block's first nstored steps (unfiltered complex64 steps only), each over the range
+  // its recompute would cover; then the forward recompute of the remaining steps
+  {
+    BwdTile<R> t[kMaxBwdTiles];
+    t[0] = BwdTile<R>{xw, Y0, 2 * H, Lw + 4 * H};
+    t[1] = BwdTile<R>{gw, GA, H, Lw + 2 * H};
+    int cnt = 2;
+    if constexpr (!FILT && sizeof(R) == 4) {
+      V* yb = Y0;
+      int h = 0;
+#pragma unroll
+      for (int s = 1; s <= kMaxBwdTiles - 2; ++s) {   // constant indices into t (no private memory)
+        if (s <= nstored) {
+          yb += static_cast<size_t>(bwd_y_width(Lw, H, h) + pad) * NPOL;
+          h += pt.K[s - 1];
+          t[1 + s] = BwdTile<R>{ys + (s - 1) * ys_stride + wave * static_cast<int64_t>(n) * NPOL, yb, 2 * H - h,
+                                bwd_y_width(Lw, H, h)};
+          cnt = 2 + s;
+        }
+      }
+    }
+    if constexpr (!FILT && sizeof(R) == 4) {
+      if (cnt > 2) load_bwd_tiles<R, NPOL, THREADS, kMaxBwdTiles>(t, cnt, n, t0, 2 * H >= n);
+      else load_bwd_tiles<R, NPOL, THREADS, 2>(t, cnt, n, t0, 2 * H >= n);
+    } else {
+      load_bwd_tiles<R, NPOL, THREADS, 2>(t, cnt, n, t0, 2 * H >= n);
+    }
+  }
   __syncthreads();
   hs = 0;
   V* ycur = Y0;
@@ -673,6 +719,12 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const int kp = kapp(s);
     V* ynext = ycur + static_cast<size_t>(bwd_y_width(Lw, H, hs, kprev) + pad) * NPOL;
     const R coef = c[pt.c0 + s - 1] * phase_coef_scale<R>();
+    if (!FILT && sizeof(R) == 4 && s <= nstored) {
+      // loaded above
+      hs += K;
+      ycur = ynext;
+      continue;
+    }
     if constexpr (FILT) {
       // FIR output over the buffer of Y_s (valid margin of Y_{s-1} minus K), power into PP, then the
       // filtered phase on the inner part
@@ -909,7 +961,7 @@ template <typename R, int NPOL>
 static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                               int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
                               int32_t ncols, int32_t ccol_base, int sym, const void* eta, int32_t ecol_base,
-                              hipStream_t stream) {
+                              const void* ys, int64_t ys_stride, int32_t nstored, hipStream_t stream) {
   using Cfg = BwdCfg<R, NPOL>;
   const int64_t ntiles = (n + tile_len - 1) / tile_len;
   const int64_t nblocks = ntiles * nwave;
@@ -932,7 +984,8 @@ static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64
                      static_cast<const cx_t<R>*>(xb), static_cast<const cx_t<R>*>(gout), static_cast<cx_t<R>*>(gin),
                      n, tile_len, static_cast<int32_t>(ntiles), static_cast<const cx_t<R>*>(taps),
                      static_cast<const R*>(c), pt, bwd_pad(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL),
-                     static_cast<double2*>(part), ncols, ccol_base, sym, static_cast<const R*>(eta), ecol_base);
+                     static_cast<double2*>(part), ncols, ccol_base, sym, static_cast<const R*>(eta), ecol_base,
+                     static_cast<const cx_t<R>*>(ys), ys_stride, nstored);
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }
@@ -940,8 +993,11 @@ static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
                      int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream, const void* eta,
-                     int32_t ecol_base) {
-#define LDBP_BWD_ARGS xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols, ccol_base, sym, eta, ecol_base, stream
+                     int32_t ecol_base, const void* ys, int64_t ys_stride, int32_t nstored) {
+  if (nstored > 0 && (eta || dtype != LDBP_C64 || nstored > kMaxBwdTiles - 2 || nstored > pt.nstep))
+    return fail(LDBP_EINVAL, "stored step outputs: %d for a block of %d steps", nstored, pt.nstep);
+#define LDBP_BWD_ARGS \
+  xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols, ccol_base, sym, eta, ecol_base, ys, ys_stride, nstored, stream
   if (dtype == LDBP_C64)
     return npol == 1 ? launch_bwd_block_t<float, 1>(LDBP_BWD_ARGS) : launch_bwd_block_t<float, 2>(LDBP_BWD_ARGS);
   return npol == 1 ? launch_bwd_block_t<double, 1>(LDBP_BWD_ARGS) : launch_bwd_block_t<double, 2>(LDBP_BWD_ARGS);

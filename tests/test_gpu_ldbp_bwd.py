@@ -223,19 +223,53 @@ def test_autograd_function_matches_oracle():
     assert _rel(ct.grad.cpu().numpy(), gc) <= 1e-4
 
 
-def test_backward_full_size_32x16384_l50_T25():
+_FULL_SIZE = {}
+
+
+def _full_size_case():
+    if not _FULL_SIZE:
+        nw, nsym = 32, 8192
+        p_dbm = 3.0
+        r, s = W.received_waveforms(303, nw, nsym, p_dbm=p_dbm)
+        taps, c = W.ldbp_init(10, 5, 25)
+        y = O.ldbp_forward(r, taps, c)
+        _, gy = X.rx_loss_and_grad(y, s, 2, 10 ** ((p_dbm - 30) / 10), W.RS)
+        _FULL_SIZE.update(r=r, taps=taps, c=c, gy=gy, ref=O.ldbp_grad(r, taps, c, gy))
+    return _FULL_SIZE
+
+
+@pytest.mark.parametrize("every", [5, 1])
+def test_backward_full_size_32x16384_l50_T25(every):
     """Training batch of 32 x 16,384 samples (10 x 100 km, 2 samples/symbol), l = 50, 25 taps, LS init,
-    gradient of the receiver MSE (matched filter, genie phase) w.r.t. the LDBP output."""
-    print("case: bwd full size", flush=True)
-    nw, nsym = 32, 8192
-    p_dbm = 3.0
-    r, s = W.received_waveforms(303, nw, nsym, p_dbm=p_dbm)
-    taps, c = W.ldbp_init(10, 5, 25)
-    y = O.ldbp_forward(r, taps, c)
-    _, gy = X.rx_loss_and_grad(y, s, 2, 10 ** ((p_dbm - 30) / 10), W.RS)
-    ref = O.ldbp_grad(r, taps, c, gy)
-    got = _gpu_grad(r, taps, c, gy, dtype=torch.complex64, ckpt_every=5, use_ckpt=True)
-    _cmp(got, ref, 1e-4)
+    gradient of the receiver MSE (matched filter, genie phase) w.r.t. the LDBP output; checkpoints every
+    5 steps (recomputed blocks) and every step (the backward reads the stored step outputs)."""
+    print("case: bwd full size every", every, flush=True)
+    f = _full_size_case()
+    got = _gpu_grad(f["r"], f["taps"], f["c"], f["gy"], dtype=torch.complex64, ckpt_every=every, use_ckpt=True)
+    _cmp(got, f["ref"], 1e-4)
+
+
+@pytest.mark.parametrize("npol", [1, 2])
+def test_backward_stored_outputs_match_recompute(npol):
+    """Every step's output stored by the forward (ckpt_every = 1): the backward reads them in blocks of the
+    library's default length instead of recomputing, the last step's output (not stored) recomputed in
+    the last block, which here holds two steps (l = 8, blocks of 2 or 3).  Same result as the
+    recomputing backward with checkpoints at the block boundaries, and as the oracle."""
+    print("case: bwd stored outputs", npol, flush=True)
+    Ts = [15, 5, 15, 3, 9, 15, 1, 7]
+    taps, c = _model(120, Ts, 0.3)
+    taps = [0.5 * (h + h[::-1]) for h in taps]
+    shape = (3, 4001) if npol == 1 else (2, 3001, 2)
+    x = synth.complex_normal(121, shape) * 0.5
+    gy = synth.complex_normal(122, shape)
+    S = 2 if npol == 1 else 3
+    stored = _gpu_grad(x, taps, c, gy, npol=npol, dtype=torch.complex64, ckpt_every=1, use_ckpt=True,
+                       symmetric=True)
+    recomp = _gpu_grad(x, taps, c, gy, npol=npol, dtype=torch.complex64, ckpt_every=S, use_ckpt=True,
+                       symmetric=True)
+    _cmp(stored, recomp, 1e-6)
+    rx, rt, rc = O.ldbp_grad(x, taps, c, gy, npol=npol)
+    _cmp(stored, (rx, _sym_projection(rt), rc), 1e-4)
 
 
 @pytest.mark.parametrize("every", [3, 2])
