@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "common.h"
@@ -505,10 +506,21 @@ static int run_resident(const SsmGeom& g, const void* x, void* y, const std::vec
   PwOp* odev = reinterpret_cast<PwOp*>(base + zbytes);
   const size_t obytes = ((static_cast<size_t>(M) + 1) * sizeof(PwOp) + 255) & ~size_t(255);
   V* tab = reinterpret_cast<V*>(base + zbytes + obytes);
-  if (M > 0) LDBP_HIP_CHECK(hipMemcpyAsync(zdev, lin_z.data(), M * sizeof(double), hipMemcpyHostToDevice, s));
-  LDBP_HIP_CHECK(hipMemcpyAsync(odev, ops.data(), (M + 1) * sizeof(PwOp), hipMemcpyHostToDevice, s));
-  // the copies read pageable host vectors that are released on return: wait for them
-  LDBP_HIP_CHECK(hipStreamSynchronize(s));
+  // The program goes to the device from a heap copy that a host function queued behind the copy frees,
+  // so the call returns without waiting for the stream (the caller's vectors are released on return).
+  {
+    auto* prog = new std::vector<char>(zbytes + obytes);
+    if (M > 0) std::memcpy(prog->data(), lin_z.data(), M * sizeof(double));
+    std::memcpy(prog->data() + zbytes, ops.data(), (M + 1) * sizeof(PwOp));
+    hipError_t e = hipMemcpyAsync(base, prog->data(), prog->size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipLaunchHostFunc(s, [](void* p) { delete static_cast<std::vector<char>*>(p); }, prog);
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      delete prog;
+      return fail(LDBP_EHIP, "copying the split-step program: %s", hipGetErrorString(e));
+    }
+  }
   TwSegs sg{};
   sg.nseg = 1;
   sg.count[0] = g.n;

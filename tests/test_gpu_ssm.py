@@ -150,3 +150,22 @@ def test_full_size_batches():
     yy2 = y2.cpu().numpy()
     for b in (0, 31):
         assert _rel(yy2[b], S.ssm_channel(x[b], o2)) <= 1e-4
+
+
+def test_resident_calls_queue_without_waiting():
+    """Resident path (n <= 4096): calls with different programs queued on one stream with one shared
+    workspace and no synchronisation between them (the program upload does not wait for the stream);
+    each result equals the same call made alone."""
+    print("case: resident queued calls", flush=True)
+    fs = 42.8e9
+    x = _t(_wave(7, 2, 2048, 1, 5e-3), torch.complex128)
+    links = [G.Link(fs=fs, alpha=ALPHA, beta2=BETA2, gamma=GAMMA, span_len=80e3, nspan=1 + i % 3, nstep=2 + i)
+             for i in range(6)]
+    ws = torch.empty(max(G.ssm_workspace_size(x, k) for k in links), dtype=torch.uint8, device=DEV)
+    torch.cuda.synchronize()
+    outs = [G.fft_dbp(x, k, ws=ws) for k in links]
+    torch.cuda.synchronize()
+    for k, out in zip(links, outs):
+        ref = G.fft_dbp(x, k)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
