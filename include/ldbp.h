@@ -297,8 +297,10 @@ int ldbp_forward_aperiodic(int32_t dtype, int32_t npol, int64_t nwave, int64_t n
  *   c      device [sum_b wave_nstep[b]] real
  * Every waveform is processed with all its steps fused in one pass (halo = sum of its K), so the
  * whole batch is one kernel launch over independent (waveform, tile) items ordered by decreasing
- * cost.  A waveform whose total halo exceeds the LDS work size is rejected (LDBP_EUNSUPPORTED).
- * The plan owns small device tables (allocated by ldbp_batch_plan_create, freed by
+ * cost.  A waveform whose total halo leaves less than half an LDS chunk of tile even at the largest
+ * work size runs in several passes: its steps in consecutive groups, group g in the (g+1)-th launch,
+ * the intermediate signal in a buffer the plan holds (its samples x npol complex values).  The plan
+ * owns its device tables and that buffer (allocated by ldbp_batch_plan_create, freed by
  * ldbp_batch_plan_destroy); the forward calls allocate nothing.
  * -------------------------------------------------------------------------*/
 typedef struct ldbp_batch_plan ldbp_batch_plan;

@@ -6,7 +6,9 @@
 // writes the L_b samples whose dependency cone it loaded (eq. model, Sec. III-B).  Work items
 // (waveform, tile) are therefore independent: one launch covers the whole batch, items are
 // ordered by decreasing cost so the hardware dispatcher balances the tail, and the launch can be
-// captured once into a hipGraph and replayed.  Per-waveform and per-step tables live in device
+// captured once into a hipGraph and replayed.  A waveform whose halo does not leave a useful tile
+// in the largest LDS work size runs its steps in groups, one further launch per group.
+// Per-waveform and per-step tables (and the intermediate signal of such waveforms) live in device
 // memory owned by the plan (allocated once when the plan is created).
 #include <algorithm>
 #include <numeric>
@@ -18,14 +20,18 @@
 
 namespace ldbp {
 
+// One pass over one waveform: all of its steps, or (a waveform whose halo leaves no tile in the LDS work
+// size) one group of consecutive steps, reading the previous group's output.
 struct BatchWave {
   int64_t off;       // first time sample of the waveform in the packed arrays
+  int64_t toff;      // first time sample of the waveform in the plan's intermediate buffer
   int32_t n;         // samples
-  int32_t nstep;     // l_b
+  int32_t nstep;     // steps of this pass
   int32_t step0;     // first entry in the step table
-  int32_t halo;      // H_b
+  int32_t halo;      // H_b: sum of K over the pass's steps
   int32_t tile_len;  // L_b
   int32_t wrap;      // 1 when H_b >= n_b
+  int32_t src, dst;  // 0: x, 1: y, 2: the intermediate buffer
 };
 
 struct BatchStep {
@@ -41,8 +47,7 @@ struct BatchItem {
 };
 
 template <typename R, int NPOL, int RB, int THREADS>
-__global__ __launch_bounds__(THREADS) void ldbp_fwd_batch_kernel(const cx_t<R>* __restrict__ x,
-                                                                 cx_t<R>* __restrict__ y,
+__global__ __launch_bounds__(THREADS) void ldbp_fwd_batch_kernel(const cx_t<R>* x, cx_t<R>* y, cx_t<R>* tmp,
                                                                  const BatchWave* __restrict__ waves,
                                                                  const BatchStep* __restrict__ steps,
                                                                  const BatchItem* __restrict__ items, int32_t work,
@@ -58,8 +63,9 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_batch_kernel(const cx_t<R>* 
   const int Lw = min(w.tile_len, w.n - t0);
   const int H = w.halo;
   const int W0 = Lw + 2 * H;
-  const V* xw = x + w.off * NPOL;
-  V* yw = y + w.off * NPOL;
+  const V* xw = (w.src == 0 ? x : w.src == 1 ? static_cast<const V*>(y) : static_cast<const V*>(tmp)) +
+                (w.src == 2 ? w.toff : w.off) * NPOL;
+  V* yw = (w.dst == 1 ? y : tmp) + (w.dst == 2 ? w.toff : w.off) * NPOL;
   load_tile<R, NPOL, THREADS>(xw, b0, w.n, t0, H, W0, w.wrap);
   __syncthreads();
   int lo = 0;
@@ -84,9 +90,11 @@ struct ldbp_batch_plan {
   int32_t dtype, npol, nwave, rb, chunks, work, sym;
   int64_t total_samples, total_sample_steps, total_taps, total_steps;
   int32_t nitems;
+  std::vector<int32_t> level_items;   // items of launch g: [level_items[g], level_items[g + 1])
   ldbp::BatchWave* d_waves = nullptr;
   ldbp::BatchStep* d_steps = nullptr;
   ldbp::BatchItem* d_items = nullptr;
+  void* d_tmp = nullptr;              // intermediate signal of the waveforms run in several passes
   int device = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -107,10 +115,17 @@ static int launch_batch_t(const ldbp_batch_plan* P, const void* taps, const void
   if (lds > 65536)
     LDBP_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(P->nitems)), dim3(THREADS), lds, s,
-                     static_cast<const cx_t<R>*>(x), static_cast<cx_t<R>*>(y), P->d_waves, P->d_steps, P->d_items,
-                     P->work, static_cast<const cx_t<R>*>(taps), static_cast<const R*>(c), P->sym);
-  LDBP_HIP_CHECK(hipGetLastError());
+  // one launch per pass level: waveforms run in several passes have their later step groups in later
+  // launches (each reads what the previous launch wrote)
+  for (size_t g = 0; g + 1 < P->level_items.size(); ++g) {
+    const int32_t i0 = P->level_items[g], i1 = P->level_items[g + 1];
+    if (i1 <= i0) continue;
+    hipLaunchKernelGGL(kern, dim3(static_cast<uint32_t>(i1 - i0)), dim3(THREADS), lds, s,
+                       static_cast<const cx_t<R>*>(x), static_cast<cx_t<R>*>(y), static_cast<cx_t<R>*>(P->d_tmp),
+                       P->d_waves, P->d_steps, P->d_items + i0, P->work, static_cast<const cx_t<R>*>(taps),
+                       static_cast<const R*>(c), P->sym);
+    LDBP_HIP_CHECK(hipGetLastError());
+  }
   return LDBP_OK;
 }
 
@@ -136,6 +151,7 @@ static void free_plan(ldbp_batch_plan* P) {
   if (P->d_waves) (void)hipFree(P->d_waves);
   if (P->d_steps) (void)hipFree(P->d_steps);
   if (P->d_items) (void)hipFree(P->d_items);
+  if (P->d_tmp) (void)hipFree(P->d_tmp);
   delete P;
 }
 
@@ -154,14 +170,19 @@ extern "C" int ldbp_batch_plan_create(int32_t dtype, int32_t npol, int32_t nwave
   const int rb = (plan && plan->outputs_per_thread > 0) ? plan->outputs_per_thread : fwd_rb_default(dtype, npol);
   if (!fwd_rb_supported(dtype, npol, rb)) return fail(LDBP_EUNSUPPORTED, "outputs_per_thread %d not available", rb);
   const int chunk = fwd_chunk(dtype, npol, rb);
-  std::vector<BatchWave> waves(nwave);
+  // per waveform: its steps (the step table) and total halo
+  struct WaveIn {
+    int64_t off;
+    int32_t n, nstep, step0, halo;
+  };
+  std::vector<WaveIn> win(nwave);
   std::vector<BatchStep> steps;
   int64_t off = 0, tapoff = 0, cidx = 0, ss = 0;
   int maxh = 0;
   for (int b = 0; b < nwave; ++b) {
     if (wave_len[b] < 1 || wave_len[b] > (int64_t(1) << 30)) return fail(LDBP_EINVAL, "wave_len[%d] invalid", b);
     if (wave_nstep[b] < 1) return fail(LDBP_EINVAL, "wave_nstep[%d] < 1", b);
-    BatchWave& w = waves[b];
+    WaveIn& w = win[b];
     w.off = off;
     w.n = static_cast<int32_t>(wave_len[b]);
     w.nstep = wave_nstep[b];
@@ -176,36 +197,89 @@ extern "C" int ldbp_batch_plan_create(int32_t dtype, int32_t npol, int32_t nwave
       ++cidx;
     }
     w.halo = h;
-    w.wrap = h >= w.n ? 1 : 0;
     maxh = std::max(maxh, h);
     off += w.n;
     ss += static_cast<int64_t>(w.n) * w.nstep;
   }
-  // LDS work size: enough chunks that the longest halo leaves at least half a chunk of tile
+  // LDS work size: enough chunks that the longest halo leaves at least half a chunk of tile, within
+  // the largest allocation
   int chunks = (plan && plan->chunks > 0) ? plan->chunks : 1;
   while (chunks * chunk - 2 * maxh < chunk / 2 && fwd_lds_bytes(dtype, npol, rb, chunks + 1) <= 160 * 1024) ++chunks;
-  if (fwd_lds_bytes(dtype, npol, rb, chunks) > 160 * 1024 || chunks * chunk - 2 * maxh < 1)
-    return fail(LDBP_EUNSUPPORTED, "a waveform's total halo (%d samples) does not fit in LDS", maxh);
+  if (fwd_lds_bytes(dtype, npol, rb, chunks) > 160 * 1024)
+    return fail(LDBP_EUNSUPPORTED, "%d LDS chunks exceed the workgroup's LDS", chunks);
   const int work = chunks * chunk;
-  std::vector<BatchItem> items;
-  std::vector<double> cost;
+  // A waveform whose halo still leaves less than half a chunk of tile runs in several passes: its steps
+  // in consecutive groups of halo at most hseg, each group a launch after the previous one, the
+  // intermediate signal alternating between y and the plan's buffer so that the last group writes y.
+  const int hseg = (work - chunk / 2) / 2;
+  std::vector<BatchWave> waves;
+  std::vector<int32_t> level;   // pass index of each entry within its waveform
+  int64_t toff = 0;
+  int nlev = 1;
   for (int b = 0; b < nwave; ++b) {
-    BatchWave& w = waves[b];
-    w.tile_len = work - 2 * w.halo;
-    const int nt = (w.n + w.tile_len - 1) / w.tile_len;
-    double per_step = 0;
-    for (int s = 0; s < w.nstep; ++s) per_step += 2 * steps[w.step0 + s].K + 1 + 8;
-    for (int t = 0; t < nt; ++t) {
-      items.push_back(BatchItem{b, t});
-      cost.push_back(per_step * (work));
+    const WaveIn& w = win[b];
+    std::vector<std::pair<int32_t, int32_t>> groups;   // (first step, steps)
+    if (w.halo <= hseg) {
+      groups.emplace_back(0, w.nstep);
+    } else {
+      int s0 = 0, h = 0;
+      for (int s = 0; s < w.nstep; ++s) {
+        const int K = steps[w.step0 + s].K;
+        if (h + K > hseg && s > s0) {
+          groups.emplace_back(s0, s - s0);
+          s0 = s;
+          h = 0;
+        }
+        h += K;
+      }
+      groups.emplace_back(s0, w.nstep - s0);
     }
+    const int G = static_cast<int>(groups.size());
+    nlev = std::max(nlev, G);
+    for (int g = 0; g < G; ++g) {
+      BatchWave e{};
+      e.off = w.off;
+      e.toff = toff;
+      e.n = w.n;
+      e.step0 = w.step0 + groups[g].first;
+      e.nstep = groups[g].second;
+      int h = 0;
+      for (int s = 0; s < e.nstep; ++s) h += steps[e.step0 + s].K;
+      e.halo = h;
+      e.wrap = h >= w.n ? 1 : 0;
+      e.tile_len = work - 2 * h;
+      if (e.tile_len < 1) return fail(LDBP_EUNSUPPORTED, "a pass's halo (%d samples) does not fit in LDS", h);
+      const int out_buf = ((G - 1 - g) % 2 == 0) ? 1 : 2;
+      e.dst = out_buf;
+      e.src = g == 0 ? 0 : (((G - g) % 2 == 0) ? 1 : 2);
+      waves.push_back(e);
+      level.push_back(g);
+    }
+    if (G > 1) toff += w.n;
   }
-  std::vector<size_t> order(items.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-  std::vector<BatchItem> sorted(items.size());
-  for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
-  if (sorted.size() > 0x7fffffffu) return fail(LDBP_EUNSUPPORTED, "too many work items");
+  std::vector<BatchItem> sorted;
+  std::vector<int32_t> level_items(1, 0);
+  for (int g = 0; g < nlev; ++g) {
+    std::vector<BatchItem> items;
+    std::vector<double> cost;
+    for (size_t e = 0; e < waves.size(); ++e) {
+      if (level[e] != g) continue;
+      const BatchWave& w = waves[e];
+      const int nt = (w.n + w.tile_len - 1) / w.tile_len;
+      double per_step = 0;
+      for (int s = 0; s < w.nstep; ++s) per_step += 2 * steps[w.step0 + s].K + 1 + 8;
+      for (int t = 0; t < nt; ++t) {
+        items.push_back(BatchItem{static_cast<int32_t>(e), t});
+        cost.push_back(per_step * work);
+      }
+    }
+    std::vector<size_t> order(items.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    for (size_t i = 0; i < order.size(); ++i) sorted.push_back(items[order[i]]);
+    if (sorted.size() > 0x7fffffffu) return fail(LDBP_EUNSUPPORTED, "too many work items");
+    level_items.push_back(static_cast<int32_t>(sorted.size()));
+  }
 
   auto* P = new ldbp_batch_plan();
   P->dtype = dtype;
@@ -220,7 +294,10 @@ extern "C" int ldbp_batch_plan_create(int32_t dtype, int32_t npol, int32_t nwave
   P->total_taps = tapoff;
   P->total_steps = cidx;
   P->nitems = static_cast<int32_t>(sorted.size());
+  P->level_items = level_items;
   hipError_t e = hipGetDevice(&P->device);
+  if (e == hipSuccess && toff > 0)
+    e = hipMalloc(&P->d_tmp, static_cast<size_t>(toff) * npol * cx_size(dtype));
   if (e == hipSuccess) e = hipMalloc(&P->d_waves, waves.size() * sizeof(BatchWave));
   if (e == hipSuccess) e = hipMalloc(&P->d_steps, std::max<size_t>(steps.size(), 1) * sizeof(BatchStep));
   if (e == hipSuccess) e = hipMalloc(&P->d_items, sorted.size() * sizeof(BatchItem));

@@ -116,10 +116,13 @@ def test_batch_plan_rejects_bad_tables_before_any_gpu_work():
     assert lib.ldbp_batch_plan_create(0, 3, 2, lens, ns, N.i32_array([3, 5, 5]), None, ctypes.byref(h)) == N.LDBP_EUNSUPPORTED
     bad = (ctypes.c_int64 * 2)(100, 0)
     assert lib.ldbp_batch_plan_create(0, 1, 2, bad, ns, N.i32_array([3, 5, 5]), None, ctypes.byref(h)) == N.LDBP_EINVAL
-    # total halo larger than any LDS work size
-    assert lib.ldbp_batch_plan_create(0, 1, 1, lens, N.i32_array([200]), N.i32_array([63] * 200), None,
-                                      ctypes.byref(h)) == N.LDBP_EUNSUPPORTED
     assert h.value in (None, 0)
+    # total halo larger than any LDS work size: planned as several passes (the tables are valid; without
+    # a GPU the device allocation fails)
+    st = lib.ldbp_batch_plan_create(0, 1, 1, lens, N.i32_array([200]), N.i32_array([63] * 200), None, ctypes.byref(h))
+    assert st in (N.LDBP_OK, N.LDBP_EHIP)
+    if st == N.LDBP_OK:
+        lib.ldbp_batch_plan_destroy(h)
     assert lib.ldbp_batch_forward(None, 16, 16, 16, 32, None) == N.LDBP_EINVAL
 
 

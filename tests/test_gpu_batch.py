@@ -68,6 +68,48 @@ def test_batch_matches_oracle_and_per_waveform_forward(npol, dtype, tol):
         np.testing.assert_array_equal(yb, ys)
 
 
+@pytest.mark.parametrize("npol", [1, 2])
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, 1e-4), (torch.complex128, 1e-10)])
+def test_batch_long_halo_runs_in_several_passes(npol, dtype, tol):
+    """A waveform whose total halo (150 steps of 63 taps: 4,650 samples a side) leaves no tile in the
+    largest LDS work size runs its steps in groups, one launch per group, beside waveforms that run in
+    one pass; each output against the oracle, and the graph replay of the several launches.  The long
+    model is the least-squares LDBP of 30 x 100 km at 5 steps per span with 63 taps, each filter
+    scaled to unit peak gain (a bounded cascade), on a white input at 0 dBm."""
+    print("case: batch several passes", npol, dtype, flush=True)
+    g = synth.rng(31, 3)
+    lengths = [8000, 3001, 257]
+    nsteps = [150, 7, 3]
+    models, waves = [], []
+    for i, (n, L) in enumerate(zip(lengths, nsteps)):
+        if i == 0:
+            tp, c = W.ldbp_init(30, 5, 63, kerr_scale=8.0 / 9.0 if npol == 2 else 1.0)
+            tp = [W.unit_peak_gain(h) for h in tp]
+            amp = math.sqrt(1e-3)
+        else:
+            Ts = [int(t) for t in g.choice([3, 5, 9, 15], size=L)]
+            tp = synth.random_taps(3100 + i, Ts)
+            tp = [h / np.linalg.norm(h) for h in tp]
+            c = synth.random_real(3200 + i, L, -0.3, 0.3)
+            amp = 0.5
+        models.append((tp, np.asarray(c, np.float64)))
+        shape = (n,) if npol == 1 else (n, 2)
+        waves.append(synth.complex_normal(3300 + i, shape) * amp)
+    plan = B.BatchPlan(lengths, nsteps, [len(h) for tp, _ in models for h in tp], dtype=dtype, npol=npol)
+    taps, c, x = _pack(models, waves, dtype)
+    y = plan.forward(taps, c, x)
+    yg = torch.empty_like(x)
+    for _ in range(2):
+        yg.zero_()
+        plan.forward(taps, c, x, y=yg, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(yg, y)
+    y = y.cpu().numpy()
+    off = np.cumsum([0] + lengths)
+    for b, (tp, cc) in enumerate(models):
+        assert _rel(y[off[b]:off[b + 1]], O.ldbp_forward(waves[b], tp, cc, npol=npol)) <= tol, b
+
+
 def test_batch_graph_replays():
     print("case: batch graph", flush=True)
     lengths, models, waves = _mixed(6)
