@@ -842,38 +842,42 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
                               "note": "the paper's values (Sec. V-A, Fig. results_Ip2008), context only"}}
 
 
-def e8_reduced(torch, dev, iters: int, powers):
-    """The paper's 32 GBd scenario (Sec. V-F) at reduced training length: 10 x 100 km, LDBP on the
-    symmetric split-step with log step sizes, 2 steps per span (l = 21, 23 taps per filter: an overall
-    impulse response of 21 * 22 + 1 = 463 taps) trained at P = {3, 4, 5} dBm, and 4 steps per span
-    (l = 41, 13 taps: 493) at {4, 5, 6} dBm; Gaussian symbols, no pruning, Adam lr 1e-3 on the filters
-    and the Kerr coefficients (the last step stays linear).  Channel at 4 samples per symbol (the paper:
-    6) with 100 steps per span and amplifier noise.  Effective SNR per power on held-out batches, with
-    FFT-DBP at the same number of steps per span (and 10) for reference."""
+def e8_reduced(torch, dev, iters: int, powers, rho_a: int = 4, data_pool: int = 0, eval_batches: int = 4):
+    """The paper's 32 GBd scenario (Sec. V-F): 10 x 100 km, LDBP on the symmetric split-step with log
+    step sizes, 2 steps per span (l = 21, 23 taps per filter: an overall impulse response of
+    21 * 22 + 1 = 463 taps) trained at P = {3, 4, 5} dBm, and 4 steps per span (l = 41, 13 taps: 493)
+    at {4, 5, 6} dBm; Gaussian symbols, no pruning, Adam lr 1e-3 on the filters and the Kerr
+    coefficients (the last step stays linear).  Channel at rho_a samples per symbol (the paper: 6) with
+    100 steps per span and amplifier noise; data_pool > 0: training cycles through that many simulated
+    batches.  Effective SNR per power on eval_batches held-out batches of 32 x 8,192 symbols, with
+    FFT-DBP at the same number of steps per span (and 10) for reference, on the same waveforms."""
     from paper_2010_14258_amd import train as TRN
 
     out = {}
     for stps, ntaps, ptrain in ((2, 23, (3.0, 4.0, 5.0)), (4, 13, (4.0, 5.0, 6.0))):
-        cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=4, rho_d=2, rs=32e9, nspan=10, span_km=100.0,
+        cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=rho_a, rho_d=2, rs=32e9, nspan=10, span_km=100.0,
                               channel_steps=100, ldbp_steps=stps, t_init=ntaps, t_final=ntaps, iters=iters,
-                              powers_dbm=ptrain, symbols="gauss", ssm="symmetric", seed=1301 + stps)
+                              powers_dbm=ptrain, symbols="gauss", ssm="symmetric", seed=1301 + stps,
+                              data_pool=data_pool)
         trn = TRN.Trainer(cfg, device=dev)
-        init = {p_: trn.evaluate(nbatch=4, p_dbm=p_) for p_ in powers}
+        nb = eval_batches
+        init = {p_: trn.evaluate(nbatch=nb, p_dbm=p_) for p_ in powers}
         t0 = time.perf_counter()
         curve = []
         while trn.it < iters:
-            loss = trn.step(sync=(trn.it + 1) % 500 == 0)
-            if trn.it % 500 == 0:
+            every = 500 if iters <= 20000 else 5000
+            loss = trn.step(sync=(trn.it + 1) % every == 0)
+            if trn.it % every == 0:
                 curve.append([trn.it, loss])
                 print(f"e8 {stps} StPS {trn.it}/{iters} loss {loss:.4e} {time.perf_counter() - t0:.0f} s",
                       file=sys.stderr, flush=True)
         train_s = time.perf_counter() - t0
         rows = []
         for p_ in powers:
-            row = {"launch_dbm": p_, "ldbp_trained_snr_db": trn.evaluate(nbatch=4, p_dbm=p_),
+            row = {"launch_dbm": p_, "ldbp_trained_snr_db": trn.evaluate(nbatch=nb, p_dbm=p_),
                    "ldbp_ls_init_snr_db": init[p_],
-                   "fft_dbp_same_stps_snr_db": trn.evaluate_fft_dbp(stps, nbatch=4, p_dbm=p_),
-                   "fft_dbp_10stps_snr_db": trn.evaluate_fft_dbp(10, nbatch=4, p_dbm=p_)}
+                   "fft_dbp_same_stps_snr_db": trn.evaluate_fft_dbp(stps, nbatch=nb, p_dbm=p_),
+                   "fft_dbp_10stps_snr_db": trn.evaluate_fft_dbp(10, nbatch=nb, p_dbm=p_)}
             rows.append(row)
             print(json.dumps(row), file=sys.stderr, flush=True)
         peak = {k: max(r[k] for r in rows) for k in rows[0] if k.endswith("_snr_db")}
@@ -885,7 +889,8 @@ def e8_reduced(torch, dev, iters: int, powers):
                                - peak["fft_dbp_same_stps_snr_db"]}
         del trn
     return {"workload": "32 GBd, 10 x 100 km SSMF, Gaussian symbols, symmetric-SSM LDBP, 2 and 4 steps per span",
-            "train_iterations": iters, "models": out,
+            "train_iterations": iters, "rho_a": rho_a, "data_pool": data_pool,
+            "symbols_per_snr": eval_batches * 32 * 8192, "models": out,
             "paper_context": {"gain_over_dbp_db": {"2_stps": 2.1, "4_stps": 0.6}, "taps": 463,
                               "note": "the paper's values (Sec. V-F), after 150,000 + 1,500 iterations; context only"}}
 
@@ -1084,8 +1089,8 @@ def main():
                                          [float(v) for v in args.powers.split(",")])), flush=True)
         return
     if args.mode == "e8":
-        print(json.dumps(e8_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")])),
-              flush=True)
+        print(json.dumps(e8_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
+                                    args.rho_a, args.data_pool, args.eval_batches)), flush=True)
         return
     if args.mode == "init":
         print(json.dumps(init_schemes(torch, dev, args.train_iters, schemes=args.schemes.split(","),
