@@ -41,18 +41,73 @@ __device__ constexpr double kC5_1 = 0.30901699437494742410, kC5_2 = -0.809016994
 __device__ constexpr double kS5_1 = 0.95105651629515357212, kS5_2 = 0.58778525229247312917;
 __device__ constexpr double kS3 = 0.86602540378443864676;
 
+// cos and sin of 2 pi m / R, m < R, for the composite radices 6, 9, 10, 12 and 15
+__device__ constexpr double kCos6[6] = {1.0, 5.0e-1, -5.0e-1, -1.0, -5.0e-1, 5.0e-1};
+__device__ constexpr double kSin6[6] = {0.0, 8.66025403784438646764e-1, 8.66025403784438646764e-1, 0.0, -8.66025403784438646764e-1, -8.66025403784438646764e-1};
+__device__ constexpr double kCos9[9] = {1.0, 7.66044443118978035202e-1, 1.73648177666930348852e-1, -5.0e-1, -9.39692620785908384054e-1, -9.39692620785908384054e-1, -5.0e-1, 1.73648177666930348852e-1, 7.66044443118978035202e-1};
+__device__ constexpr double kSin9[9] = {0.0, 6.42787609686539326323e-1, 9.84807753012208059367e-1, 8.66025403784438646764e-1, 3.42020143325668733044e-1, -3.42020143325668733044e-1, -8.66025403784438646764e-1, -9.84807753012208059367e-1, -6.42787609686539326323e-1};
+__device__ constexpr double kCos10[10] = {1.0, 8.09016994374947424102e-1, 3.09016994374947424102e-1, -3.09016994374947424102e-1, -8.09016994374947424102e-1, -1.0, -8.09016994374947424102e-1, -3.09016994374947424102e-1, 3.09016994374947424102e-1, 8.09016994374947424102e-1};
+__device__ constexpr double kSin10[10] = {0.0, 5.87785252292473129169e-1, 9.51056516295153572116e-1, 9.51056516295153572116e-1, 5.87785252292473129169e-1, 0.0, -5.87785252292473129169e-1, -9.51056516295153572116e-1, -9.51056516295153572116e-1, -5.87785252292473129169e-1};
+__device__ constexpr double kCos12[12] = {1.0, 8.66025403784438646764e-1, 5.0e-1, 0.0, -5.0e-1, -8.66025403784438646764e-1, -1.0, -8.66025403784438646764e-1, -5.0e-1, 0.0, 5.0e-1, 8.66025403784438646764e-1};
+__device__ constexpr double kSin12[12] = {0.0, 5.0e-1, 8.66025403784438646764e-1, 1.0, 8.66025403784438646764e-1, 5.0e-1, 0.0, -5.0e-1, -8.66025403784438646764e-1, -1.0, -8.66025403784438646764e-1, -5.0e-1};
+__device__ constexpr double kCos15[15] = {1.0, 9.13545457642600895502e-1, 6.69130606358858213826e-1, 3.09016994374947424102e-1, -1.045284632676534714e-1, -5.0e-1, -8.09016994374947424102e-1, -9.78147600733805637929e-1, -9.78147600733805637929e-1, -8.09016994374947424102e-1, -5.0e-1, -1.045284632676534714e-1, 3.09016994374947424102e-1, 6.69130606358858213826e-1, 9.13545457642600895502e-1};
+__device__ constexpr double kSin15[15] = {0.0, 4.06736643075800207754e-1, 7.43144825477394235015e-1, 9.51056516295153572116e-1, 9.94521895368273336923e-1, 8.66025403784438646764e-1, 5.87785252292473129169e-1, 2.07911690817759337102e-1, -2.07911690817759337102e-1, -5.87785252292473129169e-1, -8.66025403784438646764e-1, -9.94521895368273336923e-1, -9.51056516295153572116e-1, -7.43144825477394235015e-1, -4.06736643075800207754e-1};
+
+template <typename R, int RAD, int DIR>
+__device__ __forceinline__ cx_t<R> root_of_unity(int m) {
+  // W_RAD^m = exp(-2 pi i DIR m / RAD)
+  double c, s;
+  if constexpr (RAD == 6) { c = kCos6[m]; s = kSin6[m]; }
+  else if constexpr (RAD == 9) { c = kCos9[m]; s = kSin9[m]; }
+  else if constexpr (RAD == 10) { c = kCos10[m]; s = kSin10[m]; }
+  else if constexpr (RAD == 12) { c = kCos12[m]; s = kSin12[m]; }
+  else { c = kCos15[m]; s = kSin15[m]; }
+  return cx_t<R>{static_cast<R>(c), static_cast<R>(DIR > 0 ? -s : s)};
+}
+
 // (x + i y) times -i DIR: DIR (y - i x)
 template <typename V, int DIR>
 __device__ __forceinline__ V mul_mi(V a) {
   return DIR > 0 ? V{a.y, -a.x} : V{-a.y, a.x};
 }
 
-// In-register DFT of RAD points (RAD = 2, 3, 4, 5, 8, 16), natural order in and out.
+// In-register DFT of RAD points (RAD = 2, 3, 4, 5, 6, 8, 9, 10, 12, 15, 16), natural order in and out.
 // X_k = sum_r v_r W_RAD^{r k} with W = exp(-2 pi i DIR / RAD).
 template <typename R, int RAD, int DIR>
 __device__ __forceinline__ void dft_reg(cx_t<R>* v) {
   using V = cx_t<R>;
-  if constexpr (RAD == 3) {
+  if constexpr (RAD == 6 || RAD == 9 || RAD == 10 || RAD == 12 || RAD == 15) {
+    // RAD = A B: with r = a + A b and k = kb + B ka, X_k = sum_a W_A^{a ka} W_RAD^{a kb} sum_b v_{a+Ab} W_B^{b kb}
+    // (B-point DFTs, twiddles, then A-point DFTs)
+    constexpr int A = (RAD == 6 || RAD == 10) ? 2 : 3;
+    constexpr int B = RAD / A;
+    V t[RAD];
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      V u[B];
+#pragma unroll
+      for (int b = 0; b < B; ++b) u[b] = v[a + A * b];
+      dft_reg<R, B, DIR>(u);
+#pragma unroll
+      for (int kb = 0; kb < B; ++kb) {
+        if (a == 0 || kb == 0) {
+          t[a + A * kb] = u[kb];
+        } else {
+          const V w = root_of_unity<R, RAD, DIR>(a * kb);
+          t[a + A * kb] = V{u[kb].x * w.x - u[kb].y * w.y, u[kb].x * w.y + u[kb].y * w.x};
+        }
+      }
+    }
+#pragma unroll
+    for (int kb = 0; kb < B; ++kb) {
+      V w2[A];
+#pragma unroll
+      for (int a = 0; a < A; ++a) w2[a] = t[a + A * kb];
+      dft_reg<R, A, DIR>(w2);
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) v[kb + B * ka] = w2[ka];
+    }
+  } else if constexpr (RAD == 3) {
     // X0 = a + (b + c); X1,2 = a - (b + c)/2 -+ i DIR sin(2 pi/3) (b - c)
     const V a = v[0], b = v[1], c = v[2];
     const V t1{b.x + c.x, b.y + c.y};
@@ -165,11 +220,31 @@ __host__ __device__ inline uint64_t fft_radix_plan(int len, bool r16 = true) {
   return plan;
 }
 
+// The stage radices of a length 2^a 3^b 5^c with composite radices, fewer stages (each an LDS round
+// trip): the largest of 15, 12, 10, 9, 8, 6, 5, 4, 3, 2 that divides the remaining length, four bits
+// per stage from the low end (the radix itself; 0 ends the plan).
+__host__ __device__ inline uint64_t fft_radix_plan_composite(int len) {
+  constexpr int kRad[] = {15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+  uint64_t plan = 0;
+  int sh = 0, rem = len;
+  while (rem > 1 && sh < 64) {
+    int r = 0;
+    for (int i = 0; i < 10 && r == 0; ++i)
+      if (rem % kRad[i] == 0) r = kRad[i];
+    if (r == 0) break;
+    plan |= static_cast<uint64_t>(r) << sh;
+    sh += 4;
+    rem /= r;
+  }
+  return plan;
+}
+
 // Full transform of `width` (a power of two) interleaved length-len sequences held in A, with the
-// stages of `plan` (fft_radix_plan(len, R16)); B is scratch of the same size.  Returns the buffer
-// holding the result.  Ends with a barrier.  Without R16 the radix-16 stage is not compiled in (fewer
-// registers for kernels whose lengths are mostly odd).
-template <typename R, int DIR, int THREADS, bool R16 = true>
+// stages of `plan` (fft_radix_plan(len, R16), or fft_radix_plan_composite(len) with COMP); B is scratch
+// of the same size.  Returns the buffer holding the result.  Ends with a barrier.  Without R16 the
+// radix-16 stage is not compiled in (fewer registers for kernels whose lengths are mostly odd); COMP
+// compiles in the composite radices 6, 9, 10, 12 and 15.
+template <typename R, int DIR, int THREADS, bool R16 = true, bool COMP = false>
 __device__ cx_t<R>* lds_fft_plan(cx_t<R>* A, cx_t<R>* B, int len, int width, const cx_t<R>* __restrict__ tw,
                                  uint64_t plan) {
   using V = cx_t<R>;
@@ -191,6 +266,21 @@ __device__ cx_t<R>* lds_fft_plan(cx_t<R>* A, cx_t<R>* B, int len, int width, con
       case 4: fft_stage<R, 4, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 4; rem /= 4; break;
       case 2: fft_stage<R, 2, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 2; rem /= 2; break;
       case 3: fft_stage<R, 3, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 3; rem /= 3; break;
+      case 6:
+        if constexpr (COMP) { fft_stage<R, 6, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 6; rem /= 6; }
+        break;
+      case 9:
+        if constexpr (COMP) { fft_stage<R, 9, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 9; rem /= 9; }
+        break;
+      case 10:
+        if constexpr (COMP) { fft_stage<R, 10, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 10; rem /= 10; }
+        break;
+      case 12:
+        if constexpr (COMP) { fft_stage<R, 12, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 12; rem /= 12; }
+        break;
+      case 15:
+        if constexpr (COMP) { fft_stage<R, 15, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 15; rem /= 15; }
+        break;
       default: fft_stage<R, 5, DIR, THREADS>(in, out, len, width, wlog, Ns, rem, inv, tw); Ns *= 5; rem /= 5; break;
     }
     __syncthreads();

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_col(const cx_t<R>* src, c
   V* cur = A;
   V* oth = B;
   if (do_ifft) {
-    cur = lds_fft_plan<R, -1, kVarThreads, false>(A, B, N2, width, tw, w.plan2);
+    cur = lds_fft_plan<R, -1, kVarThreads, false, true>(A, B, N2, width, tw, w.plan2);
     oth = (cur == A) ? B : A;
   }
   // pointwise operation on every time sample (t2, t1) of the tile, all polarisations together
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_col(const cx_t<R>* src, c
     }
   }
   __syncthreads();
-  if (do_fft) cur = lds_fft_plan<R, 1, kVarThreads, false>(cur, oth, N2, width, tw, w.plan2);
+  if (do_fft) cur = lds_fft_plan<R, 1, kVarThreads, false, true>(cur, oth, N2, width, tw, w.plan2);
   for (int e = threadIdx.x; e < tot; e += kVarThreads) {
     const int f2 = e >> wlog, q = e & (width - 1);
     if (c0 + (q >> plog) >= N1) continue;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_row(cx_t<R>* data, VarArg
       A[(e >> plog) * width + r * np + (e & plog)] = r < rows ? row0[static_cast<int64_t>(r) * rowlen + e] : V{0, 0};
   }
   __syncthreads();
-  V* F = lds_fft_plan<R, 1, kVarThreads, false>(A, B, N1, width, tw, w.plan1);
+  V* F = lds_fft_plan<R, 1, kVarThreads, false, true>(A, B, N1, width, tw, w.plan1);
   V* oth = (F == A) ? B : A;
   const double n = static_cast<double>(w.n);
   const double zrev = z * a.beta2 * M_PI * a.fs * a.fs / (n * n);
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kVarThreads) void ssm_var_row(cx_t<R>* data, VarArg
     F[e] = cmul(F[e], lin_response<R>(k, w.n, zrev, amp));
   }
   __syncthreads();
-  V* T = lds_fft_plan<R, -1, kVarThreads, false>(F, oth, N1, width, tw, w.plan1);
+  V* T = lds_fft_plan<R, -1, kVarThreads, false, true>(F, oth, N1, width, tw, w.plan1);
   for (int r = 0; r < rows; ++r) {
     for (int e = threadIdx.x; e < rowlen; e += kVarThreads)
       row0[static_cast<int64_t>(r) * rowlen + e] = T[(e >> plog) * width + r * np + (e & plog)];
@@ -241,8 +241,8 @@ int var_geometry(int dtype, int npol, int64_t n, VarWave& w, size_t* lds_bytes) 
   w.ctiles = static_cast<int32_t>((N1 + w.C - 1) / w.C);
   w.rtiles = static_cast<int32_t>((N2 + w.RW - 1) / w.RW);
   w.lo_log = (ceil_log2(n) + 1) / 2;
-  w.plan1 = fft_radix_plan(static_cast<int>(N1), false);
-  w.plan2 = fft_radix_plan(static_cast<int>(N2), false);
+  w.plan1 = fft_radix_plan_composite(static_cast<int>(N1));
+  w.plan2 = fft_radix_plan_composite(static_cast<int>(N2));
   const size_t lds = (2 * std::max<size_t>(static_cast<size_t>(N2) * w.C, static_cast<size_t>(N1) * w.RW) * npol +
                       static_cast<size_t>(std::max(N1, N2))) * cx_size(dtype);
   if (lds > kVarMaxLds)
