@@ -473,7 +473,7 @@ def manakov(torch, dev, reps: int):
     ws = torch.empty(max(L.ldbp_forward_workspace_size(r, ntap, 2, plan=plan), 1), dtype=torch.uint8, device=dev)
     ms = event_time(torch, stream,
                     lambda: L.ldbp_forward(r, taps, c, ntap, npol=2, y=y, plan=plan, ws=ws, stream=stream), reps, 2)
-    S = 3   # the library's default block length for two polarisations
+    S = 2   # the library's default block length
     ck = torch.empty((L.num_checkpoints(ell, S),) + tuple(r.shape), dtype=r.dtype, device=dev)
     z = L.ldbp_forward(r, taps, c, ntap, npol=2)
     s = TX.qam16_symbols(words, dtype=torch.complex64)
@@ -586,7 +586,7 @@ def manakov_trained(torch, dev, iters: int, powers, pool: int = 4, channel_steps
 
     cfg = TRN.TrainConfig(nwave=8, nsym=524288, nspan=32, span_km=80.0, channel_steps=channel_steps,
                           ldbp_steps=2, t_init=5, t_final=5, iters=iters, powers_dbm=tuple(powers), npol=2,
-                          peak_normalise=True, data_pool=pool, ckpt_every=3, seed=501)
+                          peak_normalise=True, data_pool=pool, ckpt_every=2, seed=501)
     trn = TRN.Trainer(cfg, device=dev)
     init = {p_: trn.evaluate(nbatch=1, p_dbm=p_) for p_ in powers}
     dbp = {p_: {k: trn.evaluate_fft_dbp(k, nbatch=1, p_dbm=p_) for k in (1, 2, 4)} for p_ in powers}

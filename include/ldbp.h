@@ -211,8 +211,8 @@ int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
  *                the backward reads the stored outputs in blocks of the default length
  *                instead of recomputing each step (more HBM traffic, fewer instructions)
  *   ckpt_every   block length S (1..LDBP_MAX_STEPS_PER_PASS); 0 = library default
- *                (only with ckpt == NULL: 2 steps for complex64 with one polarisation,
- *                3 otherwise, or nstep if smaller).  Long blocks may not fit in LDS
+ *                (only with ckpt == NULL: 2 steps for complex64, 3 for complex128, or
+ *                nstep if smaller).  Long blocks may not fit in LDS
  *                (LDBP_EUNSUPPORTED).
  *   gy           device [nwave][n][npol] complex: dL/dy
  *   gx           device [nwave][n][npol] complex output dL/dx, or NULL when not needed

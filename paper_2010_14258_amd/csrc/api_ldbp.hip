@@ -665,13 +665,13 @@ struct BwdLayout {
 // Longest block whose stored step outputs the backward kernel loads with its inputs.
 constexpr int kMaxStoredSteps = 3;
 
-// Block length of the backward when the caller gives none.  complex64: 2 steps for one polarisation,
-// 3 for two (forward with checkpoints + backward on 64 x 65,536, l = 50, 15 taps: S = 1-5 took 2.44,
-// 1.98, 2.11, 2.39, 2.55 ms; on 8 x 2^20 x 2, l = 64, 5 taps, with the short-filter kernel variants and
-// the current tile rule: S = 2, 3, 4, 5, 6, 8 took 5.22, 5.32, 5.74, 6.31, 9.08, 11.75 ms, 2 and 3
-// within the spread of repeated runs).
+// Block length of the backward when the caller gives none.  complex64: 2 steps (forward with
+// checkpoints + backward on 64 x 65,536, l = 50, 15 taps: S = 1-5 took 2.44, 1.98, 2.11, 2.39, 2.55 ms;
+// on 8 x 2^20 x 2, l = 64, 5 taps, with the short-filter kernel variants and the current tile rule:
+// S = 2, 3, 4, 5, 6, 8 took 5.22, 5.32, 5.74, 6.31, 9.08, 11.75 ms, and three repeated pairs 5.22-5.26
+// against 5.34-5.35 ms for S = 2 and 3); complex128: 3.
 static int default_bwd_S(const ModelArgs& m) {
-  const int s = m.dtype == LDBP_C64 ? (m.npol == 2 ? 3 : 2) : 3;
+  const int s = m.dtype == LDBP_C64 ? 2 : 3;
   return std::min<int32_t>(m.nstep, s);
 }
 

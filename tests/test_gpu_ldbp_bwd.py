@@ -253,7 +253,7 @@ def test_backward_full_size_32x16384_l50_T25(every):
 def test_backward_stored_outputs_match_recompute(npol):
     """Every step's output stored by the forward (ckpt_every = 1): the backward reads them in blocks of the
     library's default length instead of recomputing, the last step's output (not stored) recomputed in
-    the last block, which here holds two steps (l = 8, blocks of 2 or 3).  Same result as the
+    the last block, which here holds two steps (l = 8, blocks of 2).  Same result as the
     recomputing backward with checkpoints at the block boundaries, and as the oracle."""
     print("case: bwd stored outputs", npol, flush=True)
     Ts = [15, 5, 15, 3, 9, 15, 1, 7]
@@ -262,7 +262,7 @@ def test_backward_stored_outputs_match_recompute(npol):
     shape = (3, 4001) if npol == 1 else (2, 3001, 2)
     x = synth.complex_normal(121, shape) * 0.5
     gy = synth.complex_normal(122, shape)
-    S = 2 if npol == 1 else 3
+    S = 2   # the library's default block length
     stored = _gpu_grad(x, taps, c, gy, npol=npol, dtype=torch.complex64, ckpt_every=1, use_ckpt=True,
                        symmetric=True)
     recomp = _gpu_grad(x, taps, c, gy, npol=npol, dtype=torch.complex64, ckpt_every=S, use_ckpt=True,
