@@ -31,6 +31,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -1014,6 +1015,9 @@ def main():
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"],
                     help="--mode e1: Adam step size; cosine: decay to 1e-4 after the last pruning event")
     ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
+    ap.add_argument("--out-dir", default=None,
+                    help="--mode e1: directory of the trainer checkpoints and learning curve (default: the "
+                         "system temporary directory)")
     ap.add_argument("--schemes", default="least_squares,unit,random",
                     help="--mode init: initialisations (least_squares, unit, random, multiobjective)")
     ap.add_argument("--init-taps", type=int, default=9, help="--mode init: taps per step")
@@ -1074,7 +1078,7 @@ def main():
         return
     if args.mode == "e1":
         out = e1_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
-                         os.path.join(ROOT, "gpurun_out"), args.resume, args.stop_at, not args.fixed_c,
+                         args.out_dir or tempfile.gettempdir(), args.resume, args.stop_at, not args.fixed_c,
                          args.lr_schedule, args.prune_frac, args.rho_a, args.data_pool, args.eval_batches)
         print(json.dumps(out), flush=True)
         return

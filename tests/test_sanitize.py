@@ -4,7 +4,7 @@ Every csrc/*.hip source is compiled for the host alone with the sanitizers (no d
 translation unit's device-code bundle is replaced by an empty one, so nothing can be launched),
 linked into a shared library, and tests/abi_sanitize.c drives the C ABI through it: argument
 validation, workspace sizes, plan queries, backward layouts, batch-plan validation.  The sanitizers
-abort the driver on an out-of-bounds access, a use after free or undefined behaviour.
+abort the test program on an out-of-bounds access, a use after free or undefined behaviour.
 """
 import concurrent.futures as cf
 import glob
