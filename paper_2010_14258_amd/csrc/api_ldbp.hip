@@ -98,23 +98,35 @@ static SideStream* side_stream(hipStream_t caller) {
   return x.s ? &sides.back() : nullptr;
 }
 
-// Runs run(w0, w1, stream) over the waveforms of the batch: with split, waveforms [h, nwave) on the
-// side stream (forked from s, joined back into s) and [0, h) on s, h = ceil(nwave / 2); otherwise all
-// of them on s.  The two halves touch disjoint waveforms, so the kernels of one fill the other's
-// ramp-up and drain at every launch boundary.
+// Runs the launches run(k, w0, w1, stream), k = 0 .. nstep - 1, over the waveforms of the batch: with
+// split, waveforms [h, nwave) on the side stream (forked from s, joined back into s) and [0, h) on s,
+// h = ceil(nwave / 2); otherwise all of them on s.  The two halves touch disjoint waveforms, so the
+// kernels of one fill the other's ramp-up and drain at every launch boundary.  The halves' launches are
+// enqueued alternately (launch k of the first half, then launch k of the second): the second half then
+// starts with the first instead of after the host has enqueued every launch of the first, which for
+// the 32 launches of a two-polarisation backward left it 7 launches behind.
 template <typename F>
-static int over_halves(hipStream_t s, int64_t nwave, bool split, F&& run) {
+static int over_halves(hipStream_t s, int64_t nwave, bool split, size_t nstep, F&& run) {
   SideStream* side = (split && nwave >= 2) ? side_stream(s) : nullptr;
-  if (!side) return run(0, nwave, s);
+  if (!side) {
+    for (size_t k = 0; k < nstep; ++k) {
+      const int st = run(k, int64_t(0), nwave, s);
+      if (st) return st;
+    }
+    return LDBP_OK;
+  }
   const int64_t h = (nwave + 1) / 2;
   LDBP_HIP_CHECK(hipEventRecord(side->fork, s));
   LDBP_HIP_CHECK(hipStreamWaitEvent(side->s, side->fork, 0));
-  int st = run(0, h, s);
-  const int st2 = st ? LDBP_OK : run(h, nwave, side->s);
+  int st = LDBP_OK;
+  for (size_t k = 0; k < nstep && !st; ++k) {
+    st = run(k, int64_t(0), h, s);
+    if (!st) st = run(k, h, nwave, side->s);
+  }
   // join even after a failed launch, so that later work on s stays ordered after everything enqueued
   LDBP_HIP_CHECK(hipEventRecord(side->join, side->s));
   LDBP_HIP_CHECK(hipStreamWaitEvent(s, side->join, 0));
-  return st ? st : st2;
+  return st;
 }
 
 // The split pays when a call has several launches of at least two workgroups per compute unit.
@@ -129,10 +141,22 @@ static int max_chunks(int dtype, int npol, int rb, bool filtered = false) {
   return c;
 }
 
+// Default LDS work size: the most chunks that still let three workgroups share a compute unit's LDS.
+// Larger tiles cut the halo recomputed per output and the passes over HBM, but below three resident
+// workgroups the memory latency is no longer hidden: with 5-tap filters on two polarisations
+// (3 outputs per thread) 2 chunks run the checkpointing forward in 1.12 ms against 1.25 ms for 1 and
+// 1.20 ms for 3; with 15 taps on one polarisation (7 outputs per thread) 1 chunk beats 2 by 20%.
+static int default_chunks(int dtype, int npol, int rb, bool filtered) {
+  int c = 1;
+  while (3 * fwd_lds_bytes(dtype, npol, rb, c + 1, filtered) <= kMaxLdsBytes) ++c;
+  return c;
+}
+
 // Splits the l steps into passes.  With a checkpoint interval the passes are
 // exactly the checkpoint blocks (the backward's unit; the forward groups them, see
 // make_block_plan); otherwise each pass takes steps while twice its halo stays within
-// 1/8 of the LDS work size (or a fixed S from the plan).
+// 1/8 of the LDS work size (or a fixed S from the plan), and the steps are then spread
+// evenly over that many passes (no short last pass paying a full read and write of the signal).
 struct PassPlan {
   std::vector<PassTable> passes;
   int chunks;
@@ -147,7 +171,7 @@ static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* pl
   out.rb = rb;
   out.sym = (plan && (plan->flags & LDBP_PLAN_SYMMETRIC)) ? 1 : 0;
   const int chunk = fwd_chunk(m.dtype, m.npol, rb);
-  int chunks = (plan && plan->chunks > 0) ? plan->chunks : 1;
+  int chunks = (plan && plan->chunks > 0) ? plan->chunks : default_chunks(m.dtype, m.npol, rb, m.filtered());
   const int cmax = max_chunks(m.dtype, m.npol, rb, m.filtered());
   if (chunks > cmax) return fail(LDBP_EINVAL, "plan chunks %d exceeds the LDS limit (%d)", chunks, cmax);
   const int fixed_s = ckpt_every > 0 ? ckpt_every : ((plan && plan->steps_per_pass > 0) ? plan->steps_per_pass : 0);
@@ -162,36 +186,40 @@ static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* pl
     etaoff[i] = eacc;
     eacc += m.nl_ntap ? m.nl_ntap[i] : 1;
   }
-  out.passes.clear();
-  int s = 0;
-  int max_halo = 0;
-  while (s < m.nstep) {
-    PassTable pt{};
-    pt.c0 = s;
-    int h = 0;
-    int cnt = 0;
-    while (s + cnt < m.nstep && cnt < LDBP_MAX_STEPS_PER_PASS) {
-      const int kf = (m.ntap[s + cnt] - 1) / 2;
-      const int k = kf + m.kap(s + cnt);  // halo of the step: FIR half-length plus power-filter half-length
-      if (fixed_s > 0) {
-        if (cnt >= fixed_s) break;
-      } else if (cnt > 0 && 2 * (h + k) * 8 > chunks * chunk) {
-        break;
+  // greedy split, at most `cap` steps per pass
+  auto split = [&](int cap) {
+    out.passes.clear();
+    int s = 0;
+    while (s < m.nstep) {
+      PassTable pt{};
+      pt.c0 = s;
+      int h = 0;
+      int cnt = 0;
+      while (s + cnt < m.nstep && cnt < cap) {
+        const int kf = (m.ntap[s + cnt] - 1) / 2;
+        const int k = kf + m.kap(s + cnt);  // halo of the step: FIR half-length plus power-filter half-length
+        if (fixed_s == 0 && cnt > 0 && 2 * (h + k) * 8 > chunks * chunk) break;
+        pt.K[cnt] = kf;
+        pt.tapoff[cnt] = tapoff[s + cnt];
+        pt.kap[cnt] = m.kap(s + cnt);
+        pt.etaoff[cnt] = etaoff[s + cnt];
+        h += k;
+        ++cnt;
       }
-      pt.K[cnt] = kf;
-      pt.tapoff[cnt] = tapoff[s + cnt];
-      pt.kap[cnt] = m.kap(s + cnt);
-      pt.etaoff[cnt] = etaoff[s + cnt];
-      h += k;
-      ++cnt;
+      pt.nstep = cnt;
+      pt.halo = h;
+      pt.wrap_general = (h >= m.n) ? 1 : 0;
+      out.passes.push_back(pt);
+      s += cnt;
     }
-    pt.nstep = cnt;
-    pt.halo = h;
-    pt.wrap_general = (h >= m.n) ? 1 : 0;
-    max_halo = std::max(max_halo, h);
-    out.passes.push_back(pt);
-    s += cnt;
+  };
+  split(fixed_s > 0 ? fixed_s : LDBP_MAX_STEPS_PER_PASS);
+  if (fixed_s == 0 && out.passes.size() > 1) {
+    const int np = static_cast<int>(out.passes.size());
+    split((m.nstep + np - 1) / np);
   }
+  int max_halo = 0;
+  for (const auto& pt : out.passes) max_halo = std::max(max_halo, pt.halo);
   // Grow the LDS work size when a pass's halo leaves too little room for the tile.
   while (chunks * chunk - 2 * max_halo < chunk / 2 && chunks < cmax) ++chunks;
   if (chunks * chunk - 2 * max_halo < 1)
@@ -202,9 +230,10 @@ static int make_plan(const ModelArgs& m, int32_t ckpt_every, const ldbp_plan* pl
 }
 
 // Passes over steps [0, nrun) made of whole checkpoint blocks of S steps: a pass takes blocks
-// while twice its halo stays within 1/8 of the LDS work size (or up to plan->steps_per_pass steps,
-// at least one block), and writes the state at each inner block boundary to that block's slot
-// (ckpt_mask).  The pass output itself is the next block's slot, or y after the last step.
+// while twice its halo stays within 1/8 of the LDS work size, the blocks then spread evenly over
+// that many passes (or up to plan->steps_per_pass steps, at least one block), and writes the state
+// at each inner block boundary to that block's slot (ckpt_mask).  The pass output itself is the
+// next block's slot, or y after the last step.
 static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ldbp_plan* plan, PassPlan& out) {
   int st = make_plan(m, S, plan, out);  // exact blocks: validates rb, chunks and the per-block halo
   if (st) return st;
@@ -215,32 +244,38 @@ static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ld
   for (const auto& b : out.passes)
     if (b.c0 < nrun) blocks.push_back(b);
   std::vector<PassTable> passes;
-  int max_halo = 0;
-  for (size_t i = 0; i < blocks.size();) {
-    PassTable pt = blocks[i];
-    pt.ckpt_mask = 0;
-    pt.ckpt_every = S;
-    size_t j = i + 1;
-    while (j < blocks.size()) {
-      const PassTable& b = blocks[j];
-      if (pt.nstep + b.nstep > LDBP_MAX_STEPS_PER_PASS) break;
-      if (want > 0 ? pt.nstep + b.nstep > want : 2 * (pt.halo + b.halo) * 8 > out.chunks * chunk) break;
-      pt.ckpt_mask |= uint64_t(1) << (pt.nstep - 1);  // the end of the pass so far is an inner boundary
-      for (int k = 0; k < b.nstep; ++k) {
-        pt.K[pt.nstep + k] = b.K[k];
-        pt.tapoff[pt.nstep + k] = b.tapoff[k];
-        pt.kap[pt.nstep + k] = b.kap[k];
-        pt.etaoff[pt.nstep + k] = b.etaoff[k];
+  // greedy grouping, at most `cap` blocks per pass
+  auto group = [&](size_t cap) {
+    passes.clear();
+    for (size_t i = 0; i < blocks.size();) {
+      PassTable pt = blocks[i];
+      pt.ckpt_mask = 0;
+      pt.ckpt_every = S;
+      size_t j = i + 1;
+      while (j < blocks.size() && j - i < cap) {
+        const PassTable& b = blocks[j];
+        if (pt.nstep + b.nstep > LDBP_MAX_STEPS_PER_PASS) break;
+        if (want > 0 ? pt.nstep + b.nstep > want : 2 * (pt.halo + b.halo) * 8 > out.chunks * chunk) break;
+        pt.ckpt_mask |= uint64_t(1) << (pt.nstep - 1);  // the end of the pass so far is an inner boundary
+        for (int k = 0; k < b.nstep; ++k) {
+          pt.K[pt.nstep + k] = b.K[k];
+          pt.tapoff[pt.nstep + k] = b.tapoff[k];
+          pt.kap[pt.nstep + k] = b.kap[k];
+          pt.etaoff[pt.nstep + k] = b.etaoff[k];
+        }
+        pt.nstep += b.nstep;
+        pt.halo += b.halo;
+        ++j;
       }
-      pt.nstep += b.nstep;
-      pt.halo += b.halo;
-      ++j;
+      pt.wrap_general = (pt.halo >= m.n) ? 1 : 0;
+      passes.push_back(pt);
+      i = j;
     }
-    pt.wrap_general = (pt.halo >= m.n) ? 1 : 0;
-    max_halo = std::max(max_halo, pt.halo);
-    passes.push_back(pt);
-    i = j;
-  }
+  };
+  group(blocks.size());
+  if (want == 0 && passes.size() > 1) group((blocks.size() + passes.size() - 1) / passes.size());
+  int max_halo = 0;
+  for (const auto& pt : passes) max_halo = std::max(max_halo, pt.halo);
   int chunks = out.chunks;
   while (chunks * chunk - 2 * max_halo < chunk / 2 && chunks < cmax) ++chunks;
   if (chunks * chunk - 2 * max_halo < 1)
@@ -250,29 +285,25 @@ static int make_block_plan(const ModelArgs& m, int32_t S, int32_t nrun, const ld
   return LDBP_OK;
 }
 
-// Runs steps [0, pp's last step] from x, writing every block input b >= 1 to slot b - 1 of ckpt;
-// the output of the final pass goes to `last` (y, or the last slot).  Pointers are those of the whole
-// batch; the launches cover waveforms [w0, w1).
-static int run_block_plan(const ModelArgs& m, const PassPlan& pp, const void* taps, const void* c, const void* x,
-                          void* last, void* ckpt, int32_t S, hipStream_t s, const void* eta = nullptr,
-                          int64_t w0 = 0, int64_t w1 = -1, int32_t* nonfinite = nullptr) {
-  if (w1 < 0) w1 = m.nwave;
+// Pass i of a block plan over waveforms [w0, w1): its input is x (i = 0) or the previous pass's output;
+// its output is the next block's checkpoint slot, or `last` (y, or the last slot) after the final pass;
+// inner block inputs b >= 1 go to slot b - 1 of ckpt.  Pointers are those of the whole batch.
+static int launch_block_pass(const ModelArgs& m, const PassPlan& pp, size_t i, const void* taps, const void* c,
+                             const void* x, void* last, void* ckpt, int32_t S, hipStream_t s, const void* eta,
+                             int64_t w0, int64_t w1, int32_t* nonfinite = nullptr) {
   const size_t wave_bytes = static_cast<size_t>(m.nwave) * m.n * m.npol * cx_size(m.dtype);
   const size_t w_off = static_cast<size_t>(w0) * m.n * m.npol * cx_size(m.dtype);
   const int64_t slot_elems = m.nwave * m.n * m.npol;
-  const void* in = static_cast<const char*>(x) + w_off;
-  for (size_t i = 0; i < pp.passes.size(); ++i) {
-    const PassTable& pt = pp.passes[i];
-    char* base = (i + 1 == pp.passes.size()) ? static_cast<char*>(last)
-                                             : static_cast<char*>(ckpt) + ((pt.c0 + pt.nstep) / S - 1) * wave_bytes;
-    void* out = base + w_off;
-    int st = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0, static_cast<int32_t>(m.n), pp.chunks, pt,
-                             taps, c, pp.sym, ckpt ? static_cast<char*>(ckpt) + w_off : nullptr, s, eta, slot_elems,
-                             nullptr, i + 1 == pp.passes.size() ? nonfinite : nullptr);
-    if (st) return st;
-    in = out;
-  }
-  return LDBP_OK;
+  auto pass_out = [&](size_t j) {
+    const PassTable& pt = pp.passes[j];
+    return ((j + 1 == pp.passes.size()) ? static_cast<char*>(last)
+                                        : static_cast<char*>(ckpt) + ((pt.c0 + pt.nstep) / S - 1) * wave_bytes) + w_off;
+  };
+  const void* in = i == 0 ? static_cast<const char*>(x) + w_off : pass_out(i - 1);
+  const bool final_pass = i + 1 == pp.passes.size();
+  return launch_fwd_pass(m.dtype, m.npol, pp.rb, in, pass_out(i), w1 - w0, static_cast<int32_t>(m.n), pp.chunks,
+                         pp.passes[i], taps, c, pp.sym, ckpt ? static_cast<char*>(ckpt) + w_off : nullptr, s, eta,
+                         slot_elems, nullptr, final_pass ? nonfinite : nullptr);
 }
 
 // Workgroups of one forward launch over the batch (the pass with the largest halo has the most tiles).
@@ -370,28 +401,22 @@ static int forward_impl(const ModelArgs& m, const void* taps, const void* c, con
     LDBP_HIP_CHECK(hipGetLastError());
   }
   if (ckpt) {
-    st = over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)),
-                     [&](int64_t w0, int64_t w1, hipStream_t ss) {
-                       return run_block_plan(m, pp, taps, c, x, y, ckpt, ckpt_every, ss, e, w0, w1, flag);
+    st = over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)), np,
+                     [&](size_t i, int64_t w0, int64_t w1, hipStream_t ss) {
+                       return launch_block_pass(m, pp, i, taps, c, x, y, ckpt, ckpt_every, ss, e, w0, w1, flag);
                      });
     return (st || !flag) ? st : guard_result(flag, s);
   }
   const size_t wave_elem_bytes = static_cast<size_t>(m.n) * m.npol * cx_size(m.dtype);
-  st = over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)),
-                   [&](int64_t w0, int64_t w1, hipStream_t ss) {
+  st = over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(m, pp)), np,
+                   [&](size_t i, int64_t w0, int64_t w1, hipStream_t ss) {
                      const size_t off = static_cast<size_t>(w0) * wave_elem_bytes;
-                     const void* in = static_cast<const char*>(x) + off;
-                     for (size_t i = 0; i < np; ++i) {
-                       // ping-pong that ends in y
-                       void* out = static_cast<char*>(((np - 1 - i) % 2 == 0) ? y : ws) + off;
-                       const int r = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0,
-                                                     static_cast<int32_t>(m.n), pp.chunks, pp.passes[i], taps, c,
-                                                     pp.sym, nullptr, ss, e, 0, nullptr,
-                                                     i + 1 == np ? flag : nullptr);
-                       if (r) return r;
-                       in = out;
-                     }
-                     return static_cast<int>(LDBP_OK);
+                     // ping-pong that ends in y: pass i writes y when np - 1 - i is even, ws otherwise
+                     auto out_of = [&](size_t j) { return static_cast<char*>(((np - 1 - j) % 2 == 0) ? y : ws) + off; };
+                     const void* in = i == 0 ? static_cast<const char*>(x) + off : out_of(i - 1);
+                     return launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out_of(i), w1 - w0, static_cast<int32_t>(m.n),
+                                            pp.chunks, pp.passes[i], taps, c, pp.sym, nullptr, ss, e, 0, nullptr,
+                                            i + 1 == np ? flag : nullptr);
                    });
   return (st || !flag) ? st : guard_result(flag, s);
 }
@@ -477,28 +502,25 @@ static int aperiodic_impl(const ModelArgs& m, const void* taps, const void* c, c
   ModelArgs mw = m;
   mw.n = g.nw;
   const int32_t nw = static_cast<int32_t>(g.nw);
-  return over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(mw, pp)),
-                     [&](int64_t w0, int64_t w1, hipStream_t ss) {
-                       const char* in = static_cast<const char*>(x) + w0 * m.n * sample_bytes;
-                       for (size_t i = 0; i < np; ++i) {
-                         const bool first = i == 0, last = i + 1 == np;
-                         EdgeMap em{0, nw, 0, nw};
-                         if (first) em.in_len = static_cast<int32_t>(m.n);
-                         if (first && edge == LDBP_EDGE_ZERO) em.in_off = static_cast<int32_t>(g.P);
-                         if (last) {
-                           em.out_off = static_cast<int32_t>(g.P);
-                           em.out_len = static_cast<int32_t>(g.nout);
-                         }
-                         const bool use_em = last || (first && edge == LDBP_EDGE_ZERO);
-                         char* out = last ? static_cast<char*>(y) + w0 * g.nout * sample_bytes
-                                          : static_cast<char*>(ws) + (i % 2) * g.buf_bytes + w0 * g.nw * sample_bytes;
-                         const int r = launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0, nw, pp.chunks,
-                                                       pp.passes[i], taps, c, pp.sym, nullptr, ss, e, 0,
-                                                       use_em ? &em : nullptr);
-                         if (r) return r;
-                         in = out;
+  return over_halves(s, m.nwave, worth_splitting(plan, np, fwd_blocks(mw, pp)), np,
+                     [&](size_t i, int64_t w0, int64_t w1, hipStream_t ss) {
+                       const bool first = i == 0, last = i + 1 == np;
+                       EdgeMap em{0, nw, 0, nw};
+                       if (first) em.in_len = static_cast<int32_t>(m.n);
+                       if (first && edge == LDBP_EDGE_ZERO) em.in_off = static_cast<int32_t>(g.P);
+                       if (last) {
+                         em.out_off = static_cast<int32_t>(g.P);
+                         em.out_len = static_cast<int32_t>(g.nout);
                        }
-                       return static_cast<int>(LDBP_OK);
+                       const bool use_em = last || (first && edge == LDBP_EDGE_ZERO);
+                       // passes alternate between the two work buffers; the last writes y
+                       const char* in = first ? static_cast<const char*>(x) + w0 * m.n * sample_bytes
+                                              : static_cast<const char*>(ws) + ((i - 1) % 2) * g.buf_bytes +
+                                                    w0 * g.nw * sample_bytes;
+                       char* out = last ? static_cast<char*>(y) + w0 * g.nout * sample_bytes
+                                        : static_cast<char*>(ws) + (i % 2) * g.buf_bytes + w0 * g.nw * sample_bytes;
+                       return launch_fwd_pass(m.dtype, m.npol, pp.rb, in, out, w1 - w0, nw, pp.chunks, pp.passes[i],
+                                              taps, c, pp.sym, nullptr, ss, e, 0, use_em ? &em : nullptr);
                      });
 }
 
@@ -830,35 +852,34 @@ static int backward_impl(const ModelArgs& m, const void* taps, const void* c, co
   }
   const size_t wave_elem_bytes = static_cast<size_t>(n) * npol * cx_size(dtype);
   const int64_t tiles_per_wave = L.ntiles / nwave;
-  st = over_halves(s, nwave, worth_splitting(plan, nb, L.ntiles), [&](int64_t w0, int64_t w1, hipStream_t ss) {
+  // launches per half: the forward passes that recompute the block inputs (no checkpoints given), then
+  // the blocks from the last to the first
+  const size_t nrec = (!ckpt && nb > 1) ? bp.passes.size() : 0;
+  st = over_halves(s, nwave, worth_splitting(plan, nb, L.ntiles), nrec + nb,
+                   [&](size_t k, int64_t w0, int64_t w1, hipStream_t ss) {
+    if (k < nrec)
+      return launch_block_pass(m, bp, k, taps, c, x, wsb + L.off_ckpt + (nb - 2) * wave_bytes, wsb + L.off_ckpt,
+                               L.S, ss, e, w0, w1);
+    const size_t bi = nb - 1 - (k - nrec);
     const size_t off = static_cast<size_t>(w0) * wave_elem_bytes;
-    if (!ckpt && nb > 1) {
-      const int r = run_block_plan(m, bp, taps, c, x, wsb + L.off_ckpt + (nb - 2) * wave_bytes, wsb + L.off_ckpt,
-                                   L.S, ss, e, w0, w1);
-      if (r) return r;
-    }
     // this range's rows of the partial sums: the tiles of waveforms [w0, w1)
     void* prt = static_cast<double*>(part) + static_cast<size_t>(w0 * tiles_per_wave) * L.ncols * 2;
-    const char* gcur = static_cast<const char*>(gy) + off;
-    for (size_t bi = nb; bi-- > 0;) {
-      const char* xb = (bi == 0 ? static_cast<const char*>(x) : ck + (bi - 1) * wave_bytes) + off;
-      const char* ys = nullptr;
-      int32_t nstored = 0;
-      if (L.stored) {
-        // checkpoint j holds the output of step j + 1; the last step's output is not stored (recomputed)
-        const int32_t sb = L.blocks.passes[bi].c0;
-        xb = (sb == 0 ? static_cast<const char*>(x) : ck + static_cast<size_t>(sb - 1) * wave_bytes) + off;
-        ys = ck + static_cast<size_t>(sb) * wave_bytes + off;
-        nstored = std::min<int32_t>(L.blocks.passes[bi].nstep, m.nstep - 1 - sb);
-      }
-      char* gin = static_cast<char*>((bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0)) + off;
-      const int r = launch_bwd_block(dtype, npol, xb, gcur, gin, w1 - w0, static_cast<int32_t>(n), L.tile_len,
-                                     L.blocks.passes[bi], taps, c, prt, L.ncols, L.ntaps + L.neta, sym, ss, e,
-                                     L.ntaps, ys, static_cast<int64_t>(nwave) * n * npol, nstored);
-      if (r) return r;
-      gcur = gin;
+    // block bi's output gradient: gy for the last block, else the input gradient of block bi + 1
+    const char* gcur = static_cast<const char*>(bi + 1 == nb ? gy : (((bi + 1) % 2) ? g1 : g0)) + off;
+    const char* xb = (bi == 0 ? static_cast<const char*>(x) : ck + (bi - 1) * wave_bytes) + off;
+    const char* ys = nullptr;
+    int32_t nstored = 0;
+    if (L.stored) {
+      // checkpoint j holds the output of step j + 1; the last step's output is not stored (recomputed)
+      const int32_t sb = L.blocks.passes[bi].c0;
+      xb = (sb == 0 ? static_cast<const char*>(x) : ck + static_cast<size_t>(sb - 1) * wave_bytes) + off;
+      ys = ck + static_cast<size_t>(sb) * wave_bytes + off;
+      nstored = std::min<int32_t>(L.blocks.passes[bi].nstep, m.nstep - 1 - sb);
     }
-    return static_cast<int>(LDBP_OK);
+    char* gin = static_cast<char*>((bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0)) + off;
+    return launch_bwd_block(dtype, npol, xb, gcur, gin, w1 - w0, static_cast<int32_t>(n), L.tile_len,
+                            L.blocks.passes[bi], taps, c, prt, L.ncols, L.ntaps + L.neta, sym, ss, e, L.ntaps, ys,
+                            static_cast<int64_t>(nwave) * n * npol, nstored);
   });
   if (st) return st;
   return launch_grad_reduce(dtype, part, L.ntiles, L.ncols, L.ntaps, gtaps, gc, s, L.neta, geta, wsb + L.off_chunks);

@@ -128,9 +128,10 @@ def test_batch_plan_rejects_bad_tables_before_any_gpu_work():
 
 def test_checkpointed_forward_groups_whole_blocks():
     from paper_2010_14258_amd import ldbp as L
-    # 50 steps of 15 taps, checkpoints every 2 steps: passes of whole blocks (halo rule), not 25 passes
+    # 50 steps of 15 taps, checkpoints every 2 steps: passes of whole blocks (halo rule: at most 8
+    # blocks), not 25 passes; the 25 blocks spread evenly over the 4 passes (7, 7, 7, 4)
     npass, _, maxs = L.ldbp_forward_plan_query(0, 1, 64, 65536, [15] * 50, ckpt_every=2)
-    assert npass == 4 and maxs == 16 and maxs % 2 == 0
+    assert npass == 4 and maxs == 14
     # steps_per_pass is rounded down to whole blocks
     npass, _, maxs = L.ldbp_forward_plan_query(0, 1, 64, 65536, [15] * 50, ckpt_every=2, plan=(7, 0))
     assert maxs == 6 and npass == 9
