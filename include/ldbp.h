@@ -86,9 +86,12 @@ enum ldbp_dtype { LDBP_C64 = 0, LDBP_C128 = 1 };
  *                       output is a NaN or an infinity (y is written either way).  The guard
  *                       serves the caller that falls back to plain FFT-DBP when the learned
  *                       model misbehaves; it cannot run inside a graph capture.
- * Results are bit-identical for any steps_per_pass and chunks at fixed
- * outputs_per_thread and LDBP_PLAN_SYMMETRIC, with or without LDBP_PLAN_ONE_STREAM and
- * LDBP_PLAN_GUARD. */
+ * Zero chunks take the most that still let three workgroups share a compute unit's 160 KiB of
+ * LDS; zero steps_per_pass takes steps while twice the pass halo stays within 1/8 of the LDS work
+ * size, then spreads the steps evenly over that many passes.
+ * Every output is the same sequence of fused multiply-adds whatever the tiling, so results are
+ * bit-identical for any steps_per_pass, chunks and outputs_per_thread at fixed
+ * LDBP_PLAN_SYMMETRIC, with or without LDBP_PLAN_ONE_STREAM and LDBP_PLAN_GUARD. */
 #define LDBP_PLAN_SYMMETRIC 1
 #define LDBP_PLAN_ONE_STREAM 2
 #define LDBP_PLAN_GUARD 4

@@ -66,11 +66,27 @@ struct Rot32 {
   }
 };
 
+// The fused reduction: the exact product minus the integer nearest its rounded value, in one operation.
 __device__ __forceinline__ void phase_sincos(float coef_rev, float p, float& s, float& c) {
-  Rot32::sincos_rev(coef_rev * p, s, c);
+  const float rev = fmaf(coef_rev, p, -__builtin_rintf(coef_rev * p));
+  s = __builtin_amdgcn_sinf(rev);
+  c = __builtin_amdgcn_cosf(rev);
 }
 __device__ __forceinline__ void phase_sincos(double coef_rad, double p, double& s, double& c) {
   sincos(coef_rad * p, &s, &c);
+}
+
+// |v|^2 added to p, and v (c + j s), with every product fused explicitly.  The forward's arithmetic is
+// written without an unfused multiply feeding an add, so that the compiler has no contraction left to
+// choose: each inlined and unrolled copy then rounds alike, and an output does not depend on where the
+// tiling puts it in a thread's register window.
+template <typename V, typename R>
+__device__ __forceinline__ R add_power(R p, const V& v) {
+  return fma(v.y, v.y, fma(v.x, v.x, p));
+}
+template <typename V, typename R>
+__device__ __forceinline__ V rotate(const V& v, R c, R s) {
+  return V{fma(v.x, c, -(v.y * s)), fma(v.x, s, v.y * c)};
 }
 
 // Coefficient as the kernels consume it: revolutions for float, radians for double.

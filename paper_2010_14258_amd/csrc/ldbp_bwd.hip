@@ -770,7 +770,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
         load_sample<R, NPOL>(GA + i * NPOL, gv);
 #pragma unroll
         for (int pp = 0; pp < NPOL; ++pp) {
-          pw += yv[pp].x * yv[pp].x + yv[pp].y * yv[pp].y;
+          pw = add_power(pw, yv[pp]);
           q += gv[pp].y * yv[pp].x - gv[pp].x * yv[pp].y;
         }
         Q[i] = q;
@@ -794,7 +794,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
         load_sample<R, NPOL>(GA + i * NPOL, gv);
 #pragma unroll
         for (int pp = 0; pp < NPOL; ++pp) {
-          pw += yv[pp].x * yv[pp].x + yv[pp].y * yv[pp].y;
+          pw = add_power(pw, yv[pp]);
           q += gv[pp].y * yv[pp].x - gv[pp].x * yv[pp].y;
         }
         R sn, co;

@@ -57,8 +57,8 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
       for (int r = 0; r < RB; ++r)
 #pragma unroll
         for (int p = 0; p < NPOL; ++p) {
-          const V c = win[r + K][p];
-          acc[r][p] = V{h0.x * c.x - h0.y * c.y, h0.x * c.y + h0.y * c.x};
+          acc[r][p] = V{0, 0};
+          cmac(acc[r][p], h0, win[r + K][p]);
         }
 #pragma unroll
       for (int k = 1; k <= K; ++k) {
@@ -89,7 +89,7 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
     for (int r = 0; r < RB; ++r) {
       R pwr = 0;
 #pragma unroll
-      for (int p = 0; p < NPOL; ++p) pwr += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
+      for (int p = 0; p < NPOL; ++p) pwr = add_power(pwr, acc[r][p]);
       if constexpr (LIN) {
         if (base + r < hi) {
           pw[base + r] = pwr;
@@ -101,10 +101,7 @@ __device__ __forceinline__ void fir_kerr_fixed(const cx_t<R>* __restrict__ in, c
         if (base + r < hi) {
           V o[NPOL];
 #pragma unroll
-          for (int p = 0; p < NPOL; ++p) {
-            o[p].x = acc[r][p].x * co - acc[r][p].y * s;
-            o[p].y = acc[r][p].x * s + acc[r][p].y * co;
-          }
+          for (int p = 0; p < NPOL; ++p) o[p] = rotate(acc[r][p], co, s);
           store_sample<R, NPOL>(out + (base + r) * NPOL, o);
         }
       }
@@ -135,7 +132,7 @@ __device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in,
     for (int r = 0; r < RB; ++r) {
       R pwr = 0;
 #pragma unroll
-      for (int p = 0; p < NPOL; ++p) pwr += acc[r][p].x * acc[r][p].x + acc[r][p].y * acc[r][p].y;
+      for (int p = 0; p < NPOL; ++p) pwr = add_power(pwr, acc[r][p]);
       if constexpr (LIN) {
         if (base + r < hi) {
           pw[base + r] = pwr;
@@ -147,10 +144,7 @@ __device__ __forceinline__ void fir_kerr_generic(const cx_t<R>* __restrict__ in,
         if (base + r < hi) {
           V o[NPOL];
 #pragma unroll
-          for (int p = 0; p < NPOL; ++p) {
-            o[p].x = acc[r][p].x * co - acc[r][p].y * s;
-            o[p].y = acc[r][p].x * s + acc[r][p].y * co;
-          }
+          for (int p = 0; p < NPOL; ++p) o[p] = rotate(acc[r][p], co, s);
           store_sample<R, NPOL>(out + (base + r) * NPOL, o);
         }
       }
@@ -215,7 +209,7 @@ __device__ __forceinline__ void nl_filter_fixed(cx_t<R>* __restrict__ u, const R
         V a[NPOL];
         load_sample<R, NPOL>(u + (base + r) * NPOL, a);
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) a[p] = V{a[p].x * co - a[p].y * s, a[p].x * s + a[p].y * co};
+        for (int p = 0; p < NPOL; ++p) a[p] = rotate(a[p], co, s);
         store_sample<R, NPOL>(u + (base + r) * NPOL, a);
       }
     }
@@ -254,7 +248,7 @@ __device__ __forceinline__ void nl_filter_win(cx_t<R>* __restrict__ u, const R* 
         V a[NPOL];
         load_sample<R, NPOL>(u + (base + r) * NPOL, a);
 #pragma unroll
-        for (int p = 0; p < NPOL; ++p) a[p] = V{a[p].x * co - a[p].y * s, a[p].x * s + a[p].y * co};
+        for (int p = 0; p < NPOL; ++p) a[p] = rotate(a[p], co, s);
         store_sample<R, NPOL>(u + (base + r) * NPOL, a);
       }
     }
@@ -273,7 +267,7 @@ __device__ __forceinline__ void nl_filter_generic(cx_t<R>* __restrict__ u, const
     V a[NPOL];
     load_sample<R, NPOL>(u + m * NPOL, a);
 #pragma unroll
-    for (int p = 0; p < NPOL; ++p) a[p] = V{a[p].x * co - a[p].y * s, a[p].x * s + a[p].y * co};
+    for (int p = 0; p < NPOL; ++p) a[p] = rotate(a[p], co, s);
     store_sample<R, NPOL>(u + m * NPOL, a);
   }
 }

@@ -193,6 +193,31 @@ def test_symmetric_plans_are_bitwise_identical():
         np.testing.assert_array_equal(y.cpu().numpy(), base7.astype(np.complex64))
 
 
+@pytest.mark.parametrize("sym", [0, 1])
+@pytest.mark.parametrize("npol", [1, 2])
+@pytest.mark.parametrize("dtype,tol", [(torch.complex64, TOL64), (torch.complex128, TOL128)])
+def test_plans_are_bitwise_identical(dtype, tol, npol, sym):
+    """Every output is the same sequence of fused operations whatever the plan: steps per pass, LDS
+    chunks and outputs per thread (the position of the output in a thread's register window) change
+    no bit, for either polarisation count, precision, and for the general and the folded evaluation;
+    long filters take the streamed-tap loop (half-length beyond 12) with the same result."""
+    print("case: plan invariance", dtype, npol, sym, flush=True)
+    Ts = [3, 15, 27, 5, 1, 9, 3, 25, 7, 13]
+    taps, c = _mixed_model(54, len(Ts), Ts, 0.3)
+    if sym:
+        taps = [(h + h[::-1]) / 2 for h in taps]
+    shape = (3, 3001) if npol == 1 else (2, 2001, 2)
+    x = synth.complex_normal(55, shape) * 0.6
+    rbs = {(torch.complex64, 1): (7, 8, 9), (torch.complex64, 2): (3, 4, 5),
+           (torch.complex128, 1): (3, 4), (torch.complex128, 2): (1, 2)}[(dtype, npol)]
+    base = _run(x, taps, c, npol=npol, dtype=dtype, plan=(1, 1, rbs[0], sym))
+    assert _rel(base, O.ldbp_forward(x, taps, c, npol=npol)) <= tol
+    for rb in rbs:
+        for plan in [(0, 0, rb, sym), (2, 1, rb, sym), (3, 2, rb, sym), (len(Ts), 3, rb, sym), (4, 1, rb, sym, 1)]:
+            np.testing.assert_array_equal(_run(x, taps, c, npol=npol, dtype=dtype, plan=plan), base,
+                                          err_msg=str(plan))
+
+
 @pytest.mark.parametrize("npol", [1, 2])
 @pytest.mark.parametrize("dtype,tol", [(torch.complex64, TOL64), (torch.complex128, TOL128)])
 def test_forward_symmetric_folded_evaluation(npol, dtype, tol):
