@@ -126,6 +126,21 @@ def test_batch_plan_rejects_bad_tables_before_any_gpu_work():
     assert lib.ldbp_batch_forward(None, 16, 16, 16, 32, None) == N.LDBP_EINVAL
 
 
+def test_default_plan_chunks_and_even_passes():
+    from paper_2010_14258_amd import ldbp as L
+    # complex64, two polarisations, 3 outputs per thread: 2 chunks of 768 samples (three workgroups of
+    # 48 KiB fit a compute unit's 160 KiB of LDS, three of 72 KiB do not); 64 steps of 5 taps in 2
+    # passes of 32 (halo 64): tile 1536 - 128
+    assert L.ldbp_forward_plan_query(0, 2, 8, 1 << 20, [5] * 64) == (2, 1408, 32)
+    # one chunk asked for: 3 passes (the halo rule allows 24 steps), spread 22, 21, 21
+    assert L.ldbp_forward_plan_query(0, 2, 8, 1 << 20, [5] * 64, plan=(0, 1, 3, 1)) == (3, 680, 22)
+    # complex64, one polarisation, 7 outputs per thread: 1 chunk (three of 56 KiB exceed 160 KiB);
+    # 50 steps of 15 taps, at most 16 per pass by the halo rule, spread 13, 13, 12, 12: tile 1792 - 182
+    assert L.ldbp_forward_plan_query(0, 1, 64, 65536, [15] * 50) == (4, 1610, 13)
+    # complex128, two polarisations, 1 output per thread: 3 chunks of 256 samples
+    assert L.ldbp_forward_plan_query(1, 2, 8, 1 << 20, [5] * 64) == (3, 680, 22)
+
+
 def test_checkpointed_forward_groups_whole_blocks():
     from paper_2010_14258_amd import ldbp as L
     # 50 steps of 15 taps, checkpoints every 2 steps: passes of whole blocks (halo rule: at most 8
