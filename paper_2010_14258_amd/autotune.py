@@ -5,8 +5,9 @@ plan in a candidate set -- outputs per thread x steps per pass x LDS chunks -- w
 the caller's stream and keeps the plan with the fewest steps per pass among those within 0.5% of the
 fastest (each candidate timed as the least of three runs of back-to-back calls).  Results are
 cached in memory and, when a path is given (argument or LDBP_AUTOTUNE_CACHE), in a JSON file; a
-missing or unreadable cache file just means tuning again.  All candidates produce identical results for a fixed outputs-per-thread
-and symmetry flag; across those the results agree to rounding.
+missing or unreadable cache file just means tuning again.  All candidates with the same symmetry flag
+produce bit-identical results (every output is the same sequence of fused operations whatever the
+tiling).
 """
 from __future__ import annotations
 

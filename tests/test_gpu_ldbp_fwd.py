@@ -168,7 +168,7 @@ def _full_size_reference(symmetric: bool):
 
 def test_symmetric_plans_are_bitwise_identical():
     """The folded evaluation is the same arithmetic for every output sample whatever the tiling: any
-    steps per pass and chunks (fixed outputs per thread), one or two streams, and checkpointed blocks
+    steps per pass and chunks (and outputs per thread, see below), one or two streams, and checkpointed blocks
     give bit-identical outputs (the invariance stated for LDBP_PLAN_SYMMETRIC)."""
     print("case: symmetric plan invariance", flush=True)
     Ts = [15] * 20 + [5, 3] * 5
