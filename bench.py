@@ -500,12 +500,14 @@ def manakov(torch, dev, reps: int):
                     "steps), so the LS-initialised SNR is not a quality figure"}
 
 
-def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 3),), data_pool: int = 0):
+def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 3),), data_pool: int = 0,
+                      lr_schedule: str = "constant"):
     """The equal-SNR comparison with a trained model: LDBP (l = 50, 5 steps per span) trained by the
     training recipe (32 x 16,384 waveforms per batch simulated on the GPU, launch powers {2, 3, 4} dBm,
     filters pruned from 25 to 3 taps, Adam), then evaluated at each launch power on the 64 x 65,536
     inference batch against FFT-DBP at 1-20 steps per span; the FFT-DBP setting compared is the
-    smallest with SNR >= SNR_LDBP - 0.1 dB."""
+    smallest with SNR >= SNR_LDBP - 0.1 dB.  lr_schedule "cosine": Adam's step size decays from 1e-3 to
+    1e-4 by a half cosine after the last pruning event."""
     from paper_2010_14258_amd import autotune as AT
     from paper_2010_14258_amd import ldbp as L
     from paper_2010_14258_amd import ssm as SS
@@ -514,8 +516,8 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
 
     models = []
     for t_init, t_final in variants:
-        trn = TRN.Trainer(TRN.TrainConfig(iters=iters, t_init=t_init, t_final=t_final, data_pool=data_pool),
-                          device=dev)
+        trn = TRN.Trainer(TRN.TrainConfig(iters=iters, t_init=t_init, t_final=t_final, data_pool=data_pool,
+                                          lr_schedule=lr_schedule), device=dev)
         t0 = time.perf_counter()
         curve = []
         for it in range(iters):
@@ -571,7 +573,7 @@ def equal_snr_trained(torch, dev, iters: int, powers, reps: int, variants=((25, 
         del W, r, y, z
         torch.cuda.empty_cache()
     return {"workload": "64 waveforms x 65,536 c64 samples, 10 x 100 km, LDBP l = 50 (5 steps per span) trained",
-            "train_iterations": iters, "models": out_models, "by_power": rows}
+            "train_iterations": iters, "lr_schedule": lr_schedule, "models": out_models, "by_power": rows}
 
 
 def manakov_trained(torch, dev, iters: int, powers, pool: int = 4, channel_steps: int = 25):
@@ -759,7 +761,7 @@ def essm_trained(torch, dev, iters: int, powers, kappa: int = 20, ntaps: int = 1
     out_models = [{k: v for k, v in m.items() if k not in ("taps", "c", "ntap", "eta", "nl_ntap")} for m in models]
     return {"workload": f"10 x 100 km, l = {10 * stps} ({stps} step per span), {ntaps} taps, kappa = {kappa}; "
                         "evaluated on 64 waveforms x 65,536 c64 samples",
-            "train_iterations": iters, "models": out_models, "by_power": rows}
+            "train_iterations": iters, "lr_schedule": lr_schedule, "models": out_models, "by_power": rows}
 
 
 def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_at=None, train_c: bool = True,
@@ -1016,7 +1018,7 @@ def main():
     ap.add_argument("--eval-batches", type=int, default=4,
                     help="--mode e1: held-out batches of 32 x 8,192 symbols per launch power")
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"],
-                    help="--mode e1: Adam step size; cosine: decay to 1e-4 after the last pruning event")
+                    help="--mode e1 and snr: Adam step size; cosine: decay to 1e-4 after the last pruning event")
     ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
     ap.add_argument("--out-dir", default=None,
                     help="--mode e1: directory of the trainer checkpoints and learning curve (default: the "
@@ -1076,7 +1078,7 @@ def main():
     if args.mode == "snr":
         variants = [tuple(int(t) for t in v.split(":")) for v in args.train_taps.split(",")]
         out = equal_snr_trained(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")], 20,
-                                variants, args.data_pool)
+                                variants, args.data_pool, args.lr_schedule)
         print(json.dumps(out), flush=True)
         return
     if args.mode == "e1":
