@@ -1290,10 +1290,14 @@ def main():
                           max(5, args.steps // 5), 2)
         nblk = -(-ell // S)
         b_launch_ms = ms_b / nblk
-        b_flops_launch = nwave * n * sum(bwd_flops_per_sample_step(t, True) for t in ntap) / nblk
+        # every block but the last reads its output (the next block's checkpoint) instead of recomputing
+        # its last step, so the algorithmic work leaves that step's forward arithmetic out
+        skipped = sum(fwd_flops_per_sample_step(ntap[min(ell, (j + 1) * S) - 1], True) for j in range(nblk - 1))
+        b_flops_launch = nwave * n * (sum(bwd_flops_per_sample_step(t, True) for t in ntap) - skipped) / nblk
         b_tflops = b_flops_launch / (b_launch_ms * 1e-3) / 1e12
-        # read the block checkpoint and G_y, write G_x (not for the first block: need_gx=False)
-        b_bytes_launch = nwave * n * 8 * (2 * nblk + (nblk - 1)) / nblk
+        # read the block checkpoint, G_y and (not for the last block) the block's output, write G_x (not
+        # for the first block: need_gx=False)
+        b_bytes_launch = nwave * n * 8 * (2 * nblk + 2 * (nblk - 1)) / nblk
         b_traffic = None
         if os.path.exists(BWD_TRAFFIC_FILE):
             with open(BWD_TRAFFIC_FILE) as fh:
@@ -1309,7 +1313,7 @@ def main():
                               "frac": b_tflops / FP32_PEAK_TFLOPS, "traffic": b_traffic,
                               "kernel": "ldbp_bwd_kernel<float,1,5,5,256,false,7> folded", "launch_ms": b_launch_ms,
                               "launches": nblk, "one_stream_backward_ms": ms_b,
-                              "flops_per_sample_step": bwd_flops_per_sample_step(TAPS, True),
+                              "flops_per_sample_step": b_flops_launch * nblk / (nwave * n * ell),
                               "flops_per_launch": b_flops_launch, "algorithmic_bytes_per_launch": b_bytes_launch,
                               "hbm_achieved_gbs": b_bytes_launch / (b_launch_ms * 1e-3) / 1e9}}
         # equal-SNR comparison with FFT-DBP on the same waveforms

@@ -634,7 +634,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     int32_t tile_len, int32_t ntiles, const cx_t<R>* __restrict__ taps, const R* __restrict__ c, PassTable pt,
     int32_t pad, double2* __restrict__ part, int32_t ncols, int32_t ccol_base, int32_t sym,
     const R* __restrict__ eta, int32_t ecol_base, const cx_t<R>* __restrict__ ys, int64_t ys_stride,
-    int32_t nstored) {
+    int32_t nstored, const cx_t<R>* __restrict__ yout) {
   using V = cx_t<R>;
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int NW = THREADS / 64;
@@ -683,7 +683,10 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
 
   // 1. block input, block-output gradient (used in step 3) and, when the forward stored them, the
   // outputs of the block's first nstored steps (unfiltered complex64 steps only), each over the range
-  // its recompute would cover; then the forward recompute of the remaining steps
+  // its recompute would cover, or (yout) the block's output Y_S, which the forward stored as the next
+  // block's checkpoint; then the forward recompute of the remaining steps.  A stored output is the
+  // value the recompute would give, bit for bit: every forward output is the same sequence of fused
+  // operations whatever the tiling.
   {
     BwdTile<R> t[kMaxBwdTiles];
     t[0] = BwdTile<R>{xw, Y0, 2 * H, Lw + 4 * H};
@@ -702,6 +705,10 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
           cnt = 2 + s;
         }
       }
+      if (yout && nstored == 0) {
+        t[2] = BwdTile<R>{yout + wave * static_cast<int64_t>(n) * NPOL, Y0 + ylast, H, bwd_y_width(Lw, H, H)};
+        cnt = 3;
+      }
     }
     if constexpr (!FILT && sizeof(R) == 4) {
       if (cnt > 2) load_bwd_tiles<R, NPOL, THREADS, kMaxBwdTiles>(t, cnt, n, t0, 2 * H >= n);
@@ -719,7 +726,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const int kp = kapp(s);
     V* ynext = ycur + static_cast<size_t>(bwd_y_width(Lw, H, hs, kprev) + pad) * NPOL;
     const R coef = c[pt.c0 + s - 1] * phase_coef_scale<R>();
-    if (!FILT && sizeof(R) == 4 && s <= nstored) {
+    if (!FILT && sizeof(R) == 4 && (s <= nstored || (yout && s == S))) {
       // loaded above
       hs += K;
       ycur = ynext;
@@ -961,7 +968,8 @@ template <typename R, int NPOL>
 static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                               int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
                               int32_t ncols, int32_t ccol_base, int sym, const void* eta, int32_t ecol_base,
-                              const void* ys, int64_t ys_stride, int32_t nstored, hipStream_t stream) {
+                              const void* ys, int64_t ys_stride, int32_t nstored, const void* yout,
+                              hipStream_t stream) {
   using Cfg = BwdCfg<R, NPOL>;
   const int64_t ntiles = (n + tile_len - 1) / tile_len;
   const int64_t nblocks = ntiles * nwave;
@@ -985,7 +993,7 @@ static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64
                      n, tile_len, static_cast<int32_t>(ntiles), static_cast<const cx_t<R>*>(taps),
                      static_cast<const R*>(c), pt, bwd_pad(sizeof(R) == 4 ? LDBP_C64 : LDBP_C128, NPOL),
                      static_cast<double2*>(part), ncols, ccol_base, sym, static_cast<const R*>(eta), ecol_base,
-                     static_cast<const cx_t<R>*>(ys), ys_stride, nstored);
+                     static_cast<const cx_t<R>*>(ys), ys_stride, nstored, static_cast<const cx_t<R>*>(yout));
   LDBP_HIP_CHECK(hipGetLastError());
   return LDBP_OK;
 }
@@ -993,11 +1001,14 @@ static int launch_bwd_block_t(const void* xb, const void* gout, void* gin, int64
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
                      int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream, const void* eta,
-                     int32_t ecol_base, const void* ys, int64_t ys_stride, int32_t nstored) {
+                     int32_t ecol_base, const void* ys, int64_t ys_stride, int32_t nstored, const void* yout) {
   if (nstored > 0 && (eta || dtype != LDBP_C64 || nstored > kMaxBwdTiles - 2 || nstored > pt.nstep))
     return fail(LDBP_EINVAL, "stored step outputs: %d for a block of %d steps", nstored, pt.nstep);
+  if (yout && (eta || dtype != LDBP_C64 || nstored > 0))
+    return fail(LDBP_EINVAL, "a stored block output needs unfiltered complex64 steps and no other stored outputs");
 #define LDBP_BWD_ARGS \
-  xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols, ccol_base, sym, eta, ecol_base, ys, ys_stride, nstored, stream
+  xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols, ccol_base, sym, eta, ecol_base, ys, ys_stride, nstored, \
+      yout, stream
   if (dtype == LDBP_C64)
     return npol == 1 ? launch_bwd_block_t<float, 1>(LDBP_BWD_ARGS) : launch_bwd_block_t<float, 2>(LDBP_BWD_ARGS);
   return npol == 1 ? launch_bwd_block_t<double, 1>(LDBP_BWD_ARGS) : launch_bwd_block_t<double, 2>(LDBP_BWD_ARGS);

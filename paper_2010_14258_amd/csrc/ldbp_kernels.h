@@ -71,7 +71,8 @@ int bwd_chunk_capacity(int dtype, int npol);
 int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void* gin, int64_t nwave, int32_t n,
                      int32_t tile_len, const PassTable& pt, const void* taps, const void* c, void* part,
                      int32_t ncols, int32_t ccol_base, int sym, hipStream_t stream, const void* eta = nullptr,
-                     int32_t ecol_base = 0, const void* ys = nullptr, int64_t ys_stride = 0, int32_t nstored = 0);
+                     int32_t ecol_base = 0, const void* ys = nullptr, int64_t ys_stride = 0, int32_t nstored = 0,
+                     const void* yout = nullptr);
 // Two fixed-order stages through chunk_sums (grad_reduce_chunks(ntiles) x ncols double2).
 int64_t grad_reduce_chunks(int64_t ntiles);
 int launch_grad_reduce(int dtype, const void* part, int64_t ntiles, int32_t ncols, int32_t ntaps, void* gtaps,
