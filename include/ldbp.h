@@ -211,8 +211,9 @@ int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
  *
  *   (dtype .. c)  as for ldbp_forward
  *   x            device [nwave][n][npol] complex: the forward input
- *   ckpt         device checkpoints written by ldbp_forward with the same ckpt_every,
- *                or NULL: the backward recomputes them into its workspace.  With
+ *   ckpt         device checkpoints written by ldbp_forward with the same x, taps, c,
+ *                ckpt_every and LDBP_PLAN_SYMMETRIC flag, or NULL: the backward recomputes
+ *                them into its workspace.  With
  *                ckpt_every = 1 (every step's output stored; complex64, ldbp_backward only)
  *                the backward reads the stored outputs in blocks of the default length
  *                instead of recomputing each step (more HBM traffic, fewer instructions)
