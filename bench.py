@@ -1315,7 +1315,10 @@ def main():
                               "launches": nblk, "one_stream_backward_ms": ms_b,
                               "flops_per_sample_step": b_flops_launch * nblk / (nwave * n * ell),
                               "flops_per_launch": b_flops_launch, "algorithmic_bytes_per_launch": b_bytes_launch,
-                              "hbm_achieved_gbs": b_bytes_launch / (b_launch_ms * 1e-3) / 1e9}}
+                              "hbm_achieved_gbs": b_bytes_launch / (b_launch_ms * 1e-3) / 1e9,
+                              "note": "every block but the last reads its output from the next checkpoint, so the "
+                                      "algorithmic flops count one recomputed step per block (%d flops per "
+                                      "sample*step with both)" % bwd_flops_per_sample_step(TAPS, True)}}
         # equal-SNR comparison with FFT-DBP on the same waveforms
         snr_ldbp = snr_db(TX, z, W["s"], W["p"])
         sweep = {}
