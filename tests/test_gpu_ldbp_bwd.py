@@ -203,6 +203,42 @@ def test_backward_is_deterministic():
     np.testing.assert_array_equal(a[2], b[2])
 
 
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_backward_same_bits_whatever_forward_plan_wrote_the_checkpoints(symmetric):
+    """Forward outputs do not depend on the tiling, so checkpoints written by forwards with different
+    plans (steps per pass, LDS chunks, outputs per thread) are the same bits, and so are the gradients
+    of the backward that reads them -- which, for one polarisation, also reads every block's output
+    from the next checkpoint -- and of the backward that recomputes its checkpoints itself."""
+    print("case: bwd checkpoints from any plan", symmetric, flush=True)
+    Ts = [15, 15, 9, 15, 3, 15, 7, 15, 5, 15]
+    taps, c = _model(130, Ts, 0.3)
+    if symmetric:
+        taps = [0.5 * (h + h[::-1]) for h in taps]
+    x = synth.complex_normal(131, (3, 9001)) * 0.5
+    gy = synth.complex_normal(132, (3, 9001))
+    tp, ntap = W.pack_taps(taps)
+    xt, tt = _t(x, torch.complex64), _t(tp, torch.complex64)
+    ct, gt = _t(np.asarray(c, np.float64), torch.float32), _t(gy, torch.complex64)
+    S, sym = 2, int(symmetric)
+    outs = []
+    for plan in [(0, 0, 0, sym), (4, 1, 9, sym), (10, 2, 8, sym, 1), None]:
+        ck = None
+        if plan is not None:
+            ck = torch.empty((G.num_checkpoints(len(ntap), S),) + tuple(xt.shape), dtype=torch.complex64, device=DEV)
+            G.ldbp_forward(xt, tt, ct, ntap, ckpt=ck, ckpt_every=S, plan=plan)
+        gx, gtp, gc = G.ldbp_backward(xt, tt, ct, ntap, gt, ckpt=ck, ckpt_every=S, symmetric=symmetric)
+        torch.cuda.synchronize()
+        outs.append((gx.cpu().numpy(), gtp.cpu().numpy(), gc.cpu().numpy()))
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            np.testing.assert_array_equal(a, b)
+    rx, rt, rc = O.ldbp_grad(x, taps, c, gy)
+    got = (outs[0][0].astype(np.complex128), [outs[0][1][a:b].astype(np.complex128)
+                                              for a, b in zip(np.cumsum([0] + ntap)[:-1], np.cumsum(ntap))],
+           outs[0][2].astype(np.float64))
+    _cmp(got, (rx, _sym_projection(rt) if symmetric else rt, rc), 1e-4)
+
+
 def test_autograd_function_matches_oracle():
     print("case: autograd", flush=True)
     Ts = [9, 7, 5, 3, 9, 7]
