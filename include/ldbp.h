@@ -203,9 +203,9 @@ int essm_forward_plan_query(int32_t dtype, int32_t npol, int64_t nwave, int64_t 
  *   FIR step   dL/dh_k = sum_m G_u,m conj(x_{m-k}), G_x,p = sum_k conj(h_k) G_u,(p+k)
  * summed over waveforms and polarisations.  The forward is recomputed block by
  * block (ckpt_every steps) from checkpoints, keeping each block's intermediate
- * signals in LDS only; for unfiltered complex64 steps of one polarisation, every
- * block but the last reads its own output from the next checkpoint instead of
- * recomputing its last step (the same values bit for bit: the forward's outputs do
+ * signals in LDS only; for complex64 steps of one polarisation, every block but
+ * the last reads its own output from the next checkpoint instead of recomputing
+ * its last step (the same values bit for bit: the forward's outputs do
  * not depend on the tiling).  Sums over samples are formed per tile and reduced in
  * FP64 in a fixed order: results are deterministic.
  *

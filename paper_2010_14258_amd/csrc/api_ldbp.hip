@@ -877,11 +877,11 @@ static int backward_impl(const ModelArgs& m, const void* taps, const void* c, co
       nstored = std::min<int32_t>(L.blocks.passes[bi].nstep, m.nstep - 1 - sb);
     }
     // the block's output is the next block's checkpoint (slot bi): loaded instead of recomputing the
-    // block's last step (unfiltered complex64 steps of one polarisation; the last block's output, y,
-    // is not an argument).  Same-box A/B on 64 x 65,536, l = 50, 15 taps: backward 1.415 -> 1.373 ms;
-    // with two polarisations the extra array read makes the backward HBM-bound (8 x 2^20 x 2, 5 taps:
-    // 4.09 -> 4.33 ms), so they recompute it.
-    const char* yout = (!L.stored && !m.filtered() && dtype == LDBP_C64 && npol == 1 && bi + 1 < nb)
+    // block's last step (complex64 steps of one polarisation; the last block's output, y, is not an
+    // argument).  Same-box A/B on 64 x 65,536, l = 50, 15 taps: backward 1.415 -> 1.373 ms; with two
+    // polarisations the extra array read makes the backward HBM-bound (8 x 2^20 x 2, 5 taps: 4.09 ->
+    // 4.33 ms), so they recompute it.
+    const char* yout = (!L.stored && dtype == LDBP_C64 && npol == 1 && bi + 1 < nb)
                            ? ck + bi * wave_bytes + off : nullptr;
     char* gin = static_cast<char*>((bi == 0 && gx) ? gx : ((bi % 2) ? g1 : g0)) + off;
     return launch_bwd_block(dtype, npol, xb, gcur, gin, w1 - w0, static_cast<int32_t>(n), L.tile_len,

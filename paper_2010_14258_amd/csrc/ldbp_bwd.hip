@@ -680,6 +680,10 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
 
   const V* xw = xb + wave * static_cast<int64_t>(n) * NPOL;
   const V* gw = gout + wave * static_cast<int64_t>(n) * NPOL;
+  // the block output read from the next checkpoint: complex64; filtered steps of one polarisation only
+  // (the two-polarisation filtered kernel has no registers to spare for a third tile, and the host
+  // passes no block output with two polarisations)
+  constexpr bool kYout = sizeof(R) == 4 && (!FILT || NPOL == 1);
 
   // 1. block input, block-output gradient (used in step 3) and, when the forward stored them, the
   // outputs of the block's first nstored steps (unfiltered complex64 steps only), each over the range
@@ -705,13 +709,20 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
           cnt = 2 + s;
         }
       }
+    }
+    if constexpr (kYout) {
+      // Y_S over global [t0 - H, t0 + Lw + H): its buffer starts kappa_S earlier (filtered steps)
       if (yout && nstored == 0) {
-        t[2] = BwdTile<R>{yout + wave * static_cast<int64_t>(n) * NPOL, Y0 + ylast, H, bwd_y_width(Lw, H, H)};
+        t[2] = BwdTile<R>{yout + wave * static_cast<int64_t>(n) * NPOL, Y0 + ylast + static_cast<size_t>(kapp(S)) * NPOL,
+                          H, bwd_y_width(Lw, H, H)};
         cnt = 3;
       }
     }
     if constexpr (!FILT && sizeof(R) == 4) {
       if (cnt > 2) load_bwd_tiles<R, NPOL, THREADS, kMaxBwdTiles>(t, cnt, n, t0, 2 * H >= n);
+      else load_bwd_tiles<R, NPOL, THREADS, 2>(t, cnt, n, t0, 2 * H >= n);
+    } else if constexpr (kYout) {
+      if (cnt > 2) load_bwd_tiles<R, NPOL, THREADS, 3>(t, cnt, n, t0, 2 * H >= n);
       else load_bwd_tiles<R, NPOL, THREADS, 2>(t, cnt, n, t0, 2 * H >= n);
     } else {
       load_bwd_tiles<R, NPOL, THREADS, 2>(t, cnt, n, t0, 2 * H >= n);
@@ -726,9 +737,10 @@ __global__ __launch_bounds__(THREADS) void ldbp_bwd_kernel(
     const int kp = kapp(s);
     V* ynext = ycur + static_cast<size_t>(bwd_y_width(Lw, H, hs, kprev) + pad) * NPOL;
     const R coef = c[pt.c0 + s - 1] * phase_coef_scale<R>();
-    if (!FILT && sizeof(R) == 4 && (s <= nstored || (yout && s == S))) {
+    if (sizeof(R) == 4 && ((!FILT && s <= nstored) || (kYout && yout && s == S))) {
       // loaded above
-      hs += K;
+      hs += K + kp;
+      kprev = kp;
       ycur = ynext;
       continue;
     }
@@ -1004,8 +1016,9 @@ int launch_bwd_block(int dtype, int npol, const void* xb, const void* gout, void
                      int32_t ecol_base, const void* ys, int64_t ys_stride, int32_t nstored, const void* yout) {
   if (nstored > 0 && (eta || dtype != LDBP_C64 || nstored > kMaxBwdTiles - 2 || nstored > pt.nstep))
     return fail(LDBP_EINVAL, "stored step outputs: %d for a block of %d steps", nstored, pt.nstep);
-  if (yout && (eta || dtype != LDBP_C64 || nstored > 0))
-    return fail(LDBP_EINVAL, "a stored block output needs unfiltered complex64 steps and no other stored outputs");
+  if (yout && (dtype != LDBP_C64 || nstored > 0 || (eta && npol != 1)))
+    return fail(LDBP_EINVAL, "a stored block output needs complex64 steps, one polarisation when filtered, and no "
+                "other stored outputs");
 #define LDBP_BWD_ARGS \
   xb, gout, gin, nwave, n, tile_len, pt, taps, c, part, ncols, ccol_base, sym, eta, ecol_base, ys, ys_stride, nstored, \
       yout, stream
