@@ -20,6 +20,20 @@ namespace ldbp {
 
 constexpr int kFwdThreads = 256;
 
+// One sample to global memory with a non-temporal hint: checkpoints are read back only by the backward,
+// long after the pass, so their writes need not stay in the caches.
+template <typename R, int NPOL>
+__device__ __forceinline__ void store_sample_nt(cx_t<R>* __restrict__ dst, const cx_t<R> (&v)[NPOL]) {
+  using vec2 = R __attribute__((ext_vector_type(2)));
+  using vec4 = R __attribute__((ext_vector_type(4)));
+  if constexpr (NPOL == 2 && sizeof(R) == 4) {
+    __builtin_nontemporal_store(vec4{v[0].x, v[0].y, v[1].x, v[1].y}, reinterpret_cast<vec4*>(dst));
+  } else {
+#pragma unroll
+    for (int p = 0; p < NPOL; ++p) __builtin_nontemporal_store(vec2{v[p].x, v[p].y}, reinterpret_cast<vec2*>(dst + p));
+  }
+}
+
 
 // FILT: the steps are filtered nonlinear steps (eta != NULL); CKPT: the pass writes inner checkpoints;
 // EDGE: the pass input and output follow an EdgeMap (aperiodic forward: zero margins, cropped output).
@@ -80,7 +94,7 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
       for (int j = threadIdx.x; j < Lw; j += THREADS) {
         V v[NPOL];
         load_sample<R, NPOL>(b0 + (H + j) * NPOL, v);
-        store_sample<R, NPOL>(cw + static_cast<int64_t>(t0 + j) * NPOL, v);
+        store_sample_nt<R, NPOL>(cw + static_cast<int64_t>(t0 + j) * NPOL, v);
       }
     }
   }
@@ -94,7 +108,9 @@ __global__ __launch_bounds__(THREADS) void ldbp_fwd_kernel(const cx_t<R>* __rest
     }
     V v[NPOL];
     load_sample<R, NPOL>(b0 + (H + j) * NPOL, v);
-    store_sample<R, NPOL>(yw + static_cast<int64_t>(o) * NPOL, v);
+    // a checkpointing pass writes the next block's checkpoint (or y after the last step)
+    if constexpr (CKPT) store_sample_nt<R, NPOL>(yw + static_cast<int64_t>(o) * NPOL, v);
+    else store_sample<R, NPOL>(yw + static_cast<int64_t>(o) * NPOL, v);
     if (nonfinite) {
 #pragma unroll
       for (int p = 0; p < NPOL; ++p) bad |= !(__builtin_isfinite(v[p].x) && __builtin_isfinite(v[p].y));
