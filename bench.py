@@ -848,7 +848,8 @@ def e1_reduced(torch, dev, iters: int, powers, out_dir: str, resume=None, stop_a
                               "note": "the paper's values (Sec. V-A, Fig. results_Ip2008), context only"}}
 
 
-def e8_reduced(torch, dev, iters: int, powers, rho_a: int = 4, data_pool: int = 0, eval_batches: int = 4):
+def e8_reduced(torch, dev, iters: int, powers, rho_a: int = 4, data_pool: int = 0, eval_batches: int = 4,
+               lr_schedule: str = "constant"):
     """The paper's 32 GBd scenario (Sec. V-F): 10 x 100 km, LDBP on the symmetric split-step with log
     step sizes, 2 steps per span (l = 21, 23 taps per filter: an overall impulse response of
     21 * 22 + 1 = 463 taps) trained at P = {3, 4, 5} dBm, and 4 steps per span (l = 41, 13 taps: 493)
@@ -856,7 +857,8 @@ def e8_reduced(torch, dev, iters: int, powers, rho_a: int = 4, data_pool: int = 
     coefficients (the last step stays linear).  Channel at rho_a samples per symbol (the paper: 6) with
     100 steps per span and amplifier noise; data_pool > 0: training cycles through that many simulated
     batches.  Effective SNR per power on eval_batches held-out batches of 32 x 8,192 symbols, with
-    FFT-DBP at the same number of steps per span (and 10) for reference, on the same waveforms."""
+    FFT-DBP at the same number of steps per span (and 10) for reference, on the same waveforms.
+    lr_schedule "cosine": Adam's step size decays from 1e-3 to 1e-4 by a half cosine over the run."""
     from paper_2010_14258_amd import train as TRN
 
     out = {}
@@ -864,7 +866,7 @@ def e8_reduced(torch, dev, iters: int, powers, rho_a: int = 4, data_pool: int = 
         cfg = TRN.TrainConfig(nwave=32, nsym=8192, rho_a=rho_a, rho_d=2, rs=32e9, nspan=10, span_km=100.0,
                               channel_steps=100, ldbp_steps=stps, t_init=ntaps, t_final=ntaps, iters=iters,
                               powers_dbm=ptrain, symbols="gauss", ssm="symmetric", seed=1301 + stps,
-                              data_pool=data_pool)
+                              data_pool=data_pool, lr_schedule=lr_schedule)
         trn = TRN.Trainer(cfg, device=dev)
         nb = eval_batches
         init = {p_: trn.evaluate(nbatch=nb, p_dbm=p_) for p_ in powers}
@@ -896,7 +898,7 @@ def e8_reduced(torch, dev, iters: int, powers, rho_a: int = 4, data_pool: int = 
         del trn
     return {"workload": "32 GBd, 10 x 100 km SSMF, Gaussian symbols, symmetric-SSM LDBP, 2 and 4 steps per span",
             "train_iterations": iters, "rho_a": rho_a, "data_pool": data_pool,
-            "symbols_per_snr": eval_batches * 32 * 8192, "models": out,
+            "symbols_per_snr": eval_batches * 32 * 8192, "lr_schedule": lr_schedule, "models": out,
             "paper_context": {"gain_over_dbp_db": {"2_stps": 2.1, "4_stps": 0.6}, "taps": 463,
                               "note": "the paper's values (Sec. V-F), after 150,000 + 1,500 iterations; context only"}}
 
@@ -1018,7 +1020,7 @@ def main():
     ap.add_argument("--eval-batches", type=int, default=4,
                     help="--mode e1: held-out batches of 32 x 8,192 symbols per launch power")
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"],
-                    help="--mode e1 and snr: Adam step size; cosine: decay to 1e-4 after the last pruning event")
+                    help="--mode e1, e8 and snr: Adam step size; cosine: decay to 1e-4 after the last pruning event")
     ap.add_argument("--stop-at", type=int, default=None, help="--mode e1: checkpoint at this iteration and stop")
     ap.add_argument("--out-dir", default=None,
                     help="--mode e1: directory of the trainer checkpoints and learning curve (default: the "
@@ -1099,7 +1101,7 @@ def main():
         return
     if args.mode == "e8":
         print(json.dumps(e8_reduced(torch, dev, args.train_iters, [float(v) for v in args.powers.split(",")],
-                                    args.rho_a, args.data_pool, args.eval_batches)), flush=True)
+                                    args.rho_a, args.data_pool, args.eval_batches, args.lr_schedule)), flush=True)
         return
     if args.mode == "init":
         print(json.dumps(init_schemes(torch, dev, args.train_iters, schemes=args.schemes.split(","),
